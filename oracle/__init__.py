@@ -1,0 +1,230 @@
+"""Plain FP64 CPU oracle for the two-site DMRG step with the entropy-EMA-PID
+bond-dimension controller (arXiv 2604.03960).
+
+TEST INFRASTRUCTURE ONLY: only tests/, the smoke check in __graft_entry__ and
+the CPU-baseline leg of bench.py may import this package.  The GPU library never
+loads it.  The arithmetic lives in oracle.c (plain C, no BLAS/LAPACK); this file
+only marshals arguments.  See oracle.c for the definitions and their citations.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", "-fno-fast-math"]
+
+LOG_FIELDS = 22
+LOG_NAMES = ["sweep", "dir", "bond", "m", "n", "k", "chi_ctrl", "E", "S", "S_ema", "eps", "wdisc", "gap",
+             "lanczos_iters", "svd_sweeps", "P", "I", "D", "u", "lanczos_ok", "sigma0", "sigma_kept_last"]
+
+MODEL_XXZ, MODEL_J1J2, MODEL_TFIM = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class PidParams(C.Structure):
+    _fields_ = [("kp", C.c_double), ("ki", C.c_double), ("kd", C.c_double), ("s_target", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("chi_min", C.c_int), ("chi_max", C.c_int),
+                ("ema_init_zero", C.c_int), ("pad", C.c_int)]
+
+
+class PidState(C.Structure):
+    _fields_ = [("s_ema", C.c_double), ("s_ema_prev", C.c_double), ("e_prev", C.c_double),
+                ("integ", C.c_double), ("chi", C.c_int), ("visits", C.c_int)]
+
+
+class DmrgOpts(C.Structure):
+    _fields_ = [("n_sweeps", C.c_int), ("lanczos_kmax", C.c_int), ("lanczos_restarts", C.c_int),
+                ("fixed_iters", C.c_int), ("lanczos_tol", C.c_double), ("fixed_chi", C.c_int), ("pad", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+        _lib.or_mpo_build.argtypes = [C.c_int, C.c_int, dp, dp]
+        _lib.or_mpo_dense.argtypes = [C.c_int, C.c_int, dp, dp]
+        _lib.or_ed_apply.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        _lib.or_ed_ground.argtypes = [C.c_int, C.c_int, dp, C.c_double, dp, dp, ip]
+        _lib.or_sym_eig_jacobi.argtypes = [C.c_int, dp, dp, dp]
+        _lib.or_svd_jacobi.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, ip]
+        _lib.or_spectrum.argtypes = [C.c_int, dp, C.c_int, dp]
+        _lib.or_spectrum.restype = None
+        _lib.or_pid_update.argtypes = [C.POINTER(PidParams), C.POINTER(PidState), C.c_double, ip, dp]
+        _lib.or_heff_apply.argtypes = [C.c_int] * 4 + [dp] * 6
+        _lib.or_env_left.argtypes = [C.c_int] * 4 + [dp] * 4
+        _lib.or_env_right.argtypes = [C.c_int] * 4 + [dp] * 4
+        _lib.or_lanczos_heff.argtypes = [C.c_int] * 4 + [dp] * 5 + [C.c_double, C.c_int, C.c_int, C.c_int, dp, ip]
+        _lib.or_dmrg_run.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, ip, C.POINTER(PidParams),
+                                     C.POINTER(DmrgOpts), dp, dp, ip, C.POINTER(PidState)]
+        _lib.or_right_canonical.argtypes = [C.c_int, C.c_int, dp, ip, dp, ip]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- models
+def mpo(model: int, N: int, params) -> np.ndarray:
+    """N bulk MPO tensors, shape (N, D, D, 2, 2); boundaries select row D-1 / column 0."""
+    D = {MODEL_XXZ: 5, MODEL_J1J2: 8, MODEL_TFIM: 3}[model]
+    p = _f64(list(params) + [0.0] * (3 - len(params)))
+    W = np.zeros((N, D, D, 2, 2))
+    rc = lib().or_mpo_build(model, N, _p(p), _p(W))
+    assert rc == D
+    return W
+
+
+def mpo_dense(W: np.ndarray) -> np.ndarray:
+    N, D = W.shape[0], W.shape[1]
+    H = np.zeros((2 ** N, 2 ** N))
+    assert lib().or_mpo_dense(N, D, _p(_f64(W)), _p(H)) == 0
+    return H
+
+
+def ed_apply(model: int, N: int, params, x: np.ndarray) -> np.ndarray:
+    p = _f64(list(params) + [0.0] * (3 - len(params)))
+    y = np.zeros(2 ** N)
+    assert lib().or_ed_apply(model, N, _p(p), _p(_f64(x)), _p(y)) == 0
+    return y
+
+
+def ed_ground(model: int, N: int, params, tol: float = 1e-13):
+    p = _f64(list(params) + [0.0] * (3 - len(params)))
+    E = np.zeros(1)
+    psi = np.zeros(2 ** N)
+    psi[:] = 1.0 + 0.37 * np.sin(1.7 * np.arange(2 ** N) + 0.3) + 1e-3 * (np.arange(2 ** N) % 7)
+    it = np.zeros(1, dtype=np.int32)
+    rc = lib().or_ed_ground(model, N, _p(p), tol, _p(E), _p(psi), _ip(it))
+    return float(E[0]), psi, int(it[0]), rc
+
+
+# ---------------------------------------------------------------- linear algebra
+def sym_eig(A: np.ndarray):
+    n = A.shape[0]
+    a = _f64(A).copy()
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    rc = lib().or_sym_eig_jacobi(n, _p(a), _p(w), _p(V))
+    return w, V, rc
+
+
+def svd(A: np.ndarray):
+    """One-sided Jacobi SVD: returns (S, U, V, sweeps, rc); A = U diag(S) V^T."""
+    A = _f64(A)
+    m, n = A.shape
+    R = min(m, n)
+    S, U, V = np.zeros(R), np.zeros((m, R)), np.zeros((n, R))
+    info = np.zeros(1, dtype=np.int32)
+    rc = lib().or_svd_jacobi(m, n, _p(A), _p(S), _p(U), _p(V), _ip(info))
+    return S, U, V, int(info[0]), rc
+
+
+def spectrum(S: np.ndarray, k: int):
+    """(Z, entropy, eps, discarded weight) of Eq. (4)-(5)."""
+    out = np.zeros(4)
+    S = _f64(S)
+    lib().or_spectrum(len(S), _p(S), int(k), _p(out))
+    return tuple(float(v) for v in out)
+
+
+def pid_params(kp, ki, kd, s_target, alpha, chi_min, chi_max, beta=0.0, ema_init_zero=False) -> PidParams:
+    return PidParams(kp, ki, kd, s_target, alpha, beta, chi_min, chi_max, int(ema_init_zero), 0)
+
+
+def pid_update(pp: PidParams, st: PidState, s_raw: float):
+    chi = C.c_int(0)
+    terms = np.zeros(6)
+    rc = lib().or_pid_update(C.byref(pp), C.byref(st), float(s_raw), C.byref(chi), _p(terms))
+    assert rc == 0
+    return chi.value, dict(P=terms[0], I=terms[1], D=terms[2], u=terms[3], sbar=terms[4], e=terms[5])
+
+
+def heff_apply(L, W1, W2, R, theta):
+    chl, D, _ = L.shape
+    chr_ = R.shape[0]
+    d = W1.shape[2]
+    out = np.zeros((chl, d, d, chr_))
+    lib().or_heff_apply(chl, chr_, d, D, _p(_f64(L)), _p(_f64(W1)), _p(_f64(W2)), _p(_f64(R)),
+                        _p(_f64(theta)), _p(out))
+    return out
+
+
+def env_left(L, W, A):
+    chl, d, chn = A.shape
+    D = W.shape[0]
+    out = np.zeros((chn, D, chn))
+    lib().or_env_left(chl, chn, d, D, _p(_f64(L)), _p(_f64(W)), _p(_f64(A)), _p(out))
+    return out
+
+
+def env_right(R, W, B):
+    chn, d, chr_ = B.shape
+    D = W.shape[0]
+    out = np.zeros((chn, D, chn))
+    lib().or_env_right(chn, chr_, d, D, _p(_f64(R)), _p(_f64(W)), _p(_f64(B)), _p(out))
+    return out
+
+
+def lanczos_heff(L, W1, W2, R, theta0, tol=1e-12, kmax=100, restarts=5, fixed_iters=0):
+    chl, D, _ = L.shape
+    chr_ = R.shape[0]
+    d = W1.shape[2]
+    th = _f64(theta0).copy()
+    E = np.zeros(1)
+    it = np.zeros(1, dtype=np.int32)
+    rc = lib().or_lanczos_heff(chl, chr_, d, D, _p(_f64(L)), _p(_f64(W1)), _p(_f64(W2)), _p(_f64(R)), _p(th),
+                               tol, kmax, restarts, fixed_iters, _p(E), _ip(it))
+    return float(E[0]), th.reshape(chl, d, d, chr_), int(it[0]), rc
+
+
+def right_canonical(N, d, A_packed, chi):
+    A_out = np.zeros_like(_f64(A_packed))
+    chi_out = np.zeros(N - 1, dtype=np.int32)
+    lib().or_right_canonical(N, d, _p(_f64(A_packed)), _ip(np.asarray(chi, dtype=np.int32)), _p(A_out),
+                             _ip(chi_out))
+    return A_out, chi_out
+
+
+def dmrg_run(W, A_packed, chi_init, pp: PidParams, n_sweeps, lanczos_tol=1e-12, kmax=100, restarts=5,
+             fixed_iters=0, fixed_chi=0):
+    """Runs the two-site DMRG; returns dict(log=[records], E=[per sweep], chi=[final], pid=[states], rc)."""
+    W = _f64(W)
+    N, D, _, d, _ = W.shape
+    opts = DmrgOpts(n_sweeps, kmax, restarts, fixed_iters, lanczos_tol, fixed_chi, 0)
+    nrec = n_sweeps * 2 * (N - 1)
+    log = np.zeros((nrec, LOG_FIELDS))
+    E = np.zeros(n_sweeps)
+    chi = np.zeros(N - 1, dtype=np.int32)
+    pid = (PidState * (N - 1))()
+    rc = lib().or_dmrg_run(N, d, D, _p(W), _p(_f64(A_packed)), _ip(np.asarray(chi_init, dtype=np.int32)),
+                           C.byref(pp), C.byref(opts), _p(log), _p(E), _ip(chi), pid)
+    recs = [dict(zip(LOG_NAMES, row)) for row in log]
+    return dict(log=recs, log_array=log, E=E, chi=chi, pid=pid, rc=rc)
