@@ -1,0 +1,174 @@
+/*
+ * tna.h -- C ABI of the MI355X (gfx950) two-site DMRG hot path with an
+ * entropy-EMA-PID bond-dimension controller (arXiv 2604.03960).
+ *
+ * Conventions shared by every entry point
+ *  - All arrays are row-major.  Tensors named "device" live in device memory
+ *    owned by the caller (e.g. PyTorch tensors passed as data pointers); the
+ *    library never frees them.  "host" arrays are ordinary CPU memory.
+ *  - site tensor  A_i[a][s][b]        (chi_{i-1}, d, chi_i)
+ *    MPO tensor   W_i[wl][wr][s][s']  (D, D, d, d), s = output/bra, s' = input/ket
+ *    left env     L[a][w][a']         (chi_l, D, chi_l)   bra, MPO, ket
+ *    right env    R[b][w][b']         (chi_r, D, chi_r)   bra, MPO, ket
+ *    two-site     theta[a][s][t][b]   (chi_l, d, d, chi_r) = matrix (chi_l d) x (d chi_r)
+ *    The left boundary selects MPO row D-1 and the right boundary column 0.
+ *  - Work is enqueued on the context's stream and is asynchronous unless the
+ *    comment says the call synchronises.  Every call returns a tna_status;
+ *    nothing throws across the ABI.  On TNA_ERR_ARG nothing has been launched.
+ *    tna_last_error() returns a thread-local message for the last failure.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef TNA_H
+#define TNA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TNA_OK = 0,
+  TNA_ERR_ARG = 1,         /* bad dimension, pointer or parameter */
+  TNA_ERR_NOMEM = 2,       /* device or pinned-host allocation failed */
+  TNA_ERR_DEVICE = 3,      /* a HIP runtime call failed */
+  TNA_ERR_NOCONV = 4,      /* iteration cap reached; the best result so far is written */
+  TNA_ERR_NONFINITE = 5,   /* NaN or Inf met in the input or in an intermediate */
+  TNA_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+} tna_status;
+
+typedef enum { TNA_F64 = 0, TNA_F32 = 1 } tna_dtype;
+
+/* Arithmetic of the effective-Hamiltonian matvec.  theta and the result are
+ * always FP64; F32 converts the operands to FP32, accumulates in FP32 on the
+ * matrix cores and stores FP64.  BF16X3 splits each FP32 operand x into
+ * hi = bf16(x), lo = bf16(x - hi) and forms hi*hi + hi*lo + lo*hi in FP32. */
+typedef enum { TNA_HEFF_F64 = 0, TNA_HEFF_F32 = 1, TNA_HEFF_BF16X3 = 2 } tna_prec;
+
+typedef struct tna_ctx_s *tna_ctx;
+
+/* ---------------------------------------------------------------- context */
+/* Creates a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+tna_status tna_create(tna_ctx *out, int device, void *hip_stream);
+void tna_destroy(tna_ctx ctx);
+tna_status tna_set_stream(tna_ctx ctx, void *hip_stream);
+/* Waits for all work the context enqueued.  Synchronises. */
+tna_status tna_synchronize(tna_ctx ctx);
+const char *tna_last_error(void);
+/* Milliseconds spent in the kernel families of the last calls (see
+ * tna_timing_* below); accumulated with HIP events when timing is enabled. */
+tna_status tna_set_timing(tna_ctx ctx, int enable);
+
+/* ---------------------------------------------------------------- models */
+/* Bulk MPO tensors of an open chain (host).  model 0: XXZ,
+ * H = J sum[(S+S- + S-S+)/2 + Delta Sz Sz] - hz sum Sz, params {J, Delta, hz}
+ * (Eq. 20 is J=1, Delta=1, hz=0), D = 5.  model 1: J1-J2 Heisenberg, params
+ * {J1, J2}, D = 8.  model 2: transverse-field Ising in Pauli units,
+ * H = -J sum sz sz - h sum sx, params {J, h}, D = 3.  W receives N copies of
+ * the D x D x 2 x 2 tensor; *D_out the bond dimension.  Host only. */
+tna_status tna_mpo_build(int model, int N, const double *params, double *W, int *D_out);
+
+/* ---------------------------------------------------------------- H_eff */
+/* Two-site effective Hamiltonian of Eq. (18) applied to theta:
+ *   out[a][s][t][b] = sum L[a][w][a'] W1[w][w'][s][s'] W2[w'][w''][t][t']
+ *                         R[b][w''][b'] theta[a'][s'][t'][b']
+ * L (chi_l,D,chi_l), W1 and W2 (D,D,d,d), R (chi_r,D,chi_r), theta and out
+ * (chi_l,d,d,chi_r): all device, FP64, caller-owned; out must not alias
+ * theta.  prec is a tna_prec.  Scratch comes from the context. */
+tna_status tna_heff_apply(tna_ctx ctx, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
+                          const double *W2, const double *R, const double *theta, double *out, int prec);
+
+/* ---------------------------------------------------------------- SVD */
+/* Truncated SVD of Eq. (3)/(19), A = U diag(S) Vt, by blocked one-sided
+ * Jacobi, plus the spectrum sums of Eq. (4)-(5).
+ *  A       device, m x n, dtype (TNA_F64: double, TNA_F32: float; F32 runs
+ *          the Gram and rotation products in FP32, the rotations in FP64)
+ *  chi_keep  k = min(chi_keep, m, n) vectors are returned (chi_keep >= 1)
+ *  S       device double[min(m,n)]: full spectrum, descending
+ *  U       device, m x k (same dtype as A);  Vt device, k x n
+ *  spec    device double[6]: {Z = sum S^2, entropy -sum p ln p (p = S^2/Z),
+ *          eps = sqrt(sum_{j>=k} S_j^2), eps^2/Z, |S_0..k-1|, gap
+ *          (S_{k-1}-S_k)/S_0 (1 if k = min(m,n))}
+ *  k_out, sweeps_out  host, may be NULL; filling them synchronises.
+ * Gauge: the largest-magnitude entry of each column of U is positive (ties:
+ * lowest row).  Returns TNA_ERR_NOCONV if the Jacobi sweeps hit the cap. */
+tna_status tna_svd_truncate(tna_ctx ctx, int m, int n, int dtype, const void *A, int chi_keep, double *S, void *U,
+                            void *Vt, double *spec, int *k_out, int *sweeps_out);
+
+/* The same for `batch` independent m x n matrices at element strides
+ * strideA (A), strideS (S), strideU (U), strideVt (Vt); spec is batch x 6.
+ * The batch runs through the same launches (one grid dimension per member). */
+tna_status tna_svd_truncate_batched(tna_ctx ctx, int batch, int m, int n, int dtype, const void *A, int64_t strideA,
+                                    int chi_keep, double *S, int64_t strideS, void *U, int64_t strideU, void *Vt,
+                                    int64_t strideVt, double *spec, int *sweeps_out);
+
+/* ---------------------------------------------------------------- controller */
+/* EMA (Eq. 8), optional linear predictor (Eq. 16, beta > 0) and PID with
+ * anti-windup (Eq. 9-11, Algorithm 2), one call per bond visit.
+ * First visit: the EMA starts at S (or at 0 with ema_init_zero) and the
+ * previous error equals the current one.  Rounding is to nearest, ties to
+ * even.  The stored controller chi (not the realised rank) enters the
+ * update.  Host only, pure: the result depends only on (params, state, s_raw).
+ * terms (may be NULL) receives {P, I, D, u, Sbar, e}. */
+typedef struct {
+  double kp, ki, kd, s_target, alpha, beta;
+  int chi_min, chi_max, ema_init_zero, pad;
+} tna_pid_params;
+
+typedef struct {
+  double s_ema, s_ema_prev, e_prev, integ;
+  int chi, visits;
+} tna_pid_state;
+
+tna_status tna_pid_chi_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next,
+                              double *terms);
+
+/* ---------------------------------------------------------------- DMRG */
+typedef struct {
+  double lanczos_tol;     /* residual |beta_j y_j| <= tol*max(1,|E|); default 1e-12 */
+  int lanczos_kmax;       /* Krylov vectors before a restart; default 100 */
+  int lanczos_restarts;   /* default 5 */
+  int lanczos_fixed_iters;/* >0: exactly this many matvecs per visit (throughput mode) */
+  int heff_prec;          /* tna_prec */
+  int fixed_chi;          /* >0: keep min(fixed_chi, m, n) regardless of the controller */
+  int svd_max_sweeps;     /* default 60 */
+  double eps_target;      /* truncation-error target that is reported (and used by schedulers) */
+} tna_dmrg_opts;
+
+/* One record per bond visit (host). */
+typedef struct {
+  int sweep, dir, bond, m, n, k, chi_ctrl, lanczos_iters, svd_sweeps, lanczos_ok;
+  double E, S, S_ema, eps, wdisc, gap, P, I, D, u, sigma0, sigma_last;
+  double ms_lanczos, ms_svd, ms_other;
+} tna_visit_log;
+
+typedef struct tna_dmrg_s *tna_dmrg;
+
+/* Device-resident two-site DMRG (Sec. 10) with one controller per bond.
+ * W_host: N MPO tensors (N, D, D, d, d).  A_host: the initial MPS packed site
+ * after site (site tensor shapes from chi_init: chi_init[b] = dim of bond b,
+ * N-1 values; boundary dims 1).  The library right-canonicalises it on the
+ * device.  The controller starts every bond at chi_min.  Allocates device
+ * memory owned by the returned object.  Synchronises. */
+tna_status tna_dmrg_create(tna_ctx ctx, int N, int d, int D, const double *W_host, const double *A_host,
+                           const int *chi_init, const tna_pid_params *pid, const tna_dmrg_opts *opts, tna_dmrg *out);
+/* One full sweep: bonds 0..N-2 left to right, then N-2..0 right to left.
+ * Per visit: theta = A_b A_{b+1}; Lanczos (FP64) on H_eff; SVD of theta;
+ * entropy of the full spectrum; controller -> chi; keep k = min(chi, m, n);
+ * renormalise the kept values; move the orthogonality centre; grow the
+ * environment.  E_out (host) receives the last Ritz value; log (host, may be
+ * NULL) receives 2*(N-1) records.  Synchronises. */
+tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log);
+/* Current realised bond dims (N-1) and controller states (N-1), host. */
+tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid);
+/* Copies the MPS packed site after site into A_host (capacity given in
+ * doubles); *count receives the number of doubles.  Synchronises. */
+tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t *count);
+void tna_dmrg_destroy(tna_dmrg dm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNA_H */

@@ -1,0 +1,265 @@
+"""Python binding of libtna: the MI355X (gfx950) two-site DMRG hot path with an
+entropy-EMA-PID bond-dimension controller (arXiv 2604.03960).
+
+Argument marshalling only: every numerical step runs in the HIP kernels behind
+the C ABI declared in include/tna.h.  PyTorch provides device memory and
+streams.  Importing this module fails loudly when libtna.so has not been
+built (python -m paper_2604_03960_amd.build); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtna.so")
+
+TNA_OK, TNA_ERR_ARG, TNA_ERR_NOMEM, TNA_ERR_DEVICE, TNA_ERR_NOCONV, TNA_ERR_NONFINITE, TNA_ERR_UNSUPPORTED = range(7)
+F64, F32 = 0, 1
+HEFF_F64, HEFF_F32, HEFF_BF16X3 = 0, 1, 2
+MODEL_XXZ, MODEL_J1J2, MODEL_TFIM = 0, 1, 2
+
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_DEVICE", 4: "ERR_NOCONV", 5: "ERR_NONFINITE",
+                6: "ERR_UNSUPPORTED"}
+
+
+class TnaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tna status {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_03960_amd.build` "
+                      "(the GPU path has no fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+
+
+class PidParams(C.Structure):
+    _fields_ = [("kp", C.c_double), ("ki", C.c_double), ("kd", C.c_double), ("s_target", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("chi_min", C.c_int), ("chi_max", C.c_int),
+                ("ema_init_zero", C.c_int), ("pad", C.c_int)]
+
+
+class PidState(C.Structure):
+    _fields_ = [("s_ema", C.c_double), ("s_ema_prev", C.c_double), ("e_prev", C.c_double),
+                ("integ", C.c_double), ("chi", C.c_int), ("visits", C.c_int)]
+
+
+class DmrgOpts(C.Structure):
+    _fields_ = [("lanczos_tol", C.c_double), ("lanczos_kmax", C.c_int), ("lanczos_restarts", C.c_int),
+                ("lanczos_fixed_iters", C.c_int), ("heff_prec", C.c_int), ("fixed_chi", C.c_int),
+                ("svd_max_sweeps", C.c_int), ("eps_target", C.c_double)]
+
+
+class VisitLog(C.Structure):
+    _fields_ = [(n, C.c_int) for n in ("sweep", "dir", "bond", "m", "n", "k", "chi_ctrl", "lanczos_iters",
+                                       "svd_sweeps", "lanczos_ok")] + \
+               [(n, C.c_double) for n in ("E", "S", "S_ema", "eps", "wdisc", "gap", "P", "I", "D", "u", "sigma0",
+                                          "sigma_last", "ms_lanczos", "ms_svd", "ms_other")]
+
+
+_vp, _dp, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+_SIGS = {
+    "tna_create": ([C.POINTER(C.c_void_p), C.c_int, _vp], C.c_int),
+    "tna_destroy": ([_vp], None),
+    "tna_set_stream": ([_vp, _vp], C.c_int),
+    "tna_synchronize": ([_vp], C.c_int),
+    "tna_last_error": ([], C.c_char_p),
+    "tna_set_timing": ([_vp, C.c_int], C.c_int),
+    "tna_mpo_build": ([C.c_int, C.c_int, _dp, _dp, _ip], C.c_int),
+    "tna_heff_apply": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int], C.c_int),
+    "tna_svd_truncate": ([_vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp, _vp, _vp, _vp, _ip, _ip], C.c_int),
+    "tna_svd_truncate_batched": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int, _vp, C.c_int64,
+                                  _vp, C.c_int64, _vp, C.c_int64, _vp, _ip], C.c_int),
+    "tna_pid_chi_update": ([C.POINTER(PidParams), C.POINTER(PidState), C.c_double, _ip, _dp], C.c_int),
+    "tna_dmrg_create": ([_vp, C.c_int, C.c_int, C.c_int, _dp, _dp, _ip, C.POINTER(PidParams), C.POINTER(DmrgOpts),
+                         C.POINTER(C.c_void_p)], C.c_int),
+    "tna_dmrg_sweep": ([_vp, _dp, C.POINTER(VisitLog)], C.c_int),
+    "tna_dmrg_get_state": ([_vp, _ip, C.POINTER(PidState)], C.c_int),
+    "tna_dmrg_get_mps": ([_vp, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+    "tna_dmrg_destroy": ([_vp], None),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+def last_error() -> str:
+    return _lib.tna_last_error().decode()
+
+
+def _check(status, allow=()):
+    if status != TNA_OK and status not in allow:
+        raise TnaError(status, last_error())
+    return status
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ host-only helpers
+def mpo_build(model: int, N: int, params) -> np.ndarray:
+    """Bulk MPO tensors (N, D, D, 2, 2) from the library's host builder."""
+    p = np.zeros(3)
+    p[:len(params)] = params
+    D = {MODEL_XXZ: 5, MODEL_J1J2: 8, MODEL_TFIM: 3}[model]
+    W = np.zeros((N, D, D, 2, 2))
+    d_out = C.c_int(0)
+    _check(_lib.tna_mpo_build(model, N, p.ctypes.data_as(_dp), W.ctypes.data_as(_dp), C.byref(d_out)))
+    assert d_out.value == D
+    return W
+
+
+def pid_params(kp, ki, kd, s_target, alpha, chi_min, chi_max, beta=0.0, ema_init_zero=False) -> PidParams:
+    return PidParams(kp, ki, kd, s_target, alpha, beta, chi_min, chi_max, int(ema_init_zero), 0)
+
+
+def pid_chi_update(pp: PidParams, st: PidState, s_raw: float):
+    chi = C.c_int(0)
+    terms = np.zeros(6)
+    _check(_lib.tna_pid_chi_update(C.byref(pp), C.byref(st), float(s_raw), C.byref(chi), terms.ctypes.data_as(_dp)))
+    return chi.value, dict(P=terms[0], I=terms[1], D=terms[2], u=terms[3], sbar=terms[4], e=terms[5])
+
+
+# ------------------------------------------------------------------ device context
+class Context:
+    """One library context on a HIP device, enqueueing on a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        _check(_lib.tna_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tna_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        _check(_lib.tna_synchronize(self.h))
+
+    def set_stream(self, stream):
+        _check(_lib.tna_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    # -------------------------------------------------------------- H_eff
+    def heff_apply(self, L, W1, W2, R, theta, prec=HEFF_F64, out=None):
+        torch = self.torch
+        chl, D, _ = L.shape
+        chr_ = R.shape[0]
+        d = W1.shape[2]
+        for t in (L, W1, W2, R, theta):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        assert theta.shape == (chl, d, d, chr_)
+        if out is None:
+            out = torch.empty_like(theta)
+        _check(_lib.tna_heff_apply(self.h, chl, chr_, d, D, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(theta),
+                                   _ptr(out), prec))
+        return out
+
+    # -------------------------------------------------------------- SVD
+    def svd_truncate(self, A, chi_keep: int):
+        """Returns (S, U, Vt, spec, k, sweeps, status); spec = [Z, S_vN, eps, eps^2/Z, |S_k|, gap]."""
+        torch = self.torch
+        assert A.is_cuda and A.is_contiguous() and A.dim() == 2
+        m, n = A.shape
+        dt = F64 if A.dtype == torch.float64 else F32
+        k = min(chi_keep, m, n)
+        S = torch.empty(min(m, n), dtype=torch.float64, device=A.device)
+        U = torch.empty((m, k), dtype=A.dtype, device=A.device)
+        Vt = torch.empty((k, n), dtype=A.dtype, device=A.device)
+        spec = torch.empty(6, dtype=torch.float64, device=A.device)
+        k_out, sw = C.c_int(0), C.c_int(0)
+        st = _check(_lib.tna_svd_truncate(self.h, m, n, dt, _ptr(A), chi_keep, _ptr(S), _ptr(U), _ptr(Vt),
+                                          _ptr(spec), C.byref(k_out), C.byref(sw)), allow=(TNA_ERR_NOCONV,))
+        return S, U, Vt, spec, k_out.value, sw.value, st
+
+    def svd_truncate_batched(self, A, chi_keep: int):
+        torch = self.torch
+        assert A.is_cuda and A.is_contiguous() and A.dim() == 3
+        B, m, n = A.shape
+        dt = F64 if A.dtype == torch.float64 else F32
+        k = min(chi_keep, m, n)
+        R = min(m, n)
+        S = torch.empty((B, R), dtype=torch.float64, device=A.device)
+        U = torch.empty((B, m, k), dtype=A.dtype, device=A.device)
+        Vt = torch.empty((B, k, n), dtype=A.dtype, device=A.device)
+        spec = torch.empty((B, 6), dtype=torch.float64, device=A.device)
+        sw = C.c_int(0)
+        st = _check(_lib.tna_svd_truncate_batched(self.h, B, m, n, dt, _ptr(A), m * n, chi_keep, _ptr(S), R, _ptr(U),
+                                                  m * k, _ptr(Vt), k * n, _ptr(spec), C.byref(sw)),
+                    allow=(TNA_ERR_NOCONV,))
+        return S, U, Vt, spec, sw.value, st
+
+
+# ------------------------------------------------------------------ DMRG
+class Dmrg:
+    """Device-resident two-site DMRG with per-bond EMA+PID bond dimensions."""
+
+    def __init__(self, ctx: Context, W: np.ndarray, A_packed: np.ndarray, chi_init, pid: PidParams,
+                 lanczos_tol=1e-12, lanczos_kmax=100, lanczos_restarts=5, fixed_iters=0, heff_prec=HEFF_F64,
+                 fixed_chi=0, svd_max_sweeps=60, eps_target=1e-8):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        N, D, _, d, _ = W.shape
+        self.N, self.d, self.D = N, d, D
+        self.ctx = ctx
+        A = np.ascontiguousarray(A_packed, dtype=np.float64)
+        chi = np.ascontiguousarray(chi_init, dtype=np.int32)
+        self.opts = DmrgOpts(lanczos_tol, lanczos_kmax, lanczos_restarts, fixed_iters, heff_prec, fixed_chi,
+                             svd_max_sweeps, eps_target)
+        self.pid = pid
+        h = C.c_void_p()
+        _check(_lib.tna_dmrg_create(ctx.h, N, d, D, W.ctypes.data_as(_dp), A.ctypes.data_as(_dp),
+                                    chi.ctypes.data_as(_ip), C.byref(pid), C.byref(self.opts), C.byref(h)))
+        self.h = h
+
+    def sweep(self):
+        """One full sweep; returns (E, list of per-visit dicts, status)."""
+        n = 2 * (self.N - 1)
+        logs = (VisitLog * n)()
+        E = C.c_double(0.0)
+        st = _check(_lib.tna_dmrg_sweep(self.h, C.byref(E), logs), allow=(TNA_ERR_NOCONV,))
+        recs = [{f: getattr(r, f) for f, _ in VisitLog._fields_} for r in logs]
+        return E.value, recs, st
+
+    def state(self):
+        chi = np.zeros(self.N - 1, dtype=np.int32)
+        pid = (PidState * (self.N - 1))()
+        _check(_lib.tna_dmrg_get_state(self.h, chi.ctypes.data_as(_ip), pid))
+        return chi, list(pid)
+
+    def mps(self):
+        cnt = C.c_size_t(0)
+        _check(_lib.tna_dmrg_get_mps(self.h, None, 0, C.byref(cnt)))
+        out = np.zeros(cnt.value)
+        _check(_lib.tna_dmrg_get_mps(self.h, out.ctypes.data_as(_dp), cnt.value, C.byref(cnt)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tna_dmrg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

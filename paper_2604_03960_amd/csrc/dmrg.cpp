@@ -1,0 +1,337 @@
+// Device-resident two-site DMRG (Sec. 10 of the paper) with one EMA+PID bond
+// controller per bond (Algorithm 2, Sec. 6).  The MPS tensors, environments,
+// Lanczos basis and SVD work buffers live in device memory for the whole run;
+// per bond visit the host reads back only the Lanczos coefficients and the
+// entropy of the two-site spectrum.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+
+using namespace tna;
+
+struct tna_dmrg_s {
+  tna_ctx ctx;
+  int N, d, D;
+  tna_pid_params pid;
+  tna_dmrg_opts opts;
+  std::vector<int> chi;            // N-1 realised bond dims
+  std::vector<tna_pid_state> st;   // N-1 controllers
+  std::vector<DevBuf> A, Le, Re;   // site tensors, left envs (site i), right envs (site i)
+  DevBuf W, M12, Ml, Mr;           // MPO tensors and mixing matrices (device)
+  DevBuf V, T1, T2, spec, S;       // Lanczos basis, env scratch, spectrum
+  int sweeps_done = 0;
+  double *host_stage = nullptr;    // pinned: per-visit readbacks
+  int CL(int i) const { return i == 0 ? 1 : chi[i - 1]; }
+  int CR(int i) const { return i == N - 1 ? 1 : chi[i]; }
+};
+
+static tna_status check_dmrg_args(int N, int d, int D, const double *W, const double *A, const int *chi,
+                                  const tna_pid_params *pid) {
+  if (N < 2 || d < 1 || D < 1 || !W || !A || !chi || !pid) {
+    set_error("dmrg_create: bad arguments");
+    return TNA_ERR_ARG;
+  }
+  if (D * d * d > 32) {
+    set_error("dmrg_create: D*d*d must be <= 32");
+    return TNA_ERR_ARG;
+  }
+  if (pid->chi_min < 1 || pid->chi_max < pid->chi_min) {
+    set_error("dmrg_create: need 1 <= chi_min <= chi_max");
+    return TNA_ERR_ARG;
+  }
+  for (int b = 0; b < N - 1; ++b) {
+    const int cl = b == 0 ? 1 : chi[b - 1];
+    if (chi[b] < 1 || cl > d * chi[b] || chi[b] > d * cl) {
+      set_error("dmrg_create: inconsistent initial bond dimensions");
+      return TNA_ERR_ARG;
+    }
+  }
+  return TNA_OK;
+}
+
+static tna_status svd_into(tna_dmrg dm, int m, int n, const double *src, int k_req, void *U, void *Vt,
+                           int scale_mode, int *k_out, double *entropy_host, int *sweeps, bool need_entropy) {
+  (void)entropy_host;
+  (void)need_entropy;
+  tna_ctx c = dm->ctx;
+  SvdPlan p;
+  TNA_TRY(svd_plan(1, m, n, TNA_F64, &p));
+  TNA_TRY(dm->S.ensure(sizeof(double) * p.R));
+  int sw = 0;
+  tna_status st = svd_run(p, c->svd, src, (int64_t)m * n, dm->opts.svd_max_sweeps, &sw, c->stream, c->host_ctr);
+  if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
+  TNA_TRY(svd_spectrum(p, c->svd, dm->S.as<double>(), p.R, dm->spec.as<double>(), c->stream));
+  const int k = std::min(k_req, p.R);
+  TNA_TRY(svd_trunc_S(p, dm->S.as<double>(), p.R, k, dm->spec.as<double>(), c->stream));
+  TNA_TRY(svd_outputs_S(p, c->svd, dm->S.as<double>(), p.R, k, U, (int64_t)m * k, Vt, (int64_t)k * n, TNA_F64,
+                        scale_mode, dm->spec.as<double>(), c->stream));
+  if (k_out) *k_out = k;
+  if (sweeps) *sweeps = sw;
+  return st == TNA_ERR_NOCONV ? TNA_ERR_NOCONV : TNA_OK;
+}
+
+extern "C" {
+
+tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host, const double *A_host,
+                           const int *chi_init, const tna_pid_params *pid, const tna_dmrg_opts *opts, tna_dmrg *out) {
+  if (!c || !out) {
+    set_error("dmrg_create: null context/out");
+    return TNA_ERR_ARG;
+  }
+  TNA_TRY(check_dmrg_args(N, d, D, W_host, A_host, chi_init, pid));
+  auto dm = std::make_unique<tna_dmrg_s>();
+  dm->ctx = c;
+  dm->N = N; dm->d = d; dm->D = D;
+  dm->pid = *pid;
+  tna_dmrg_opts o{};
+  if (opts) o = *opts;
+  if (!(o.lanczos_tol > 0)) o.lanczos_tol = 1e-12;
+  if (o.lanczos_kmax <= 0) o.lanczos_kmax = 100;
+  if (o.lanczos_restarts < 0) o.lanczos_restarts = 5;
+  if (o.svd_max_sweeps <= 0) o.svd_max_sweeps = 60;
+  if (o.heff_prec < 0 || o.heff_prec > 1) {
+    set_error("dmrg_create: heff_prec must be F64 or F32");
+    return TNA_ERR_ARG;
+  }
+  dm->opts = o;
+  dm->chi.assign(chi_init, chi_init + N - 1);
+  dm->st.assign(N - 1, tna_pid_state{0, 0, 0, 0, pid->chi_min, 0});
+  dm->A.resize(N);
+  dm->Le.resize(N);
+  dm->Re.resize(N);
+  hipStream_t s = c->stream;
+  TNA_HIP(hipHostMalloc((void **)&dm->host_stage, sizeof(double) * 64, hipHostMallocDefault));
+  // MPO and mixing matrices
+  const size_t wsz = (size_t)D * D * d * d;
+  TNA_TRY(dm->W.ensure(sizeof(double) * wsz * N));
+  TNA_HIP(hipMemcpy(dm->W.ptr, W_host, sizeof(double) * wsz * N, hipMemcpyHostToDevice));
+  const int I2 = D * d * d, I1 = D * d;
+  TNA_TRY(dm->M12.ensure(sizeof(double) * I2 * I2 * (N - 1)));
+  TNA_TRY(dm->Ml.ensure(sizeof(double) * I1 * I1 * N));
+  TNA_TRY(dm->Mr.ensure(sizeof(double) * I1 * I1 * N));
+  const double *Wd = dm->W.as<double>();
+  for (int b = 0; b < N - 1; ++b)
+    TNA_TRY(build_mix_matrix(0, d, D, Wd + wsz * b, Wd + wsz * (b + 1), dm->M12.as<double>() + (size_t)I2 * I2 * b, s));
+  for (int i = 0; i < N; ++i) {
+    TNA_TRY(build_mix_matrix(1, d, D, Wd + wsz * i, nullptr, dm->Ml.as<double>() + (size_t)I1 * I1 * i, s));
+    TNA_TRY(build_mix_matrix(2, d, D, Wd + wsz * i, nullptr, dm->Mr.as<double>() + (size_t)I1 * I1 * i, s));
+  }
+  // site tensors
+  size_t off = 0;
+  for (int i = 0; i < N; ++i) {
+    const size_t n = (size_t)dm->CL(i) * d * dm->CR(i);
+    TNA_TRY(dm->A[i].ensure(sizeof(double) * n));
+    TNA_HIP(hipMemcpy(dm->A[i].ptr, A_host + off, sizeof(double) * n, hipMemcpyHostToDevice));
+    off += n;
+  }
+  TNA_TRY(dm->spec.ensure(sizeof(double) * 8));
+  // right-canonicalise on the device: A_b = U S Vt -> A_b <- Vt, A_{b-1} <- A_{b-1} U S
+  DevBuf Ub, Vb, Tb;
+  for (int b = N - 1; b >= 1; --b) {
+    const int m = dm->chi[b - 1], n = d * dm->CR(b);
+    const int R = std::min(m, n);
+    TNA_TRY(Ub.ensure(sizeof(double) * m * R));
+    TNA_TRY(Vb.ensure(sizeof(double) * R * n));
+    int k = 0, sw = 0;
+    tna_status st = svd_into(dm.get(), m, n, dm->A[b].as<double>(), R, Ub.ptr, Vb.ptr, 2, &k, nullptr, &sw, false);
+    if (st != TNA_OK) return st;
+    const int ml = dm->CL(b - 1) * d;
+    TNA_TRY(Tb.ensure(sizeof(double) * ml * k));
+    GemmArgs g{};
+    g.M = ml; g.N = k; g.K = m;
+    g.A = dm->A[b - 1].ptr; g.lda = m; g.B = Ub.ptr; g.ldb = k; g.C = Tb.ptr; g.ldc = k;
+    g.alpha = 1.0; g.batch = 1; g.compute = G_F64;
+    TNA_TRY(gemm(g, s));
+    TNA_TRY(dm->A[b - 1].ensure(sizeof(double) * ml * k));
+    TNA_HIP(hipMemcpyAsync(dm->A[b - 1].ptr, Tb.ptr, sizeof(double) * ml * k, hipMemcpyDeviceToDevice, s));
+    TNA_TRY(dm->A[b].ensure(sizeof(double) * k * n));
+    TNA_HIP(hipMemcpyAsync(dm->A[b].ptr, Vb.ptr, sizeof(double) * k * n, hipMemcpyDeviceToDevice, s));
+    dm->chi[b - 1] = k;
+  }
+  {
+    const int64_t n0 = (int64_t)d * dm->CR(0);
+    double *nr = c->misc.as<double>() + 512;
+    TNA_TRY(norm2(dm->A[0].as<double>(), n0, nr, c->part.as<double>(), s));
+    TNA_TRY(scale(dm->A[0].as<double>(), dm->A[0].as<double>(), n0, nr, 0.0, s));
+  }
+  Ub.release(); Vb.release(); Tb.release();
+  // boundary environments and the right environments of the canonical MPS
+  std::vector<double> bnd(D, 0.0);
+  bnd[D - 1] = 1.0;
+  TNA_TRY(dm->Le[0].ensure(sizeof(double) * D));
+  TNA_HIP(hipMemcpy(dm->Le[0].ptr, bnd.data(), sizeof(double) * D, hipMemcpyHostToDevice));
+  std::fill(bnd.begin(), bnd.end(), 0.0);
+  bnd[0] = 1.0;
+  TNA_TRY(dm->Re[N - 1].ensure(sizeof(double) * D));
+  TNA_HIP(hipMemcpy(dm->Re[N - 1].ptr, bnd.data(), sizeof(double) * D, hipMemcpyHostToDevice));
+  for (int i = N - 1; i >= 2; --i) {
+    const int k = dm->CL(i), cr = dm->CR(i);
+    TNA_TRY(dm->T1.ensure(sizeof(double) * (size_t)cr * D * k * d));
+    TNA_TRY(dm->T2.ensure(sizeof(double) * (size_t)cr * D * k * d));
+    TNA_TRY(dm->Re[i - 1].ensure(sizeof(double) * (size_t)k * D * k));
+    TNA_TRY(env_right(k, cr, d, D, dm->Re[i].as<double>(), dm->Mr.as<double>() + (size_t)I1 * I1 * i,
+                           dm->A[i].as<double>(), dm->T1.as<double>(), dm->T2.as<double>(), dm->Re[i - 1].as<double>(),
+                           s));
+  }
+  TNA_HIP(hipStreamSynchronize(s));
+  *out = dm.release();
+  return TNA_OK;
+}
+
+tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
+  if (!dm) {
+    set_error("dmrg_sweep: null handle");
+    return TNA_ERR_ARG;
+  }
+  tna_ctx c = dm->ctx;
+  hipStream_t s = c->stream;
+  const int N = dm->N, d = dm->d, D = dm->D;
+  const int I1 = D * d, I2 = D * d * d;
+  tna_status worst = TNA_OK;
+  double E = 0.0;
+  int rec = 0;
+  for (int half = 0; half < 2; ++half) {
+    for (int step = 0; step < N - 1; ++step) {
+      const int b = half == 0 ? step : N - 2 - step;
+      const int chl = dm->CL(b), chm = dm->chi[b], chr = dm->CR(b + 1);
+      const int m = chl * d, n = d * chr;
+      const int64_t nv = (int64_t)m * n;
+      const int kmax = std::min<int64_t>(dm->opts.lanczos_fixed_iters > 0 ? dm->opts.lanczos_fixed_iters
+                                                                          : dm->opts.lanczos_kmax,
+                                         std::min<int64_t>(nv, 120));
+      TNA_TRY(dm->V.ensure(sizeof(double) * (size_t)(kmax + 2) * nv));
+      double *theta = dm->V.as<double>() + (int64_t)(kmax + 1) * nv;
+      auto t0 = std::chrono::steady_clock::now();
+      // theta = A_b A_{b+1}
+      GemmArgs g{};
+      g.M = m; g.N = n; g.K = chm;
+      g.A = dm->A[b].ptr; g.lda = chm; g.B = dm->A[b + 1].ptr; g.ldb = n; g.C = theta; g.ldc = n;
+      g.alpha = 1.0; g.batch = 1; g.compute = G_F64;
+      TNA_TRY(gemm(g, s));
+      LanczosResult lr{};
+      tna_status st = heff_lanczos(c, chl, chr, d, D, dm->Le[b].as<double>(), dm->Re[b + 1].as<double>(),
+                                        dm->M12.as<double>() + (size_t)I2 * I2 * b, dm->opts.heff_prec, theta,
+                                        dm->V.as<double>(), dm->opts.lanczos_tol, kmax, dm->opts.lanczos_restarts,
+                                        dm->opts.lanczos_fixed_iters, &lr);
+      if (st != TNA_OK) return st;
+      if (!lr.converged && worst == TNA_OK) worst = TNA_ERR_NOCONV;
+      auto t1 = std::chrono::steady_clock::now();
+      // SVD of theta and entropy of the full spectrum
+      SvdPlan p;
+      TNA_TRY(svd_plan(1, m, n, TNA_F64, &p));
+      TNA_TRY(dm->S.ensure(sizeof(double) * p.R));
+      int sw = 0;
+      st = svd_run(p, c->svd, theta, nv, dm->opts.svd_max_sweeps, &sw, s, c->host_ctr);
+      if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
+      if (st == TNA_ERR_NOCONV && worst == TNA_OK) worst = TNA_ERR_NOCONV;
+      double *spec = dm->spec.as<double>();
+      TNA_TRY(svd_spectrum(p, c->svd, dm->S.as<double>(), p.R, spec, s));
+      TNA_HIP(hipMemcpyAsync(dm->host_stage, spec, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      TNA_HIP(hipStreamSynchronize(s));
+      const double S_ent = dm->host_stage[1];
+      double terms[6];
+      int chi_next = 0;
+      TNA_TRY(pid_update(&dm->pid, &dm->st[b], S_ent, &chi_next, terms));
+      const int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next;
+      const int k = std::min(keep, p.R);
+      TNA_TRY(svd_trunc_S(p, dm->S.as<double>(), p.R, k, spec, s));
+      TNA_TRY(dm->A[b].ensure(sizeof(double) * (size_t)m * k));
+      TNA_TRY(dm->A[b + 1].ensure(sizeof(double) * (size_t)k * n));
+      TNA_TRY(svd_outputs_S(p, c->svd, dm->S.as<double>(), p.R, k, dm->A[b].ptr, 0, dm->A[b + 1].ptr, 0, TNA_F64,
+                            half == 0 ? 1 : 2, spec, s));
+      dm->chi[b] = k;
+      auto t2 = std::chrono::steady_clock::now();
+      // grow the environment past the moved centre
+      if (half == 0) {
+        TNA_TRY(dm->T1.ensure(sizeof(double) * (size_t)chl * D * d * k));
+        TNA_TRY(dm->T2.ensure(sizeof(double) * (size_t)chl * D * d * k));
+        TNA_TRY(dm->Le[b + 1].ensure(sizeof(double) * (size_t)k * D * k));
+        TNA_TRY(env_left(chl, k, d, D, dm->Le[b].as<double>(), dm->Ml.as<double>() + (size_t)I1 * I1 * b,
+                              dm->A[b].as<double>(), dm->T1.as<double>(), dm->T2.as<double>(),
+                              dm->Le[b + 1].as<double>(), s));
+      } else {
+        TNA_TRY(dm->T1.ensure(sizeof(double) * (size_t)chr * D * k * d));
+        TNA_TRY(dm->T2.ensure(sizeof(double) * (size_t)chr * D * k * d));
+        TNA_TRY(dm->Re[b].ensure(sizeof(double) * (size_t)k * D * k));
+        TNA_TRY(env_right(k, chr, d, D, dm->Re[b + 1].as<double>(), dm->Mr.as<double>() + (size_t)I1 * I1 * (b + 1),
+                               dm->A[b + 1].as<double>(), dm->T1.as<double>(), dm->T2.as<double>(),
+                               dm->Re[b].as<double>(), s));
+      }
+      // per-visit readback of the truncation sums and the first/last kept value
+      TNA_HIP(hipMemcpyAsync(dm->host_stage + 8, spec, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+      TNA_HIP(hipMemcpyAsync(dm->host_stage + 16, dm->S.as<double>(), sizeof(double), hipMemcpyDeviceToHost, s));
+      TNA_HIP(hipMemcpyAsync(dm->host_stage + 17, dm->S.as<double>() + (k - 1), sizeof(double), hipMemcpyDeviceToHost,
+                             s));
+      TNA_HIP(hipStreamSynchronize(s));
+      auto t3 = std::chrono::steady_clock::now();
+      E = lr.E;
+      if (log) {
+        tna_visit_log &r = log[rec];
+        const double *h = dm->host_stage;
+        r.sweep = dm->sweeps_done; r.dir = half; r.bond = b; r.m = m; r.n = n; r.k = k; r.chi_ctrl = chi_next;
+        r.lanczos_iters = lr.iters; r.svd_sweeps = sw; r.lanczos_ok = lr.converged;
+        r.E = lr.E; r.S = S_ent; r.S_ema = terms[4]; r.eps = h[8 + 2]; r.wdisc = h[8 + 3]; r.gap = h[8 + 5];
+        r.P = terms[0]; r.I = terms[1]; r.D = terms[2]; r.u = terms[3]; r.sigma0 = h[16]; r.sigma_last = h[17];
+        r.ms_lanczos = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        r.ms_svd = std::chrono::duration<double, std::milli>(t2 - t1).count();
+        r.ms_other = std::chrono::duration<double, std::milli>(t3 - t2).count();
+      }
+      ++rec;
+    }
+  }
+  dm->sweeps_done += 1;
+  if (E_out) *E_out = E;
+  return worst;
+}
+
+tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid) {
+  if (!dm) {
+    set_error("dmrg_get_state: null handle");
+    return TNA_ERR_ARG;
+  }
+  if (chi) std::memcpy(chi, dm->chi.data(), sizeof(int) * (dm->N - 1));
+  if (pid) std::memcpy(pid, dm->st.data(), sizeof(tna_pid_state) * (dm->N - 1));
+  return TNA_OK;
+}
+
+tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t *count) {
+  if (!dm) {
+    set_error("dmrg_get_mps: null handle");
+    return TNA_ERR_ARG;
+  }
+  size_t total = 0;
+  for (int i = 0; i < dm->N; ++i) total += (size_t)dm->CL(i) * dm->d * dm->CR(i);
+  if (count) *count = total;
+  if (!A_host) return TNA_OK;
+  if (capacity < total) {
+    set_error("dmrg_get_mps: capacity too small");
+    return TNA_ERR_ARG;
+  }
+  TNA_HIP(hipStreamSynchronize(dm->ctx->stream));
+  size_t off = 0;
+  for (int i = 0; i < dm->N; ++i) {
+    const size_t n = (size_t)dm->CL(i) * dm->d * dm->CR(i);
+    TNA_HIP(hipMemcpy(A_host + off, dm->A[i].ptr, sizeof(double) * n, hipMemcpyDeviceToHost));
+    off += n;
+  }
+  return TNA_OK;
+}
+
+void tna_dmrg_destroy(tna_dmrg dm) {
+  if (!dm) return;
+  (void)hipStreamSynchronize(dm->ctx->stream);
+  for (auto &b : dm->A) b.release();
+  for (auto &b : dm->Le) b.release();
+  for (auto &b : dm->Re) b.release();
+  for (DevBuf *b : {&dm->W, &dm->M12, &dm->Ml, &dm->Mr, &dm->V, &dm->T1, &dm->T2, &dm->spec, &dm->S}) b->release();
+  if (dm->host_stage) (void)hipHostFree(dm->host_stage);
+  delete dm;
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+// Dense contractions of the two-site DMRG step on the gfx950 matrix cores.
+//
+// One kernel template serves every GEMM of the path: H_eff stages S1 (L x theta)
+// and S4 (Z x R^T), the environment updates, theta formation.  A 256-thread
+// workgroup (four wave64s in a 2 x 2 arrangement) owns a BM x BN tile of C;
+// K advances in steps of 16 through two LDS buffers (the next slab is
+// fetched into registers while the current one feeds the MFMAs).  Each
+// wave accumulates (BM/2) x (BN/2) as 16 x 16 MFMA tiles:
+//   FP64: v_mfma_f64_16x16x4_f64, FP32: v_mfma_f32_16x16x4_f32.
+// Operand layout of the 16x16x4 MFMA (lane l, r = 0..3):
+//   A[i][k]: lane i + 16k      B[k][j]: lane j + 16k      D[i][j]: lane j + 16(i/4), reg i%4.
+#include "internal.h"
+
+namespace tna {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef v4d type; };
+template <> struct Acc<float> { typedef v4f type; };
+
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+struct GemmDev {
+  int M, N, K, lda, ldb, ldc;
+  const void *A;
+  const void *B;
+  void *C;
+  double alpha, beta;
+  int64_t sA, sB, sC;
+};
+
+constexpr int BK = 16;
+
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
+  constexpr int PAD = 1;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int LA = BM * BK / 256;  // A elements per thread per slab
+  constexpr int LB = BN * BK / 256;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int z = blockIdx.z;
+  const TA *A = static_cast<const TA *>(g.A) + g.sA * z;
+  const TB *B = static_cast<const TB *>(g.B) + g.sB * z;
+  TC *C = static_cast<TC *>(g.C) + g.sC * z;
+  const int M = g.M, N = g.N, K = g.K;
+
+  // element coordinates this thread loads (tile-local)
+  auto a_coord = [&](int p, int &i, int &k) {
+    if (!TRA) { k = tid % BK; i = tid / BK + (256 / BK) * p; }
+    else { i = tid % BM; k = tid / BM + (256 / BM) * p; }
+  };
+  auto b_coord = [&](int p, int &k, int &j) {
+    if (!TRB) { j = tid % BN; k = tid / BN + (256 / BN) * p; }
+    else { k = tid % BK; j = tid / BK + (256 / BK) * p; }
+  };
+
+  T ra[LA], rb[LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      int i, k;
+      a_coord(p, i, k);
+      int gi = m0 + i, gk = k0 + k;
+      T v = T(0);
+      if (gi < M && gk < K) v = T(TRA ? A[(int64_t)gk * g.lda + gi] : A[(int64_t)gi * g.lda + gk]);
+      ra[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      int k, j;
+      b_coord(p, k, j);
+      int gk = k0 + k, gj = n0 + j;
+      T v = T(0);
+      if (gj < N && gk < K) v = T(TRB ? B[(int64_t)gj * g.ldb + gk] : B[(int64_t)gk * g.ldb + gj]);
+      rb[p] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      int i, k;
+      a_coord(p, i, k);
+      As[buf][k][i] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      int k, j;
+      b_coord(p, k, j);
+      Bs[buf][k][j] = rb[p];
+    }
+  };
+
+  typename Acc<T>::type acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = typename Acc<T>::type{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[buf][kk + lk][wr * WM + a * 16 + lr];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kk + lk][wc * WN + b * 16 + lr];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = m0 + wr * WM + a * 16 + 4 * lk + r;
+        int col = n0 + wc * WN + b * 16 + lr;
+        if (row < M && col < N) {
+          double v = alpha * (double)acc[a][b][r];
+          int64_t idx = (int64_t)row * g.ldc + col;
+          if (beta != 0.0) v += beta * (double)C[idx];
+          C[idx] = (TC)v;
+        }
+      }
+}
+
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN>
+tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  if (grid.y > 65535 || grid.z > 65535) {
+    set_error("gemm: grid too large");
+    return TNA_ERR_ARG;
+  }
+  if (!a.transA && !a.transB)
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, false>), grid, dim3(256), 0, s, d);
+  else if (!a.transA && a.transB)
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, true>), grid, dim3(256), 0, s, d);
+  else if (a.transA && !a.transB)
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, true, false>), grid, dim3(256), 0, s, d);
+  else {
+    set_error("gemm: transA && transB not built");
+    return TNA_ERR_UNSUPPORTED;
+  }
+  TNA_HIP(hipGetLastError());
+  return TNA_OK;
+}
+
+// Tile choice: the 128 x 128 tile when the grid still has >= 2 waves of
+// workgroups on 256 CUs, else 64 x 64 to spread small problems.
+template <typename T, typename TA, typename TB, typename TC>
+tna_status launch_types(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
+  int64_t big = (int64_t)((a.M + 127) / 128) * ((a.N + 127) / 128) * a.batch;
+  if (big >= 512) return launch_tile<T, TA, TB, TC, 128, 128>(a, d, s);
+  return launch_tile<T, TA, TB, TC, 64, 64>(a, d, s);
+}
+
+}  // namespace
+
+tna_status gemm(const GemmArgs &a, hipStream_t s) {
+  if (a.M < 0 || a.N < 0 || a.K < 0 || a.batch < 1) {
+    set_error("gemm: negative size");
+    return TNA_ERR_ARG;
+  }
+  if (a.M == 0 || a.N == 0) return TNA_OK;
+  GemmDev d{a.M, a.N, a.K, a.lda, a.ldb, a.ldc, a.A, a.B, a.C, a.alpha, a.beta, a.sA, a.sB, a.sC};
+  if (a.K == 0) d.alpha = 0.0;
+  const int code = a.typeA * 4 + a.typeB * 2 + a.typeC;  // 0 = all double
+  if (a.compute == G_F64) {
+    if (code != 0) {
+      set_error("gemm: FP64 compute takes double operands");
+      return TNA_ERR_UNSUPPORTED;
+    }
+    return launch_types<double, double, double, double>(a, d, s);
+  }
+  switch (code) {
+    case 0: return launch_types<float, double, double, double>(a, d, s);
+    case 1: return launch_types<float, double, double, float>(a, d, s);
+    case 5: return launch_types<float, float, double, float>(a, d, s);
+    case 6: return launch_types<float, float, float, double>(a, d, s);
+    case 7: return launch_types<float, float, float, float>(a, d, s);
+  }
+  set_error("gemm: FP32 operand combination not built");
+  return TNA_ERR_UNSUPPORTED;
+}
+
+}  // namespace tna

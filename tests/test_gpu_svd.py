@@ -1,0 +1,96 @@
+"""Truncated SVD + spectrum sums on the GPU vs the oracle and closed forms."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import ctx, to_dev
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -53
+
+
+def _svd(c, A, k):
+    S, U, Vt, spec, kk, sw, st = c.svd_truncate(to_dev(A), k)
+    return S.cpu().numpy(), U.cpu().numpy(), Vt.cpu().numpy(), spec.cpu().numpy(), kk, sw, st
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 8), (8, 2), (5, 7), (33, 33), (64, 100), (100, 64), (130, 70),
+                                 (97, 300), (256, 256)])
+def test_svd_matches_oracle(m, n):
+    A = synth.random_matrix(m, n, 100 + m + 7 * n)
+    c = ctx()
+    R = min(m, n)
+    k = max(1, (2 * R) // 3)
+    S, U, Vt, spec, kk, sw, st = _svd(c, A, k)
+    So, Uo, Vo, swo, rc = oracle.svd(A)
+    print(f"svd {m}x{n} k={kk} sweeps gpu={sw} oracle={swo} max|dS|={np.abs(S - So).max():.3e}")
+    assert st == 0 and kk == k
+    assert np.abs(S - So).max() <= 1e-12 * So[0]
+    # factors: reconstruction of the kept part, orthonormality, gauge-identical columns
+    tol = 64 * max(m, n) * EPS
+    assert np.abs(U.T @ U - np.eye(k)).max() <= tol
+    assert np.abs(Vt @ Vt.T - np.eye(k)).max() <= tol
+    assert np.abs((U * S[:k]) @ Vt - (Uo[:, :k] * So[:k]) @ Vo[:, :k].T).max() <= tol * So[0]
+    gaps = np.abs(np.diff(So[:k + 1])) / So[0] if k < R else np.abs(np.diff(So[:k])) / So[0]
+    if gaps.size == 0 or gaps.min() > 1e-6:
+        assert np.abs(U - Uo[:, :k]).max() <= 1e-9
+        assert np.abs(Vt - Vo[:, :k].T).max() <= 1e-9
+    # spectrum sums vs the oracle's
+    Z, ent, eps, w = oracle.spectrum(So, k)
+    assert abs(spec[0] - Z) <= 1e-13 * Z
+    assert abs(spec[1] - ent) <= 1e-12 * max(1.0, ent)
+    assert abs(spec[2] - eps) <= 1e-10 * max(eps, 1e-300) + 1e-14 * So[0]
+
+
+@pytest.mark.parametrize("n,tau", [(512, 8.0), (512, 64.0)])
+def test_prescribed_spectrum_c3_small(n, tau):
+    A = synth.svd_test_matrix(n, tau, seed=0)
+    c = ctx()
+    S, U, Vt, spec, kk, sw, st = _svd(c, A, n // 2)
+    sig = synth.svd_test_spectrum(n, tau)
+    So = oracle.svd(A)[0]
+    print(f"c3 n={n} tau={tau} sweeps={sw} max|S-sig|={np.abs(S - sig).max():.3e} max|S-So|={np.abs(S - So).max():.3e}")
+    assert np.abs(S - sig).max() <= 64 * n * EPS
+    big = So >= 1e-4 * So[0]
+    assert np.all(np.abs(S[big] - So[big]) <= 1e-10 * So[big])
+    q = math.exp(-2.0 / tau)
+    ent = -math.log((1 - q) / (1 - q ** n)) - (q / (1 - q) - n * q ** n / (1 - q ** n)) * math.log(q)
+    assert abs(spec[1] - ent) <= 1e-10
+
+
+def test_svd_rank_deficient_and_zero():
+    c = ctx()
+    x, y = synth.random_matrix(40, 1, 1), synth.random_matrix(1, 24, 2)
+    S, U, Vt, spec, kk, sw, st = _svd(c, x @ y, 5)
+    assert abs(S[0] - np.linalg.norm(x) * np.linalg.norm(y)) <= 1e-13 * S[0]
+    assert np.all(S[1:] <= 1e-13 * S[0])
+    assert np.abs(U.T @ U - np.eye(5)).max() <= 1e-12
+    assert np.abs(Vt @ Vt.T - np.eye(5)).max() <= 1e-12
+    S, U, Vt, spec, kk, sw, st = _svd(c, np.zeros((6, 9)), 3)
+    assert np.all(S == 0)
+    assert np.abs(Vt @ Vt.T - np.eye(3)).max() <= 1e-14
+
+
+def test_svd_batched_equals_single():
+    import torch
+    c = ctx()
+    As = np.stack([synth.random_matrix(70, 90, 200 + i) for i in range(4)])
+    S, U, Vt, spec, sw, st = c.svd_truncate_batched(to_dev(As), 20)
+    for i in range(4):
+        S1, U1, Vt1, spec1, _, _, _ = _svd(c, As[i], 20)
+        assert np.abs(S[i].cpu().numpy() - S1).max() <= 1e-13 * S1[0]
+        assert np.abs(U[i].cpu().numpy() - U1).max() <= 1e-10
+
+
+def test_svd_f32_input():
+    import torch
+    c = ctx()
+    A = synth.svd_test_matrix(128, 8.0, seed=1)
+    A32 = A.astype(np.float32)
+    S, U, Vt, spec, kk, sw, st = c.svd_truncate(torch.from_numpy(A32).cuda(), 64)
+    So = oracle.svd(A32.astype(np.float64))[0]
+    assert U.dtype == torch.float32
+    assert np.abs(S.cpu().numpy() - So).max() <= 1e-12 * So[0]
