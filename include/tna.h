@@ -57,9 +57,15 @@ tna_status tna_set_stream(tna_ctx ctx, void *hip_stream);
 /* Waits for all work the context enqueued.  Synchronises. */
 tna_status tna_synchronize(tna_ctx ctx);
 const char *tna_last_error(void);
-/* Milliseconds spent in the kernel families of the last calls (see
- * tna_timing_* below); accumulated with HIP events when timing is enabled. */
-tna_status tna_set_timing(tna_ctx ctx, int enable);
+/* Kernel timing.  With enable != 0, every launch whose kernel name starts
+ * with `prefix` (NULL or "" = all) is bracketed by HIP events on its stream;
+ * this perturbs the timing of small launches, so filter to the kernel of
+ * interest.  tna_kernel_stats() synchronises, then writes a JSON array of
+ * {name, count, ms, flops, bytes} (flops and bytes: the algorithmic amounts
+ * the launch sites declare, summed over launches) into out (cap bytes) and
+ * clears the counters if reset != 0. */
+tna_status tna_set_timing(tna_ctx ctx, int enable, const char *prefix);
+tna_status tna_kernel_stats(tna_ctx ctx, char *out, size_t cap, int reset);
 
 /* ---------------------------------------------------------------- models */
 /* Bulk MPO tensors of an open chain (host).  model 0: XXZ,
@@ -167,6 +173,38 @@ tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid);
  * doubles); *count receives the number of doubles.  Synchronises. */
 tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t *count);
 void tna_dmrg_destroy(tna_dmrg dm);
+
+/* ---------------------------------------------------------------- learned scheduler */
+/* A 25 -> 64 -> 64 -> 1 perceptron (tanh hidden units, linear output), the
+ * learned stand-in for the predictive scheduler of Sec. 7, trained and run
+ * in FP32 by the library's own kernels.  Inputs per bond visit: the last 8
+ * EMA entropies (oldest first, missing history repeats the oldest), the 16
+ * largest log singular values (floored at ln 1e-16) and the relative bond
+ * position; output: log2 of the bond dimension the bond needs at its next
+ * visit.  Parameter layout (5889 floats): W1[64][25] b1[64] W2[64][64] b2[64]
+ * W3[64] b3.  Inputs are standardised by (x - mean)/std when a normalisation
+ * is set. */
+typedef struct tna_mlp_s *tna_mlp;
+#define TNA_MLP_IN 25
+#define TNA_MLP_NPARAM 5889
+/* params_host: initial parameters (host, 5889 floats; the caller draws them). */
+tna_status tna_mlp_create(tna_ctx ctx, const float *params_host, tna_mlp *out);
+tna_status tna_mlp_set_normalization(tna_mlp n, const float *mean_host, const float *std_host);
+tna_status tna_mlp_get_params(tna_mlp n, float *params_host);
+/* y[b] (device, B floats) for X (device, B x 25 floats). */
+tna_status tna_mlp_forward(tna_mlp n, int B, const float *X, float *y);
+/* grad (device, 5889 floats) and loss (device, 1 float, may be NULL) of
+ * (1/B) sum_b (y_b - T_b)^2. */
+tna_status tna_mlp_loss_grad(tna_mlp n, int B, const float *X, const float *T, float *grad, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
+tna_status tna_mlp_adam_step(tna_mlp n, const float *grad, float lr);
+/* epochs of mini-batch Adam over (X, T) (device, nsamp samples); perm (device,
+ * epochs x nsamp ints) gives the sample order of every epoch; loss_per_epoch
+ * (host, may be NULL) receives the full-data loss after each epoch.
+ * Synchronises. */
+tna_status tna_mlp_train(tna_mlp n, int nsamp, const float *X, const float *T, const int *perm, int epochs,
+                         int batch, float lr, float *loss_per_epoch);
+void tna_mlp_destroy(tna_mlp n);
 
 #ifdef __cplusplus
 }

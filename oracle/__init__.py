@@ -76,6 +76,13 @@ def lib():
         _lib.or_dmrg_run.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, ip, C.POINTER(PidParams),
                                      C.POINTER(DmrgOpts), dp, dp, ip, C.POINTER(PidState)]
         _lib.or_right_canonical.argtypes = [C.c_int, C.c_int, dp, ip, dp, ip]
+        _lib.or_mlp_forward.argtypes = [dp, C.c_int, dp, dp]
+        _lib.or_mlp_forward.restype = None
+        _lib.or_mlp_loss_grad.argtypes = [dp, C.c_int, dp, dp, dp]
+        _lib.or_mlp_loss_grad.restype = C.c_double
+        _lib.or_adam_step.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                      C.c_double]
+        _lib.or_adam_step.restype = None
     return _lib
 
 
@@ -228,3 +235,27 @@ def dmrg_run(W, A_packed, chi_init, pp: PidParams, n_sweeps, lanczos_tol=1e-12, 
                            C.byref(pp), C.byref(opts), _p(log), _p(E), _ip(chi), pid)
     recs = [dict(zip(LOG_NAMES, row)) for row in log]
     return dict(log=recs, log_array=log, E=E, chi=chi, pid=pid, rc=rc)
+
+
+# ---------------------------------------------------------------- learned scheduler (MLP)
+MLP_IN, MLP_H = 25, 64
+MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+
+
+def mlp_forward(params, x):
+    x = _f64(np.atleast_2d(x))
+    y = np.zeros(x.shape[0])
+    lib().or_mlp_forward(_p(_f64(params)), x.shape[0], _p(x), _p(y))
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    x = _f64(np.atleast_2d(x))
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().or_mlp_loss_grad(_p(_f64(params)), x.shape[0], _p(x), _p(_f64(t)), _p(g))
+    return float(loss), g
+
+
+def adam_step(params, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on params, m, v (float64 arrays)."""
+    lib().or_adam_step(len(params), _p(params), _p(_f64(g)), _p(m), _p(v), int(t), lr, b1, b2, eps)

@@ -878,3 +878,99 @@ int or_right_canonical(int N, int d, const double *A_in, const int *chi_in, doub
   free(A); free(chi);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Learned bond-dimension scheduler (the learned stand-in for the predictive */
+/* scheduler of Sec. 7): a multilayer perceptron 25 -> 64 -> 64 -> 1 with    */
+/* tanh hidden units and a linear output, trained by mean-squared error with */
+/* Adam (Kingma & Ba 2015).  Parameter layout (5889 values):                  */
+/*   W1[64][25] b1[64] W2[64][64] b2[64] W3[64] b3                            */
+/* ------------------------------------------------------------------------ */
+#define MLP_IN 25
+#define MLP_H 64
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
+
+int or_mlp_nparam(void) { return MLP_NPARAM; }
+
+/* y[b] = W3 . tanh(W2 tanh(W1 x_b + b1) + b2) + b3 */
+void or_mlp_forward(const double *p, int B, const double *x, double *y) {
+  const double *W1 = p, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+  const double *W3 = b2 + MLP_H, *b3 = W3 + MLP_H;
+  for (int b = 0; b < B; ++b) {
+    double h1[MLP_H], h2[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = b1[i];
+      for (int k = 0; k < MLP_IN; ++k) s += W1[i * MLP_IN + k] * x[(size_t)b * MLP_IN + k];
+      h1[i] = tanh(s);
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = b2[i];
+      for (int k = 0; k < MLP_H; ++k) s += W2[i * MLP_H + k] * h1[k];
+      h2[i] = tanh(s);
+    }
+    double s = b3[0];
+    for (int k = 0; k < MLP_H; ++k) s += W3[k] * h2[k];
+    y[b] = s;
+  }
+}
+
+/* loss = (1/B) sum_b (y_b - t_b)^2 and its gradient with respect to p
+ * (chain rule through the three layers; d tanh(s)/ds = 1 - tanh(s)^2). */
+double or_mlp_loss_grad(const double *p, int B, const double *x, const double *t, double *g) {
+  const double *W1 = p, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+  const double *W3 = b2 + MLP_H, *b3 = W3 + MLP_H;
+  double *gW1 = g, *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H;
+  double *gW3 = gb2 + MLP_H, *gb3 = gW3 + MLP_H;
+  memset(g, 0, sizeof(double) * MLP_NPARAM);
+  double loss = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const double *xb = x + (size_t)b * MLP_IN;
+    double h1[MLP_H], h2[MLP_H], d2[MLP_H], d1[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = b1[i];
+      for (int k = 0; k < MLP_IN; ++k) s += W1[i * MLP_IN + k] * xb[k];
+      h1[i] = tanh(s);
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = b2[i];
+      for (int k = 0; k < MLP_H; ++k) s += W2[i * MLP_H + k] * h1[k];
+      h2[i] = tanh(s);
+    }
+    double y = b3[0];
+    for (int k = 0; k < MLP_H; ++k) y += W3[k] * h2[k];
+    const double r = y - t[b];
+    loss += r * r;
+    const double dy = 2.0 * r / B;
+    gb3[0] += dy;
+    for (int k = 0; k < MLP_H; ++k) {
+      gW3[k] += dy * h2[k];
+      d2[k] = dy * W3[k] * (1.0 - h2[k] * h2[k]);
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      gb2[i] += d2[i];
+      for (int k = 0; k < MLP_H; ++k) gW2[i * MLP_H + k] += d2[i] * h1[k];
+    }
+    for (int k = 0; k < MLP_H; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < MLP_H; ++i) s += W2[i * MLP_H + k] * d2[i];
+      d1[k] = s * (1.0 - h1[k] * h1[k]);
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      gb1[i] += d1[i];
+      for (int k = 0; k < MLP_IN; ++k) gW1[i * MLP_IN + k] += d1[i] * xb[k];
+    }
+  }
+  return loss / B;
+}
+
+/* One Adam step at step count t (1-based): m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, p -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps). */
+void or_adam_step(int n, double *p, const double *g, double *m, double *v, int t, double lr, double b1, double b2,
+                  double eps) {
+  const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+  for (int i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+  }
+}

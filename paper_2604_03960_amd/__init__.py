@@ -69,7 +69,8 @@ _SIGS = {
     "tna_set_stream": ([_vp, _vp], C.c_int),
     "tna_synchronize": ([_vp], C.c_int),
     "tna_last_error": ([], C.c_char_p),
-    "tna_set_timing": ([_vp, C.c_int], C.c_int),
+    "tna_set_timing": ([_vp, C.c_int, C.c_char_p], C.c_int),
+    "tna_kernel_stats": ([_vp, C.c_char_p, C.c_size_t, C.c_int], C.c_int),
     "tna_mpo_build": ([C.c_int, C.c_int, _dp, _dp, _ip], C.c_int),
     "tna_heff_apply": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int], C.c_int),
     "tna_svd_truncate": ([_vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp, _vp, _vp, _vp, _ip, _ip], C.c_int),
@@ -82,6 +83,14 @@ _SIGS = {
     "tna_dmrg_get_state": ([_vp, _ip, C.POINTER(PidState)], C.c_int),
     "tna_dmrg_get_mps": ([_vp, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "tna_dmrg_destroy": ([_vp], None),
+    "tna_mlp_create": ([_vp, _vp, C.POINTER(C.c_void_p)], C.c_int),
+    "tna_mlp_set_normalization": ([_vp, _vp, _vp], C.c_int),
+    "tna_mlp_get_params": ([_vp, _vp], C.c_int),
+    "tna_mlp_forward": ([_vp, C.c_int, _vp, _vp], C.c_int),
+    "tna_mlp_loss_grad": ([_vp, C.c_int, _vp, _vp, _vp, _vp], C.c_int),
+    "tna_mlp_adam_step": ([_vp, _vp, C.c_float], C.c_int),
+    "tna_mlp_train": ([_vp, C.c_int, _vp, _vp, _vp, C.c_int, C.c_int, C.c_float, _vp], C.c_int),
+    "tna_mlp_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -156,6 +165,17 @@ class Context:
 
     def synchronize(self):
         _check(_lib.tna_synchronize(self.h))
+
+    def set_timing(self, enable: bool, prefix: str = ""):
+        """HIP-event timing of launches whose kernel name starts with prefix."""
+        _check(_lib.tna_set_timing(self.h, int(enable), prefix.encode()))
+
+    def kernel_stats(self, reset: bool = True):
+        """[{name, count, ms, flops, bytes}] accumulated since the last reset (synchronises)."""
+        import json
+        buf = C.create_string_buffer(1 << 20)
+        _check(_lib.tna_kernel_stats(self.h, buf, len(buf), int(reset)))
+        return json.loads(buf.value.decode())
 
     def set_stream(self, stream):
         _check(_lib.tna_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
@@ -256,6 +276,69 @@ class Dmrg:
     def close(self):
         if getattr(self, "h", None):
             _lib.tna_dmrg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ learned scheduler
+MLP_IN, MLP_NPARAM = 25, 5889
+
+
+class Mlp:
+    """The learned bond-dimension scheduler network (FP32, library kernels)."""
+
+    def __init__(self, ctx: Context, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_NPARAM
+        h = C.c_void_p()
+        _check(_lib.tna_mlp_create(ctx.h, C.c_void_p(p.ctypes.data), C.byref(h)))
+        self.h, self.ctx = h, ctx
+
+    def set_normalization(self, mean=None, std=None):
+        if mean is None:
+            _check(_lib.tna_mlp_set_normalization(self.h, None, None))
+            return
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(std, dtype=np.float32)
+        self._norm = (m, s)
+        _check(_lib.tna_mlp_set_normalization(self.h, C.c_void_p(m.ctypes.data), C.c_void_p(s.ctypes.data)))
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(_lib.tna_mlp_get_params(self.h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def forward(self, X):
+        torch = self.ctx.torch
+        assert X.is_cuda and X.dtype == torch.float32 and X.is_contiguous() and X.shape[1] == MLP_IN
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(_lib.tna_mlp_forward(self.h, X.shape[0], _ptr(X), _ptr(y)))
+        return y
+
+    def loss_grad(self, X, T):
+        torch = self.ctx.torch
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(_lib.tna_mlp_loss_grad(self.h, X.shape[0], _ptr(X), _ptr(T), _ptr(g), _ptr(loss)))
+        return loss, g
+
+    def adam_step(self, g, lr=1e-3):
+        _check(_lib.tna_mlp_adam_step(self.h, _ptr(g), float(lr)))
+
+    def train(self, X, T, perm, epochs, batch=256, lr=1e-3):
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(_lib.tna_mlp_train(self.h, X.shape[0], _ptr(X), _ptr(T), _ptr(perm), epochs, batch, float(lr),
+                                  C.c_void_p(losses.ctypes.data)))
+        return losses
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tna_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

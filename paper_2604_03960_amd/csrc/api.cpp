@@ -9,8 +9,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
@@ -21,6 +24,96 @@ namespace tna {
 
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
+
+// ---------------------------------------------------------------- kernel timing
+namespace {
+struct KStat {
+  long count = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+struct Pending {
+  std::string name;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::string prefix;
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  std::map<std::string, KStat> stats;
+  hipEvent_t open_a = nullptr;
+  std::string open_name;
+} g_tm;
+
+hipEvent_t take_event() {
+  if (!g_tm.pool.empty()) {
+    hipEvent_t e = g_tm.pool.back();
+    g_tm.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void drain_pending() {
+  for (auto &p : g_tm.pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    KStat &k = g_tm.stats[p.name];
+    k.count += 1;
+    k.ms += ms;
+    k.flops += p.flops;
+    k.bytes += p.bytes;
+    g_tm.pool.push_back(p.a);
+    g_tm.pool.push_back(p.b);
+  }
+  g_tm.pending.clear();
+}
+}  // namespace
+
+bool timing_on() { return g_tm.on; }
+
+bool timing_wanted(const char *name) {
+  if (!g_tm.on) return false;
+  return g_tm.prefix.empty() || std::strncmp(name, g_tm.prefix.c_str(), g_tm.prefix.size()) == 0;
+}
+
+void timer_begin(const char *name, hipStream_t s) {
+  if (!timing_wanted(name)) return;
+  std::lock_guard<std::mutex> lk(g_tm.mu);
+  g_tm.open_a = take_event();
+  g_tm.open_name = name;
+  (void)hipEventRecord(g_tm.open_a, s);
+}
+
+void timer_end(const char *name, double flops, double bytes, hipStream_t s) {
+  if (!timing_wanted(name)) return;
+  std::lock_guard<std::mutex> lk(g_tm.mu);
+  if (!g_tm.open_a || g_tm.open_name != name) return;
+  hipEvent_t b = take_event();
+  (void)hipEventRecord(b, s);
+  g_tm.pending.push_back(Pending{name, g_tm.open_a, b, flops, bytes});
+  g_tm.open_a = nullptr;
+  if (g_tm.pending.size() > 8192) drain_pending();
+}
+
+tna_status post_launch(const char *what) {
+  static const int dbg = [] {
+    const char *e = std::getenv("TNA_DEBUG_SYNC");
+    return e && e[0] == '1';
+  }();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && dbg) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return TNA_ERR_DEVICE;
+  }
+  return TNA_OK;
+}
 
 // ---------------------------------------------------------------- contraction recipes
 struct HeffOp {
@@ -419,12 +512,43 @@ tna_status tna_synchronize(tna_ctx c) {
   return TNA_OK;
 }
 
-tna_status tna_set_timing(tna_ctx c, int enable) {
+tna_status tna_set_timing(tna_ctx c, int enable, const char *prefix) {
   if (!c) {
     set_error("null context");
     return TNA_ERR_ARG;
   }
+  std::lock_guard<std::mutex> lk(g_tm.mu);
   c->timing = enable;
+  g_tm.on = enable != 0;
+  g_tm.prefix = prefix ? prefix : "";
+  return TNA_OK;
+}
+
+tna_status tna_kernel_stats(tna_ctx c, char *out, size_t cap, int reset) {
+  if (!c || !out || cap == 0) {
+    set_error("kernel_stats: null argument");
+    return TNA_ERR_ARG;
+  }
+  TNA_HIP(hipStreamSynchronize(c->stream));
+  std::lock_guard<std::mutex> lk(g_tm.mu);
+  drain_pending();
+  std::string js = "[";
+  bool first = true;
+  for (auto &kv : g_tm.stats) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "%s{\"name\":\"%s\",\"count\":%ld,\"ms\":%.6f,\"flops\":%.6e,\"bytes\":%.6e}",
+                  first ? "" : ",", kv.first.c_str(), kv.second.count, kv.second.ms, kv.second.flops,
+                  kv.second.bytes);
+    js += buf;
+    first = false;
+  }
+  js += "]";
+  if (reset) g_tm.stats.clear();
+  if (js.size() + 1 > cap) {
+    set_error("kernel_stats: buffer too small");
+    return TNA_ERR_ARG;
+  }
+  std::memcpy(out, js.c_str(), js.size() + 1);
   return TNA_OK;
 }
 

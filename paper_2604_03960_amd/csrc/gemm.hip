@@ -7,8 +7,11 @@
 // fetched into registers while the current one feeds the MFMAs).  Each
 // wave accumulates (BM/2) x (BN/2) as 16 x 16 MFMA tiles:
 //   FP64: v_mfma_f64_16x16x4_f64, FP32: v_mfma_f32_16x16x4_f32.
-// Operand layout of the 16x16x4 MFMA (lane l, r = 0..3):
-//   A[i][k]: lane i + 16k      B[k][j]: lane j + 16k      D[i][j]: lane j + 16(i/4), reg i%4.
+// Operand layout of the 16x16x4 MFMAs (lane l, result register r = 0..3):
+//   A[i][k]: lane i + 16k      B[k][j]: lane j + 16k
+//   D[i][j]: lane j + 16(i%4), reg i/4 for f64;  lane j + 16(i/4), reg i%4 for f32.
+#include <cstdio>
+
 #include "internal.h"
 
 namespace tna {
@@ -27,6 +30,9 @@ __device__ inline v4d mfma16(double a, double b, v4d c) {
 __device__ inline v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// row of result register r held by lane group lk (= lane / 16)
+__device__ inline int mfma_row(double, int lk, int r) { return 4 * r + lk; }
+__device__ inline int mfma_row(float, int lk, int r) { return 4 * lk + r; }
 
 struct GemmDev {
   int M, N, K, lda, ldb, ldc;
@@ -142,7 +148,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = m0 + wr * WM + a * 16 + 4 * lk + r;
+        int row = m0 + wr * WM + a * 16 + mfma_row(T(0), lk, r);
         int col = n0 + wc * WN + b * 16 + lr;
         if (row < M && col < N) {
           double v = alpha * (double)acc[a][b][r];
@@ -160,6 +166,12 @@ tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
     set_error("gemm: grid too large");
     return TNA_ERR_ARG;
   }
+  char name[64] = "";
+  if (timing_on()) {
+    std::snprintf(name, sizeof name, "gemm.%s.%dx%d.%c%c", sizeof(T) == 8 ? "f64" : "f32", BM, BN,
+                  a.transA ? 'T' : 'N', a.transB ? 'T' : 'N');
+    timer_begin(name, s);
+  }
   if (!a.transA && !a.transB)
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, false>), grid, dim3(256), 0, s, d);
   else if (!a.transA && a.transB)
@@ -170,7 +182,13 @@ tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
     set_error("gemm: transA && transB not built");
     return TNA_ERR_UNSUPPORTED;
   }
-  TNA_HIP(hipGetLastError());
+  if (name[0]) {
+    const double mnk = (double)a.M * a.N * a.K * a.batch;
+    const double by = ((double)a.M * a.K * sizeof(TA) + (double)a.K * a.N * sizeof(TB) + (double)a.M * a.N * sizeof(TC)) *
+                      a.batch;
+    timer_end(name, 2.0 * mnk, by, s);
+  }
+  TNA_LAUNCHED("gemm.hip:1");
   return TNA_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -22,11 +23,25 @@ void set_error(const std::string &msg);
       return TNA_ERR_DEVICE;                                                           \
     }                                                                                  \
   } while (0)
+// After a launch: report launch errors; with TNA_DEBUG_SYNC=1 in the
+// environment also synchronise the device and report execution errors.
+tna_status post_launch(const char *what);
+#define TNA_LAUNCHED(what) TNA_TRY(::tna::post_launch(what))
 #define TNA_TRY(st)                      \
   do {                                   \
     tna_status s_ = (st);                \
     if (s_ != TNA_OK) return s_;         \
   } while (0)
+
+// ------------------------------------------------------------------ kernel timing
+// When enabled (tna_set_timing), launches whose name starts with the filter
+// prefix are bracketed by HIP events on their stream; tna_kernel_stats()
+// reports per-name launch count, total milliseconds and the algorithmic
+// flops and bytes the launch sites declare.
+bool timing_on();
+bool timing_wanted(const char *name);
+void timer_begin(const char *name, hipStream_t s);
+void timer_end(const char *name, double flops, double bytes, hipStream_t s);
 
 // ------------------------------------------------------------------ device buffer
 // Grow-only device allocation; contents are not preserved across growth.
@@ -152,6 +167,7 @@ tna_status env_left(int chl, int k, int d, int D, const double *L, const double 
 tna_status env_right(int k, int chr, int d, int D, const double *R, const double *Mr, const double *B, double *T1,
                      double *T2, double *Rn, hipStream_t s);
 tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next, double *terms);
+tna_status mlp_forward_dev(tna_mlp n, int B, const float *X, float *y);
 
 }  // namespace tna
 

@@ -48,6 +48,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr double EPS53 = 1.1102230246251565e-16;
 constexpr int BS = 32;  // rows per block
 
+// v_mfma_f64_16x16x4_f64: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// result D[i][j] in lane j + 16(i%4), register i/4.
 __device__ inline v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(256) void gram_kernel(SvdDev a) {
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 32 * qi + 16 * i + 4 * lk + r, col = 32 * qj + 16 * j + lr;
+        const int row = 32 * qi + 16 * i + 4 * r + lk, col = 32 * qj + 16 * j + lr;  // f64 result layout
         G[row * 64 + col] = acc[i][j][r];
       }
 }
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void apply_kernel(SvdDev a, int ntile_b) {
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int so = 16 * wave + 4 * lk + r, col = 16 * t + lr;
+      const int so = 16 * wave + 4 * r + lk, col = 16 * t + lr;  // f64 result layout
       if (valid(so) && c0 + col < ld) X[(int64_t)grow(so) * ld + c0 + col] = acc[t][r];
     }
 }
@@ -652,21 +654,34 @@ tna_status svd_run(const SvdPlan &p, SvdBuffers &wb, const void *A, int64_t stri
       hipLaunchKernelGGL(load_trans_kernel<float>, g, dim3(256), 0, s, static_cast<const float *>(A), strideA, p.m,
                          p.n, wb.bw.as<double>());
   }
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:1");
   TNA_TRY(set_identity(wb.jt.as<double>(), p.R, p.R, B, (int64_t)p.R * p.R, s));
   SvdDev d = make_dev(p, wb, (double)p.C * EPS53);
   const int ntile_b = ceil_div(p.C, 64), ntile_j = ceil_div(p.R, 64);
+  // algorithmic work of one step: every row of B meets its partner block once
+  // (Gram: 2 (2b)^2 C per pair), then [B;J] rows are rotated (2 (2b)^2 (C+R) per pair)
+  const double pairs = (double)npairs * B, b2 = 64.0 * 64.0;
+  const double gram_flops = 2.0 * b2 * p.C * pairs, gram_bytes = 8.0 * (double)p.R * p.C * B;
+  const double eig_bytes = 8.0 * b2 * pairs * (p.ksplit + 1);
+  const double apply_flops = 2.0 * b2 * (double)(p.C + p.R) * pairs;
+  const double apply_bytes = 16.0 * ((double)p.R * p.C + (double)p.R * p.R) * B;
   int sw = 0;
   bool conv = false;
   for (sw = 1; sw <= max_sweeps; ++sw) {
     TNA_TRY(fill_int(wb.ctr.as<int>(), 1, 0, s));
     for (int step = 0; step < p.nb - 1; ++step) {
       d.step = step;
+      timer_begin("svd.gram", s);
       hipLaunchKernelGGL(gram_kernel, dim3(npairs, p.ksplit, B), dim3(256), 0, s, d);
+      timer_end("svd.gram", gram_flops, gram_bytes, s);
+      timer_begin("svd.eigen", s);
       hipLaunchKernelGGL(eigen_kernel, dim3(npairs, B), dim3(256), 0, s, d);
+      timer_end("svd.eigen", 0.0, eig_bytes, s);
+      timer_begin("svd.apply", s);
       hipLaunchKernelGGL(apply_kernel, dim3(npairs, ntile_b + ntile_j, B), dim3(256), 0, s, d, ntile_b);
+      timer_end("svd.apply", apply_flops, apply_bytes, s);
     }
-    TNA_HIP(hipGetLastError());
+    TNA_LAUNCHED("svd.hip:2");
     TNA_HIP(hipMemcpyAsync(host_ctr, wb.ctr.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
     TNA_HIP(hipStreamSynchronize(s));
     if (*host_ctr == 0) {
@@ -677,7 +692,7 @@ tna_status svd_run(const SvdPlan &p, SvdBuffers &wb, const void *A, int64_t stri
   if (sweeps) *sweeps = conv ? sw : max_sweeps;
   hipLaunchKernelGGL(norms_kernel, dim3(ceil_div(p.R, 4), B), dim3(256), 0, s, wb.bw.as<double>(), p.R, p.C,
                      wb.sig.as<double>());
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:3");
   if (!conv) {
     set_error("svd: Jacobi sweep cap reached");
     return TNA_ERR_NOCONV;
@@ -692,13 +707,13 @@ tna_status svd_spectrum(const SvdPlan &p, SvdBuffers &wb, double *S_out, int64_t
   hipLaunchKernelGGL(sort_kernel, dim3(p.batch), dim3(1024), 0, s, wb.sig.as<double>(), p.R, P, wb.perm.as<int>(),
                      S_out, strideS);
   hipLaunchKernelGGL(entropy_kernel, dim3(p.batch), dim3(256), 0, s, S_out, p.R, strideS, spec);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:4");
   return TNA_OK;
 }
 
 tna_status svd_trunc_S(const SvdPlan &p, const double *S, int64_t strideS, int k, double *spec, hipStream_t s) {
   hipLaunchKernelGGL(trunc_kernel, dim3(p.batch), dim3(256), 0, s, S, p.R, k, strideS, spec);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:5");
   return TNA_OK;
 }
 
@@ -723,19 +738,19 @@ tna_status svd_outputs_S(const SvdPlan &p, SvdBuffers &wb, const double *S, int6
     hipLaunchKernelGGL(complete_kernel<float>, dim3(B), dim3(256), 0, s, o);
     hipLaunchKernelGGL(gauge_kernel<float>, dim3(k, B), dim3(256), 0, s, o, scale_mode, spec);
   }
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:6");
   return TNA_OK;
 }
 
 tna_status spectrum_entropy(const double *S, int R, double *spec, int batch, int64_t strideS, hipStream_t s) {
   hipLaunchKernelGGL(entropy_kernel, dim3(batch), dim3(256), 0, s, S, R, strideS, spec);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:7");
   return TNA_OK;
 }
 
 tna_status spectrum_trunc(const double *S, int R, int k, double *spec, int batch, int64_t strideS, hipStream_t s) {
   hipLaunchKernelGGL(trunc_kernel, dim3(batch), dim3(256), 0, s, S, R, k, strideS, spec);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("svd.hip:8");
   return TNA_OK;
 }
 

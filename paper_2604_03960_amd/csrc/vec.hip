@@ -245,6 +245,8 @@ tna_status mix(const MixArgs &a, hipStream_t s) {
   for (int i = 0; i < 32; ++i) { d.ioff[i] = a.ioff[i]; d.ooff[i] = a.ooff[i]; }
   d.in = a.in; d.out = a.out; d.M = a.M;
   dim3 grid((unsigned)((total + NT - 1) / NT));
+  const char *name = a.type_in == G_F64 ? "mix.f64" : "mix.f32";
+  timer_begin(name, s);
   if (a.type_in == G_F64 && a.type_out == G_F64)
     hipLaunchKernelGGL((mix_kernel<double, double>), grid, dim3(NT), 0, s, d);
   else if (a.type_in == G_F32 && a.type_out == G_F32)
@@ -253,14 +255,16 @@ tna_status mix(const MixArgs &a, hipStream_t s) {
     set_error("mix: type combination not built");
     return TNA_ERR_UNSUPPORTED;
   }
-  TNA_HIP(hipGetLastError());
+  const int es = a.type_in == G_F64 ? 8 : 4;
+  timer_end(name, 2.0 * a.I * a.J * (double)total, (double)total * (a.I + a.J) * es, s);
+  TNA_LAUNCHED("vec.hip:1");
   return TNA_OK;
 }
 
 tna_status build_mix_matrix(int mode, int d, int D, const double *W1, const double *W2, double *M, hipStream_t s) {
   int n = (mode == 0) ? (D * d * d) * (D * d * d) : (D * d) * (D * d);
   hipLaunchKernelGGL(build_mix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, mode, d, D, W1, W2, M);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:2");
   return TNA_OK;
 }
 
@@ -268,24 +272,28 @@ tna_status multidot(const double *V, int64_t ldv, int nv, const double *w, int64
                     hipStream_t s) {
   if (nv <= 0) return TNA_OK;
   int G = n_parts(n);
+  timer_begin("vec.multidot", s);
   hipLaunchKernelGGL(multidot_kernel, dim3(G), dim3(NT), 0, s, V, ldv, nv, w, n, part);
+  timer_end("vec.multidot", 2.0 * nv * (double)n, 8.0 * (nv + 1) * (double)n, s);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(nv), dim3(NT), 0, s, part, G, h);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:3");
   return TNA_OK;
 }
 
 tna_status axpy_multi(const double *V, int64_t ldv, int nv, const double *h, double *w, int64_t n, double *nrm2,
                       double *part, hipStream_t s) {
   int G = n_parts(n);
+  timer_begin("vec.axpy", s);
   hipLaunchKernelGGL(axpy_multi_kernel, dim3(G), dim3(NT), 0, s, V, ldv, nv, h, w, n, nrm2 ? part : nullptr);
+  timer_end("vec.axpy", 2.0 * nv * (double)n, 8.0 * (nv + 2) * (double)n, s);
   if (nrm2) hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(NT), 0, s, part, G, nrm2);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:4");
   return TNA_OK;
 }
 
 tna_status combine(const double *V, int64_t ldv, int nv, const double *c, double *y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n)), dim3(NT), 0, s, V, ldv, nv, c, y, n);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:5");
   return TNA_OK;
 }
 
@@ -293,39 +301,39 @@ tna_status norm2(const double *x, int64_t n, double *out, double *part, hipStrea
   int G = n_parts(n);
   hipLaunchKernelGGL(norm2_kernel, dim3(G), dim3(NT), 0, s, x, n, part);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(NT), 0, s, part, G, out);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:6");
   return TNA_OK;
 }
 
 tna_status scale(const double *x, double *y, int64_t n, const double *nrm2, double scal, hipStream_t s) {
   hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(NT), 0, s, x, y, n, nrm2, scal);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:7");
   return TNA_OK;
 }
 
 tna_status check_finite(const double *x, int64_t n, int *flag, hipStream_t s) {
   hipLaunchKernelGGL(finite_kernel, dim3(grid_for(n)), dim3(NT), 0, s, x, n, flag);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:8");
   return TNA_OK;
 }
 
 tna_status convert_f64_f32(const double *x, float *y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(cvt_kernel, dim3(grid_for(n)), dim3(NT), 0, s, x, y, n);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:9");
   return TNA_OK;
 }
 
 tna_status fill(double *x, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return TNA_OK;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(NT), 0, s, x, n, v);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:10");
   return TNA_OK;
 }
 
 tna_status fill_int(int *x, int64_t n, int v, hipStream_t s) {
   if (n <= 0) return TNA_OK;
   hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n)), dim3(NT), 0, s, x, n, v);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:11");
   return TNA_OK;
 }
 
@@ -335,7 +343,7 @@ tna_status copy_transpose(const void *A, int m, int n, int type, double *B, hipS
     hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(NT), 0, s, static_cast<const double *>(A), m, n, B);
   else
     hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(NT), 0, s, static_cast<const float *>(A), m, n, B);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:12");
   return TNA_OK;
 }
 
@@ -343,7 +351,7 @@ tna_status set_identity(double *J, int n, int ld, int batch, int64_t stride, hip
   int64_t total = (int64_t)n * ld;
   dim3 grid((unsigned)grid_for(total), batch);
   hipLaunchKernelGGL(identity_kernel, grid, dim3(NT), 0, s, J, n, ld, stride);
-  TNA_HIP(hipGetLastError());
+  TNA_LAUNCHED("vec.hip:13");
   return TNA_OK;
 }
 
