@@ -143,14 +143,21 @@ typedef struct {
   double eps_target;      /* truncation-error target that is reported (and used by schedulers) */
 } tna_dmrg_opts;
 
-/* One record per bond visit (host). */
+/* One record per bond visit (host).  k_needed: smallest rank whose
+ * truncation error meets opts.eps_target on this visit's spectrum;
+ * chi_sched: the learned scheduler's proposal (0 if none); fallback: 1 when
+ * the proposal would have missed eps_target and the controller's chi was
+ * used; feat: the scheduler's 25 inputs for this visit. */
 typedef struct {
   int sweep, dir, bond, m, n, k, chi_ctrl, lanczos_iters, svd_sweeps, lanczos_ok;
   double E, S, S_ema, eps, wdisc, gap, P, I, D, u, sigma0, sigma_last;
   double ms_lanczos, ms_svd, ms_other;
+  int k_needed, chi_sched, fallback, pad;
+  float feat[25];
 } tna_visit_log;
 
 typedef struct tna_dmrg_s *tna_dmrg;
+typedef struct tna_mlp_s *tna_mlp;
 
 /* Device-resident two-site DMRG (Sec. 10) with one controller per bond.
  * W_host: N MPO tensors (N, D, D, d, d).  A_host: the initial MPS packed site
@@ -174,6 +181,39 @@ tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid);
 tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t *count);
 void tna_dmrg_destroy(tna_dmrg dm);
 
+/* ---------------------------------------------------------------- many chains */
+/* Independent chains (own N, MPO, initial MPS) swept together: all chains
+ * advance one bond visit per step and every stage of the visit is one grouped
+ * launch over the chains (persistent grouped GEMM over a tile work list,
+ * grouped mixing and Lanczos vector kernels, one group of Jacobi SVDs of
+ * different shapes); the launch sequence of a Lanczos iteration is captured
+ * as a HIP graph once per step and replayed.  Controllers, Lanczos options
+ * and precision as for tna_dmrg_create (pid and opts are shared by all
+ * chains; opts.heff_prec F32 runs the H_eff contractions in FP32).  The work
+ * runs on a stream the batch owns (default priority).  Synchronises. */
+typedef struct tna_dmrg_batch_s *tna_dmrg_batch;
+typedef struct {
+  double ms_total, ms_lanczos, ms_svd, ms_env;
+  long lanczos_iters, graph_launches;
+  int autotune_entries, steps;
+} tna_batch_stats;
+tna_status tna_dmrg_batch_create(tna_ctx ctx, int nchains, const int *N, int d, int D, const double *const *W_host,
+                                 const double *const *A_host, const int *const *chi_init, const tna_pid_params *pid,
+                                 const tna_dmrg_opts *opts, tna_dmrg_batch *out);
+/* One sweep of every chain.  E_out (host, nchains): last Ritz value per
+ * chain.  logs (host, may be NULL): records of chain c start at
+ * log_offsets[c] (2*(N_c-1) records each).  stats (host, may be NULL). */
+tna_status tna_dmrg_batch_sweep(tna_dmrg_batch b, double *E_out, tna_visit_log *logs, const int64_t *log_offsets,
+                                tna_batch_stats *stats);
+tna_status tna_dmrg_batch_get_state(tna_dmrg_batch b, int chain, int *chi, tna_pid_state *pid);
+void tna_dmrg_batch_destroy(tna_dmrg_batch b);
+/* GEMM tile autotuner of the grouped launches: the table maps (operation,
+ * log2 flops) to the faster of the 64x64 and 128x128 tiles, measured the
+ * first time a bucket is met; it can be saved and reloaded (text). */
+tna_status tna_autotune_save(const char *path);
+tna_status tna_autotune_load(const char *path);
+int tna_autotune_entries(void);
+
 /* ---------------------------------------------------------------- learned scheduler */
 /* A 25 -> 64 -> 64 -> 1 perceptron (tanh hidden units, linear output), the
  * learned stand-in for the predictive scheduler of Sec. 7, trained and run
@@ -184,7 +224,6 @@ void tna_dmrg_destroy(tna_dmrg dm);
  * visit.  Parameter layout (5889 floats): W1[64][25] b1[64] W2[64][64] b2[64]
  * W3[64] b3.  Inputs are standardised by (x - mean)/std when a normalisation
  * is set. */
-typedef struct tna_mlp_s *tna_mlp;
 #define TNA_MLP_IN 25
 #define TNA_MLP_NPARAM 5889
 /* params_host: initial parameters (host, 5889 floats; the caller draws them). */
@@ -205,6 +244,12 @@ tna_status tna_mlp_adam_step(tna_mlp n, const float *grad, float lr);
 tna_status tna_mlp_train(tna_mlp n, int nsamp, const float *X, const float *T, const int *perm, int epochs,
                          int batch, float lr, float *loss_per_epoch);
 void tna_mlp_destroy(tna_mlp n);
+/* Attaches a trained network to a DMRG run (NULL detaches).  From each bond's
+ * second visit on, the bond keeps k = clamp(round(2^y), chi_min, chi_max)
+ * predicted at its previous visit, unless that k would leave a truncation
+ * error above opts.eps_target, in which case the controller's chi is used
+ * (fallback).  The controller keeps running either way. */
+tna_status tna_dmrg_set_scheduler(tna_dmrg dm, tna_mlp net);
 
 #ifdef __cplusplus
 }

@@ -59,7 +59,14 @@ class VisitLog(C.Structure):
     _fields_ = [(n, C.c_int) for n in ("sweep", "dir", "bond", "m", "n", "k", "chi_ctrl", "lanczos_iters",
                                        "svd_sweeps", "lanczos_ok")] + \
                [(n, C.c_double) for n in ("E", "S", "S_ema", "eps", "wdisc", "gap", "P", "I", "D", "u", "sigma0",
-                                          "sigma_last", "ms_lanczos", "ms_svd", "ms_other")]
+                                          "sigma_last", "ms_lanczos", "ms_svd", "ms_other")] + \
+               [(n, C.c_int) for n in ("k_needed", "chi_sched", "fallback", "pad")] + [("feat", C.c_float * 25)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("ms_total", C.c_double), ("ms_lanczos", C.c_double), ("ms_svd", C.c_double), ("ms_env", C.c_double),
+                ("lanczos_iters", C.c_long), ("graph_launches", C.c_long), ("autotune_entries", C.c_int),
+                ("steps", C.c_int)]
 
 
 _vp, _dp, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
@@ -91,6 +98,15 @@ _SIGS = {
     "tna_mlp_adam_step": ([_vp, _vp, C.c_float], C.c_int),
     "tna_mlp_train": ([_vp, C.c_int, _vp, _vp, _vp, C.c_int, C.c_int, C.c_float, _vp], C.c_int),
     "tna_mlp_destroy": ([_vp], None),
+    "tna_dmrg_set_scheduler": ([_vp, _vp], C.c_int),
+    "tna_dmrg_batch_create": ([_vp, C.c_int, _ip, C.c_int, C.c_int, C.POINTER(_dp), C.POINTER(_dp), C.POINTER(_ip),
+                               C.POINTER(PidParams), C.POINTER(DmrgOpts), C.POINTER(C.c_void_p)], C.c_int),
+    "tna_dmrg_batch_sweep": ([_vp, _dp, C.POINTER(VisitLog), C.POINTER(C.c_int64), C.POINTER(BatchStats)], C.c_int),
+    "tna_dmrg_batch_get_state": ([_vp, C.c_int, _ip, C.POINTER(PidState)], C.c_int),
+    "tna_dmrg_batch_destroy": ([_vp], None),
+    "tna_autotune_save": ([C.c_char_p], C.c_int),
+    "tna_autotune_load": ([C.c_char_p], C.c_int),
+    "tna_autotune_entries": ([], C.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -257,8 +273,17 @@ class Dmrg:
         logs = (VisitLog * n)()
         E = C.c_double(0.0)
         st = _check(_lib.tna_dmrg_sweep(self.h, C.byref(E), logs), allow=(TNA_ERR_NOCONV,))
-        recs = [{f: getattr(r, f) for f, _ in VisitLog._fields_} for r in logs]
+        recs = []
+        for r in logs:
+            d = {f: getattr(r, f) for f, _ in VisitLog._fields_ if f != "feat"}
+            d["feat"] = np.array(r.feat[:], dtype=np.float32)
+            recs.append(d)
         return E.value, recs, st
+
+    def set_scheduler(self, net):
+        """Attach a trained Mlp (None detaches); keeps a reference for the run's lifetime."""
+        self._sched = net
+        _check(_lib.tna_dmrg_set_scheduler(self.h, net.h if net is not None else None))
 
     def state(self):
         chi = np.zeros(self.N - 1, dtype=np.int32)
@@ -346,3 +371,76 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ many chains
+class DmrgBatch:
+    """Independent chains swept together through grouped launches."""
+
+    def __init__(self, ctx: Context, Ws, As, chis, pid: PidParams, lanczos_tol=1e-12, lanczos_kmax=100,
+                 lanczos_restarts=5, heff_prec=HEFF_F64, fixed_chi=0, svd_max_sweeps=60, eps_target=1e-8):
+        n = len(Ws)
+        self.Ws = [np.ascontiguousarray(w, dtype=np.float64) for w in Ws]
+        self.As = [np.ascontiguousarray(a, dtype=np.float64) for a in As]
+        self.chis = [np.ascontiguousarray(c, dtype=np.int32) for c in chis]
+        self.N = np.array([w.shape[0] for w in self.Ws], dtype=np.int32)
+        D, d = self.Ws[0].shape[1], self.Ws[0].shape[3]
+        Wp = (_dp * n)(*[w.ctypes.data_as(_dp) for w in self.Ws])
+        Ap = (_dp * n)(*[a.ctypes.data_as(_dp) for a in self.As])
+        Cp = (_ip * n)(*[c.ctypes.data_as(_ip) for c in self.chis])
+        self.opts = DmrgOpts(lanczos_tol, lanczos_kmax, lanczos_restarts, 0, heff_prec, fixed_chi, svd_max_sweeps,
+                             eps_target)
+        self.pid = pid
+        h = C.c_void_p()
+        _check(_lib.tna_dmrg_batch_create(ctx.h, n, self.N.ctypes.data_as(_ip), d, D, Wp, Ap, Cp, C.byref(pid),
+                                          C.byref(self.opts), C.byref(h)))
+        self.h, self.n = h, n
+        self.offsets = np.concatenate([[0], np.cumsum(2 * (self.N - 1))]).astype(np.int64)
+
+    def sweep(self):
+        """One sweep of every chain: (E per chain, per-chain lists of visit dicts, stats dict, status)."""
+        total = int(self.offsets[-1])
+        logs = (VisitLog * total)()
+        E = np.zeros(self.n)
+        stats = BatchStats()
+        off = self.offsets[:-1].copy()
+        st = _check(_lib.tna_dmrg_batch_sweep(self.h, E.ctypes.data_as(_dp), logs,
+                                              off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(stats)),
+                    allow=(TNA_ERR_NOCONV,))
+        per = []
+        for c in range(self.n):
+            recs = []
+            for r in logs[int(self.offsets[c]):int(self.offsets[c + 1])]:
+                d = {f: getattr(r, f) for f, _ in VisitLog._fields_ if f != "feat"}
+                recs.append(d)
+            per.append(recs)
+        return E, per, {f: getattr(stats, f) for f, _ in BatchStats._fields_}, st
+
+    def state(self, chain):
+        chi = np.zeros(self.N[chain] - 1, dtype=np.int32)
+        pid = (PidState * int(self.N[chain] - 1))()
+        _check(_lib.tna_dmrg_batch_get_state(self.h, chain, chi.ctypes.data_as(_ip), pid))
+        return chi, list(pid)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tna_dmrg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_save(path: str):
+    _check(_lib.tna_autotune_save(path.encode()))
+
+
+def autotune_load(path: str):
+    _check(_lib.tna_autotune_load(path.encode()))
+
+
+def autotune_entries() -> int:
+    return _lib.tna_autotune_entries()

@@ -13,14 +13,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtna.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "mlp.hip", "api.cpp", "dmrg.cpp"]
+SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "mlp.hip", "batch.hip", "api.cpp", "dmrg.cpp", "batch.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=fast",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
     cmd = ["hipcc", *FLAGS, *lang, "-c", os.path.join(SRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

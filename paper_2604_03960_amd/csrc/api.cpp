@@ -218,7 +218,7 @@ tna_status env_right(int k, int chr, int d, int D, const double *R, const double
 // Lowest eigenvalue of the symmetric tridiagonal (a, b) by Sturm-count
 // bisection, eigenvector by two steps of inverse iteration (Gaussian
 // elimination with partial pivoting on T - lambda I).
-static double tridiag_lowest(int n, const double *a, const double *b, double *y) {
+double tridiag_lowest_host(int n, const double *a, const double *b, double *y) {
   if (n == 1) {
     y[0] = 1.0;
     return a[0];
@@ -338,7 +338,7 @@ static tna_status lanczos(tna_ctx c, const HeffOp &op, int64_t n, double *theta,
         return TNA_ERR_NONFINITE;
       }
       const int nn = j + 1;
-      E = tridiag_lowest(nn, al.data(), be.data(), y.data());
+      E = tridiag_lowest_host(nn, al.data(), be.data(), y.data());
       const double resid = std::fabs(be[j] * y[j]);
       nkeep = nn;
       if (fixed_iters > 0) {
@@ -485,10 +485,8 @@ void tna_destroy(tna_ctx c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (DevBuf *b : {&c->x, &c->z, &c->lf, &c->rf, &c->m12, &c->part, &c->misc}) b->release();
-  for (DevBuf *b : {&c->svd.bw, &c->svd.jt, &c->svd.gram, &c->svd.qt, &c->svd.flags, &c->svd.sig, &c->svd.perm,
-                    &c->svd.ctr, &c->svd.scratch})
-    b->release();
+  for (DevBuf *b : {&c->x, &c->z, &c->lf, &c->rf, &c->m12, &c->part, &c->misc, &c->spec}) b->release();
+  c->svd.release();
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   delete c;
@@ -650,22 +648,41 @@ static tna_status svd_common(tna_ctx c, int batch, int m, int n, int dtype, cons
     set_error("svd_truncate: bad dtype");
     return TNA_ERR_ARG;
   }
-  if (chi_keep < 1) {
-    set_error("svd_truncate: chi_keep must be >= 1");
+  if (chi_keep < 1 || batch < 1) {
+    set_error("svd_truncate: chi_keep and batch must be >= 1");
     return TNA_ERR_ARG;
   }
-  SvdPlan p;
-  TNA_TRY(svd_plan(batch, m, n, dtype, &p));
-  const int k = std::min(chi_keep, p.R);
+  SvdMat proto;
+  TNA_TRY(svd_plan_mat(m, n, dtype, batch, &proto));
+  const int k = std::min(chi_keep, proto.R);
+  const size_t nd = svd_work_doubles(proto), ni = svd_work_ints(proto);
+  TNA_TRY(c->svd.work_d.ensure(sizeof(double) * nd * batch));
+  TNA_TRY(c->svd.work_i.ensure(sizeof(int) * ni * batch));
+  TNA_TRY(c->spec.ensure(sizeof(double) * 24 * batch));
+  const size_t el = dtype == TNA_F64 ? sizeof(double) : sizeof(float);
+  std::vector<SvdMat> mats(batch, proto);
+  for (int z = 0; z < batch; ++z) {
+    SvdMat &a = mats[z];
+    svd_bind_work(&a, c->svd.work_d.as<double>() + nd * z, c->svd.work_i.as<int>() + ni * z);
+    a.A = static_cast<const char *>(A) + el * strideA * z;
+    a.S = S + strideS * z;
+    a.spec = c->spec.as<double>() + 24 * z;
+    a.U = static_cast<char *>(U) + el * strideU * z;
+    a.Vt = static_cast<char *>(Vt) + el * strideVt * z;
+    a.k = k;
+    a.out_type = dtype;
+    a.scale_mode = 0;
+    a.eps_target = 0.0;
+  }
   hipStream_t s = c->stream;
-  int sweeps = 0;
-  tna_status st = svd_run(p, c->svd, A, strideA, 60, &sweeps, s, c->host_ctr);
+  std::vector<int> sweeps;
+  tna_status st = svd_group_run(mats, c->svd, 60, sweeps, s);
   if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
-  TNA_TRY(svd_spectrum(p, c->svd, S, strideS, spec, s));
-  TNA_TRY(svd_trunc_S(p, S, strideS, k, spec, s));
-  TNA_TRY(svd_outputs_S(p, c->svd, S, strideS, k, U, strideU, Vt, strideVt, dtype, 0, spec, s));
+  TNA_TRY(svd_group_outputs(mats, c->svd, s));
+  TNA_HIP(hipMemcpy2DAsync(spec, 6 * sizeof(double), c->spec.ptr, 24 * sizeof(double), 6 * sizeof(double), batch,
+                           hipMemcpyDeviceToDevice, s));
   if (k_out) *k_out = k;
-  if (sweeps_out) *sweeps_out = sweeps;
+  if (sweeps_out) *sweeps_out = sweeps.empty() ? 0 : *std::max_element(sweeps.begin(), sweeps.end());
   return st;
 }
 

@@ -1,0 +1,271 @@
+// Grouped kernels of the batched-chain sweep: many independent chains, each
+// at its own bond and with its own bond dimensions, advance through one set
+// of launches per step.  One grid y-slice per chain; a chain whose device
+// `active` flag is zero (converged, or finished with its sweep) returns at
+// once.  Each chain's Lanczos iteration index j lives in device memory, so the
+// launch sequence of one iteration does not change from one iteration to the
+// next and is captured once per sweep step as a HIP graph.
+#include "internal.h"
+
+namespace tna {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ mixing
+template <typename T>
+__global__ __launch_bounds__(NT) void mix_grouped_kernel(const MixProb *probs, int I1, int I2, int J1, int J2) {
+  const MixProb &p = probs[blockIdx.y];
+  if (p.active && !*p.active) return;
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t total = (int64_t)p.n0 * p.n1;
+  if (idx >= total) return;
+  const int64_t o0 = idx / p.n1, o1 = idx - o0 * p.n1;
+  const T *in = static_cast<const T *>(p.in) + o0 * p.is0 + o1 * p.is1;
+  T *out = static_cast<T *>(p.out) + o0 * p.os0 + o1 * p.os1;
+  const int I = I1 * I2, J = J1 * J2;
+  T x[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) x[i] = (i < I) ? in[(i / I2) * p.ich1 + (i % I2) * p.ich2] : T(0);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    if (j < J) {
+      T acc = T(0);
+      const double *Mj = p.M + j * I;
+#pragma unroll
+      for (int i = 0; i < 32; ++i)
+        if (i < I) acc += (T)Mj[i] * x[i];
+      out[(j / J2) * p.och1 + (j % J2) * p.och2] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Lanczos
+// h[i] partials of <V_i, w> for i <= j, w = V_{j+1}; grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int which) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const int nv = *p.j + 1;
+  const double *V = p.V, *w = p.V + (int64_t)nv * p.n;
+  const int64_t chunk = (p.n + p.G - 1) / p.G;
+  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  double *part = which ? p.part2 : p.part1;
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+      const double wv = w[e];
+#pragma unroll
+      for (int g = 0; g < 8; ++g)
+        if (i0 + g < nv) acc[g] += V[(int64_t)(i0 + g) * p.n + e] * wv;
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      if (i0 + g < nv) {
+        const double r = block_sum(acc[g], sh);
+        if (threadIdx.x == 0) part[(int64_t)(i0 + g) * p.G + blockIdx.x] = r;
+      }
+    }
+  }
+}
+
+// h[i] = sum_b part[i][b]; grid (kmax+1, chains)
+__global__ __launch_bounds__(NT) void lz_reduce_kernel(const LzProb *probs, int which) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  const int i = blockIdx.x;
+  if (!*p.active || i > *p.j) return;
+  const double *part = which ? p.part2 : p.part1;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < p.G; b += NT) v += part[(int64_t)i * p.G + b];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) (which ? p.h2 : p.h1)[i] = v;
+}
+
+// w -= sum_{i<=j} h[i] V_i; with norm: partial |w|^2 into part1[b]; grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int which, int with_norm) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const int nv = *p.j + 1;
+  const double *h = which ? p.h2 : p.h1;
+  double *w = p.V + (int64_t)nv * p.n;
+  const int64_t chunk = (p.n + p.G - 1) / p.G;
+  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  double loc = 0.0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+    double acc = 0.0;
+    for (int i = 0; i < nv; ++i) acc += h[i] * p.V[(int64_t)i * p.n + e];
+    const double v = w[e] - acc;
+    w[e] = v;
+    loc += v * v;
+  }
+  if (with_norm) {
+    const double r = block_sum(loc, sh);
+    if (threadIdx.x == 0) p.part1[blockIdx.x] = r;
+  }
+}
+
+// beta^2 = sum of the norm partials; records alpha_j, beta_j^2; grid (1, chains)
+__global__ __launch_bounds__(NT) void lz_record_kernel(const LzProb *probs) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < p.G; b += NT) v += p.part1[b];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    const int j = *p.j;
+    *p.nrm2 = v;
+    p.rec[0] = p.h1[j];  // alpha_j
+    p.rec[1] = v;        // beta_j^2
+  }
+}
+
+// V_{j+1} /= beta_j (if beta_j is not negligible); grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_normalize_kernel(const LzProb *probs) {
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const double b2 = *p.nrm2;
+  if (!(b2 > 1e-28)) return;
+  const double f = 1.0 / sqrt(b2);
+  double *w = p.V + (int64_t)(*p.j + 1) * p.n;
+  const int64_t chunk = (p.n + p.G - 1) / p.G;
+  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  for (int64_t e = beg + threadIdx.x; e < end; e += NT) w[e] *= f;
+}
+
+__global__ void lz_advance_kernel(const LzProb *probs, int nch) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nch && *probs[c].active) *probs[c].j += 1;
+}
+
+// Normalisation of theta; grid (G, chains) or (1, chains) for mode 1.
+// mode 0: partials of |theta|^2 into part1; mode 1: reduce into nrm2;
+// mode 2: V_0 = theta / |theta|; mode 3: theta /= |theta|.
+__global__ __launch_bounds__(NT) void lz_norm_kernel(const LzProb *probs, int mode, int src_theta) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active) return;
+  const double *src = src_theta ? p.theta : p.V;
+  if (mode == 1) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < p.G; b += NT) v += p.part1[b];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) *p.nrm2 = v;
+    return;
+  }
+  if (mode == 3) {  // theta /= |theta| in place
+    if ((int)blockIdx.x >= p.G) return;
+    const double f = 1.0 / sqrt(*p.nrm2);
+    const int64_t chunk = (p.n + p.G - 1) / p.G;
+    const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+    for (int64_t e = beg + threadIdx.x; e < end; e += NT) p.theta[e] *= f;
+    return;
+  }
+  if ((int)blockIdx.x >= p.G) return;
+  const int64_t chunk = (p.n + p.G - 1) / p.G;
+  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  if (mode == 0) {
+    double loc = 0.0;
+    for (int64_t e = beg + threadIdx.x; e < end; e += NT) loc += src[e] * src[e];
+    const double r = block_sum(loc, sh);
+    if (threadIdx.x == 0) p.part1[blockIdx.x] = r;
+  } else {
+    const double f = 1.0 / sqrt(*p.nrm2);  // mode 2: V_0 = theta / |theta|
+    for (int64_t e = beg + threadIdx.x; e < end; e += NT) p.V[e] = src[e] * f;
+  }
+}
+
+// theta = sum_{i < nkeep} y_i V_i (the Ritz vector, unnormalised); grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_combine_kernel(const LzProb *probs) {
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const int nv = p.nkeep;
+  const int64_t chunk = (p.n + p.G - 1) / p.G;
+  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+    double acc = 0.0;
+    for (int i = 0; i < nv; ++i) acc += p.y[i] * p.V[(int64_t)i * p.n + e];
+    p.theta[e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(NT) void convert_grouped_kernel(const CvtProb *probs) {
+  const CvtProb &p = probs[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < p.n; e += (int64_t)gridDim.x * NT) p.dst[e] = (float)p.src[e];
+}
+
+}  // namespace
+
+tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, int I2, int J1, int J2, int f32,
+                       hipStream_t s) {
+  if (nprob < 1 || max_elems < 1) return TNA_OK;
+  if (I1 * I2 > 32 || J1 * J2 > 32) {
+    set_error("mix_grouped: at most 32 channels");
+    return TNA_ERR_ARG;
+  }
+  dim3 grid((unsigned)((max_elems + NT - 1) / NT), nprob);
+  if (f32) hipLaunchKernelGGL(mix_grouped_kernel<float>, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
+  else hipLaunchKernelGGL(mix_grouped_kernel<double>, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
+  TNA_LAUNCHED("mix.grouped");
+  return TNA_OK;
+}
+
+tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, hipStream_t s) {
+  const dim3 g(maxG, nch), r(kmax + 1, nch), one(1, nch);
+  hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, 0);
+  hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, 0);
+  hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, 0, 0);
+  hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, 1);
+  hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, 1);
+  hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, 1, 1);
+  hipLaunchKernelGGL(lz_record_kernel, one, dim3(NT), 0, s, d);
+  hipLaunchKernelGGL(lz_normalize_kernel, g, dim3(NT), 0, s, d);
+  hipLaunchKernelGGL(lz_advance_kernel, dim3((nch + 63) / 64), dim3(64), 0, s, d, nch);
+  TNA_LAUNCHED("lanczos.grouped");
+  return TNA_OK;
+}
+
+tna_status lz_start(const LzProb *d, int nch, int maxG, hipStream_t s) {
+  // V_0 = theta / |theta|
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 0, 1);
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(1, nch), dim3(NT), 0, s, d, 1, 1);
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 2, 1);
+  TNA_LAUNCHED("lanczos.start");
+  return TNA_OK;
+}
+
+tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s) {
+  // theta = sum y_i V_i, then normalised in place
+  hipLaunchKernelGGL(lz_combine_kernel, dim3(maxG, nch), dim3(NT), 0, s, d);
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 0, 1);
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(1, nch), dim3(NT), 0, s, d, 1, 1);
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 3, 1);
+  TNA_LAUNCHED("lanczos.ritz");
+  return TNA_OK;
+}
+
+tna_status convert_grouped(const CvtProb *d, int nprob, hipStream_t s) {
+  if (nprob < 1) return TNA_OK;
+  hipLaunchKernelGGL(convert_grouped_kernel, dim3(64, nprob), dim3(NT), 0, s, d);
+  TNA_LAUNCHED("convert.grouped");
+  return TNA_OK;
+}
+
+}  // namespace tna

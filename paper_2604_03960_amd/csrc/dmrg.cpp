@@ -5,6 +5,7 @@
 // entropy of the two-site spectrum.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,22 +15,6 @@
 #include "internal.h"
 
 using namespace tna;
-
-struct tna_dmrg_s {
-  tna_ctx ctx;
-  int N, d, D;
-  tna_pid_params pid;
-  tna_dmrg_opts opts;
-  std::vector<int> chi;            // N-1 realised bond dims
-  std::vector<tna_pid_state> st;   // N-1 controllers
-  std::vector<DevBuf> A, Le, Re;   // site tensors, left envs (site i), right envs (site i)
-  DevBuf W, M12, Ml, Mr;           // MPO tensors and mixing matrices (device)
-  DevBuf V, T1, T2, spec, S;       // Lanczos basis, env scratch, spectrum
-  int sweeps_done = 0;
-  double *host_stage = nullptr;    // pinned: per-visit readbacks
-  int CL(int i) const { return i == 0 ? 1 : chi[i - 1]; }
-  int CR(int i) const { return i == N - 1 ? 1 : chi[i]; }
-};
 
 static tna_status check_dmrg_args(int N, int d, int D, const double *W, const double *A, const int *chi,
                                   const tna_pid_params *pid) {
@@ -55,25 +40,38 @@ static tna_status check_dmrg_args(int N, int d, int D, const double *W, const do
   return TNA_OK;
 }
 
-static tna_status svd_into(tna_dmrg dm, int m, int n, const double *src, int k_req, void *U, void *Vt,
-                           int scale_mode, int *k_out, double *entropy_host, int *sweeps, bool need_entropy) {
-  (void)entropy_host;
-  (void)need_entropy;
+// Runs the Jacobi SVD of the m x n matrix src and sorts its spectrum into
+// dm->S; *mat keeps the plan and work bindings for svd_finish.
+static tna_status svd_start(tna_dmrg dm, int m, int n, const double *src, SvdMat *mat, int *sweeps) {
   tna_ctx c = dm->ctx;
-  SvdPlan p;
-  TNA_TRY(svd_plan(1, m, n, TNA_F64, &p));
-  TNA_TRY(dm->S.ensure(sizeof(double) * p.R));
-  int sw = 0;
-  tna_status st = svd_run(p, c->svd, src, (int64_t)m * n, dm->opts.svd_max_sweeps, &sw, c->stream, c->host_ctr);
-  if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
-  TNA_TRY(svd_spectrum(p, c->svd, dm->S.as<double>(), p.R, dm->spec.as<double>(), c->stream));
-  const int k = std::min(k_req, p.R);
-  TNA_TRY(svd_trunc_S(p, dm->S.as<double>(), p.R, k, dm->spec.as<double>(), c->stream));
-  TNA_TRY(svd_outputs_S(p, c->svd, dm->S.as<double>(), p.R, k, U, (int64_t)m * k, Vt, (int64_t)k * n, TNA_F64,
-                        scale_mode, dm->spec.as<double>(), c->stream));
-  if (k_out) *k_out = k;
-  if (sweeps) *sweeps = sw;
-  return st == TNA_ERR_NOCONV ? TNA_ERR_NOCONV : TNA_OK;
+  SvdMat a;
+  TNA_TRY(svd_plan_mat(m, n, TNA_F64, 1, &a));
+  const size_t nd = svd_work_doubles(a), ni = svd_work_ints(a);
+  TNA_TRY(c->svd.work_d.ensure(sizeof(double) * nd));
+  TNA_TRY(c->svd.work_i.ensure(sizeof(int) * ni));
+  TNA_TRY(dm->S.ensure(sizeof(double) * a.R));
+  svd_bind_work(&a, c->svd.work_d.as<double>(), c->svd.work_i.as<int>());
+  a.A = src;
+  a.S = dm->S.as<double>();
+  a.spec = dm->spec.as<double>();
+  a.eps_target = dm->opts.eps_target > 0 ? dm->opts.eps_target : 1e-8;
+  a.out_type = TNA_F64;
+  std::vector<SvdMat> mats{a};
+  std::vector<int> sw;
+  tna_status st = svd_group_run(mats, c->svd, dm->opts.svd_max_sweeps, sw, c->stream);
+  *mat = mats[0];
+  if (sweeps) *sweeps = sw.empty() ? 0 : sw[0];
+  return st;
+}
+
+// Writes the kept k vectors into U (m x k) and Vt (k x n) with scale_mode.
+static tna_status svd_finish(tna_dmrg dm, SvdMat mat, int k, void *U, void *Vt, int scale_mode) {
+  mat.k = k;
+  mat.U = U;
+  mat.Vt = Vt;
+  mat.scale_mode = scale_mode;
+  std::vector<SvdMat> mats{mat};
+  return svd_group_outputs(mats, dm->ctx->svd, dm->ctx->stream);
 }
 
 extern "C" {
@@ -107,6 +105,12 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
   dm->Re.resize(N);
   hipStream_t s = c->stream;
   TNA_HIP(hipHostMalloc((void **)&dm->host_stage, sizeof(double) * 64, hipHostMallocDefault));
+  TNA_HIP(hipHostMalloc((void **)&dm->host_feat, sizeof(float) * 32, hipHostMallocDefault));
+  dm->hist.assign(N - 1, std::array<double, 8>{});
+  dm->nhist.assign(N - 1, 0);
+  dm->pred.assign(N - 1, 0);
+  TNA_TRY(dm->feat_d.ensure(sizeof(float) * 32));
+  TNA_TRY(dm->y_d.ensure(sizeof(float) * 4));
   // MPO and mixing matrices
   const size_t wsz = (size_t)D * D * d * d;
   TNA_TRY(dm->W.ensure(sizeof(double) * wsz * N));
@@ -130,7 +134,7 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
     TNA_HIP(hipMemcpy(dm->A[i].ptr, A_host + off, sizeof(double) * n, hipMemcpyHostToDevice));
     off += n;
   }
-  TNA_TRY(dm->spec.ensure(sizeof(double) * 8));
+  TNA_TRY(dm->spec.ensure(sizeof(double) * 24));
   // right-canonicalise on the device: A_b = U S Vt -> A_b <- Vt, A_{b-1} <- A_{b-1} U S
   DevBuf Ub, Vb, Tb;
   for (int b = N - 1; b >= 1; --b) {
@@ -138,9 +142,12 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
     const int R = std::min(m, n);
     TNA_TRY(Ub.ensure(sizeof(double) * m * R));
     TNA_TRY(Vb.ensure(sizeof(double) * R * n));
-    int k = 0, sw = 0;
-    tna_status st = svd_into(dm.get(), m, n, dm->A[b].as<double>(), R, Ub.ptr, Vb.ptr, 2, &k, nullptr, &sw, false);
+    int sw = 0;
+    SvdMat mat;
+    tna_status st = svd_start(dm.get(), m, n, dm->A[b].as<double>(), &mat, &sw);
     if (st != TNA_OK) return st;
+    const int k = R;
+    TNA_TRY(svd_finish(dm.get(), mat, k, Ub.ptr, Vb.ptr, 2));
     const int ml = dm->CL(b - 1) * d;
     TNA_TRY(Tb.ensure(sizeof(double) * ml * k));
     GemmArgs g{};
@@ -222,29 +229,61 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
       if (st != TNA_OK) return st;
       if (!lr.converged && worst == TNA_OK) worst = TNA_ERR_NOCONV;
       auto t1 = std::chrono::steady_clock::now();
-      // SVD of theta and entropy of the full spectrum
-      SvdPlan p;
-      TNA_TRY(svd_plan(1, m, n, TNA_F64, &p));
-      TNA_TRY(dm->S.ensure(sizeof(double) * p.R));
+      // SVD of theta, entropy of the full spectrum, needed rank, leading values
       int sw = 0;
-      st = svd_run(p, c->svd, theta, nv, dm->opts.svd_max_sweeps, &sw, s, c->host_ctr);
+      SvdMat mat;
+      st = svd_start(dm, m, n, theta, &mat, &sw);
       if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
       if (st == TNA_ERR_NOCONV && worst == TNA_OK) worst = TNA_ERR_NOCONV;
+      const int Rk = mat.R;
       double *spec = dm->spec.as<double>();
-      TNA_TRY(svd_spectrum(p, c->svd, dm->S.as<double>(), p.R, spec, s));
-      TNA_HIP(hipMemcpyAsync(dm->host_stage, spec, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      TNA_HIP(hipMemcpyAsync(dm->host_stage, spec, sizeof(double) * 24, hipMemcpyDeviceToHost, s));
       TNA_HIP(hipStreamSynchronize(s));
       const double S_ent = dm->host_stage[1];
+      const int k_needed = (int)dm->host_stage[6];
       double terms[6];
       int chi_next = 0;
       TNA_TRY(pid_update(&dm->pid, &dm->st[b], S_ent, &chi_next, terms));
-      const int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next;
-      const int k = std::min(keep, p.R);
-      TNA_TRY(svd_trunc_S(p, dm->S.as<double>(), p.R, k, spec, s));
+      // scheduler inputs: EMA history (oldest first, padded with the oldest),
+      // 16 largest log sigma (floored at ln 1e-16), relative bond position
+      {
+        auto &hb = dm->hist[b];
+        if (dm->nhist[b] < 8) hb[dm->nhist[b]++] = terms[4];
+        else {
+          for (int q = 0; q < 7; ++q) hb[q] = hb[q + 1];
+          hb[7] = terms[4];
+        }
+        const int nh = dm->nhist[b];
+        float *f = dm->host_feat;
+        for (int q = 0; q < 8; ++q) f[q] = (float)hb[q < 8 - nh ? 0 : q - (8 - nh)];
+        const double floor_ln = std::log(1e-16);
+        for (int q = 0; q < 16; ++q) {
+          const double sv = dm->host_stage[8 + q];
+          f[8 + q] = (float)(sv > 0 ? std::max(std::log(sv), floor_ln) : floor_ln);
+        }
+        f[24] = (float)((b + 1.0) / N);
+      }
+      int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next;
+      int chi_sched = 0, fallback = 0;
+      if (dm->sched && dm->opts.fixed_chi <= 0 && dm->pred[b] > 0) {
+        chi_sched = dm->pred[b];
+        if (std::min(chi_sched, Rk) < std::min(k_needed, Rk)) fallback = 1;  // would miss eps_target
+        else keep = chi_sched;
+      }
+      if (dm->sched) {  // proposal for this bond's next visit
+        TNA_HIP(hipMemcpyAsync(dm->feat_d.ptr, dm->host_feat, sizeof(float) * 25, hipMemcpyHostToDevice, s));
+        TNA_TRY(mlp_forward_dev(dm->sched, 1, dm->feat_d.as<float>(), dm->y_d.as<float>()));
+        TNA_HIP(hipMemcpyAsync(dm->host_feat + 28, dm->y_d.ptr, sizeof(float), hipMemcpyDeviceToHost, s));
+        TNA_HIP(hipStreamSynchronize(s));
+        const double yv = dm->host_feat[28];
+        double kp = std::isfinite(yv) ? std::nearbyint(std::exp2(std::min(yv, 30.0))) : dm->pid.chi_min;
+        kp = std::min<double>(std::max<double>(kp, dm->pid.chi_min), dm->pid.chi_max);
+        dm->pred[b] = (int)kp;
+      }
+      const int k = std::min(keep, Rk);
       TNA_TRY(dm->A[b].ensure(sizeof(double) * (size_t)m * k));
       TNA_TRY(dm->A[b + 1].ensure(sizeof(double) * (size_t)k * n));
-      TNA_TRY(svd_outputs_S(p, c->svd, dm->S.as<double>(), p.R, k, dm->A[b].ptr, 0, dm->A[b + 1].ptr, 0, TNA_F64,
-                            half == 0 ? 1 : 2, spec, s));
+      TNA_TRY(svd_finish(dm, mat, k, dm->A[b].ptr, dm->A[b + 1].ptr, half == 0 ? 1 : 2));
       dm->chi[b] = k;
       auto t2 = std::chrono::steady_clock::now();
       // grow the environment past the moved centre
@@ -264,9 +303,8 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
                                dm->Re[b].as<double>(), s));
       }
       // per-visit readback of the truncation sums and the first/last kept value
-      TNA_HIP(hipMemcpyAsync(dm->host_stage + 8, spec, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipMemcpyAsync(dm->host_stage + 16, dm->S.as<double>(), sizeof(double), hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipMemcpyAsync(dm->host_stage + 17, dm->S.as<double>() + (k - 1), sizeof(double), hipMemcpyDeviceToHost,
+      TNA_HIP(hipMemcpyAsync(dm->host_stage + 32, spec, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+      TNA_HIP(hipMemcpyAsync(dm->host_stage + 40, dm->S.as<double>() + (k - 1), sizeof(double), hipMemcpyDeviceToHost,
                              s));
       TNA_HIP(hipStreamSynchronize(s));
       auto t3 = std::chrono::steady_clock::now();
@@ -276,11 +314,15 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
         const double *h = dm->host_stage;
         r.sweep = dm->sweeps_done; r.dir = half; r.bond = b; r.m = m; r.n = n; r.k = k; r.chi_ctrl = chi_next;
         r.lanczos_iters = lr.iters; r.svd_sweeps = sw; r.lanczos_ok = lr.converged;
-        r.E = lr.E; r.S = S_ent; r.S_ema = terms[4]; r.eps = h[8 + 2]; r.wdisc = h[8 + 3]; r.gap = h[8 + 5];
-        r.P = terms[0]; r.I = terms[1]; r.D = terms[2]; r.u = terms[3]; r.sigma0 = h[16]; r.sigma_last = h[17];
+        r.E = lr.E; r.S = S_ent; r.S_ema = terms[4]; r.eps = h[32 + 2]; r.wdisc = h[32 + 3]; r.gap = h[32 + 5];
+        r.P = terms[0]; r.I = terms[1]; r.D = terms[2]; r.u = terms[3]; r.sigma0 = h[8]; r.sigma_last = h[40];
         r.ms_lanczos = std::chrono::duration<double, std::milli>(t1 - t0).count();
         r.ms_svd = std::chrono::duration<double, std::milli>(t2 - t1).count();
         r.ms_other = std::chrono::duration<double, std::milli>(t3 - t2).count();
+        r.k_needed = k_needed;
+        r.chi_sched = chi_sched;
+        r.fallback = fallback;
+        for (int q = 0; q < 25; ++q) r.feat[q] = dm->host_feat[q];
       }
       ++rec;
     }
@@ -323,6 +365,16 @@ tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t
   return TNA_OK;
 }
 
+tna_status tna_dmrg_set_scheduler(tna_dmrg dm, tna_mlp net) {
+  if (!dm) {
+    set_error("dmrg_set_scheduler: null handle");
+    return TNA_ERR_ARG;
+  }
+  dm->sched = net;
+  std::fill(dm->pred.begin(), dm->pred.end(), 0);
+  return TNA_OK;
+}
+
 void tna_dmrg_destroy(tna_dmrg dm) {
   if (!dm) return;
   (void)hipStreamSynchronize(dm->ctx->stream);
@@ -331,6 +383,8 @@ void tna_dmrg_destroy(tna_dmrg dm) {
   for (auto &b : dm->Re) b.release();
   for (DevBuf *b : {&dm->W, &dm->M12, &dm->Ml, &dm->Mr, &dm->V, &dm->T1, &dm->T2, &dm->spec, &dm->S}) b->release();
   if (dm->host_stage) (void)hipHostFree(dm->host_stage);
+  if (dm->host_feat) (void)hipHostFree(dm->host_feat);
+  for (DevBuf *b : {&dm->feat_d, &dm->y_d}) b->release();
   delete dm;
 }
 

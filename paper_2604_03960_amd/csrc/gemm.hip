@@ -45,26 +45,24 @@ struct GemmDev {
 
 constexpr int BK = 16;
 
+template <typename T, int BM, int BN> struct TileLds {
+  T As[2][BK][BM + 1];
+  T Bs[2][BK][BN + 1];
+};
+
+// One BM x BN tile of C = alpha op(A) op(B) + beta C at (m0, n0).
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
-  constexpr int PAD = 1;
+__device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, int lda, const TB *__restrict__ B, int ldb,
+                                          TC *__restrict__ C, int ldc, int M, int N, int K, double alpha, double beta,
+                                          int m0, int n0, TileLds<T, BM, BN> &L) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int LA = BM * BK / 256;  // A elements per thread per slab
   constexpr int LB = BN * BK / 256;
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
-
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int z = blockIdx.z;
-  const TA *A = static_cast<const TA *>(g.A) + g.sA * z;
-  const TB *B = static_cast<const TB *>(g.B) + g.sB * z;
-  TC *C = static_cast<TC *>(g.C) + g.sC * z;
-  const int M = g.M, N = g.N, K = g.K;
 
   // element coordinates this thread loads (tile-local)
   auto a_coord = [&](int p, int &i, int &k) {
@@ -84,7 +82,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
       a_coord(p, i, k);
       int gi = m0 + i, gk = k0 + k;
       T v = T(0);
-      if (gi < M && gk < K) v = T(TRA ? A[(int64_t)gk * g.lda + gi] : A[(int64_t)gi * g.lda + gk]);
+      if (gi < M && gk < K) v = T(TRA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]);
       ra[p] = v;
     }
 #pragma unroll
@@ -93,7 +91,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
       b_coord(p, k, j);
       int gk = k0 + k, gj = n0 + j;
       T v = T(0);
-      if (gj < N && gk < K) v = T(TRB ? B[(int64_t)gj * g.ldb + gk] : B[(int64_t)gk * g.ldb + gj]);
+      if (gj < N && gk < K) v = T(TRB ? B[(int64_t)gj * ldb + gk] : B[(int64_t)gk * ldb + gj]);
       rb[p] = v;
     }
   };
@@ -102,13 +100,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
     for (int p = 0; p < LA; ++p) {
       int i, k;
       a_coord(p, i, k);
-      As[buf][k][i] = ra[p];
+      L.As[buf][k][i] = ra[p];
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
       int k, j;
       b_coord(p, k, j);
-      Bs[buf][k][j] = rb[p];
+      L.Bs[buf][k][j] = rb[p];
     }
   };
 
@@ -129,9 +127,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
     for (int kk = 0; kk < BK; kk += 4) {
       T av[TM], bv[TN];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) av[a] = As[buf][kk + lk][wr * WM + a * 16 + lr];
+      for (int a = 0; a < TM; ++a) av[a] = L.As[buf][kk + lk][wr * WM + a * 16 + lr];
 #pragma unroll
-      for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kk + lk][wc * WN + b * 16 + lr];
+      for (int b = 0; b < TN; ++b) bv[b] = L.Bs[buf][kk + lk][wc * WN + b * 16 + lr];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -141,7 +139,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
     __syncthreads();
   }
 
-  const double alpha = g.alpha, beta = g.beta;
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -152,11 +149,49 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
         int col = n0 + wc * WN + b * 16 + lr;
         if (row < M && col < N) {
           double v = alpha * (double)acc[a][b][r];
-          int64_t idx = (int64_t)row * g.ldc + col;
+          int64_t idx = (int64_t)row * ldc + col;
           if (beta != 0.0) v += beta * (double)C[idx];
           C[idx] = (TC)v;
         }
       }
+}
+
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
+  __shared__ TileLds<T, BM, BN> L;
+  const int z = blockIdx.z;
+  gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>(static_cast<const TA *>(g.A) + g.sA * z, g.lda,
+                                             static_cast<const TB *>(g.B) + g.sB * z, g.ldb,
+                                             static_cast<TC *>(g.C) + g.sC * z, g.ldc, g.M, g.N, g.K, g.alpha,
+                                             g.beta, blockIdx.y * BM, blockIdx.x * BN, L);
+}
+
+// Persistent grouped GEMM: the grid walks a static work list of tiles that
+// spans every problem of the group (problem p owns tiles [tile0, tile0 +
+// tiles_m * tiles_n)); operand pointers may carry a device-side element offset
+// (*jB) * jB_stride / (*jC) * jC_stride, read at run time, so a captured
+// launch serves every Lanczos iteration.
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmProb *probs, int nprob, int total, double alpha,
+                                                           double beta) {
+  __shared__ TileLds<T, BM, BN> L;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (probs[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const GemmProb &p = probs[lo];
+    if (p.active && !*p.active) continue;
+    const int local = t - p.tile0;
+    const int tm = local / p.tiles_n, tn = local - tm * p.tiles_n;
+    const TB *B = static_cast<const TB *>(p.B) + (p.jB ? (int64_t)(*p.jB) * p.jB_stride : 0);
+    TC *C = static_cast<TC *>(p.C) + (p.jC ? (int64_t)(*p.jC) * p.jC_stride : 0);
+    gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>(static_cast<const TA *>(p.A), p.lda, B, p.ldb, C, p.ldc, p.M, p.N,
+                                               p.K, alpha, beta, tm * BM, tn * BN, L);
+    __syncthreads();
+  }
 }
 
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN>
@@ -201,7 +236,72 @@ tna_status launch_types(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
   return launch_tile<T, TA, TB, TC, 64, 64>(a, d, s);
 }
 
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN>
+tna_status launch_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int total, hipStream_t s) {
+  int grid = total < 2048 ? total : 2048;
+  if (grid < 1) return TNA_OK;
+  char name[64] = "";
+  if (timing_on()) {
+    std::snprintf(name, sizeof name, "gemmg.%s.%dx%d.%c%c", sizeof(T) == 8 ? "f64" : "f32", BM, BN,
+                  g.transA ? 'T' : 'N', g.transB ? 'T' : 'N');
+    timer_begin(name, s);
+  }
+  if (!g.transA && !g.transB)
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, false>), dim3(grid), dim3(256), 0, s, d,
+                       nprob, total, g.alpha, g.beta);
+  else if (!g.transA && g.transB)
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, true>), dim3(grid), dim3(256), 0, s, d,
+                       nprob, total, g.alpha, g.beta);
+  else if (g.transA && !g.transB)
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, true, false>), dim3(grid), dim3(256), 0, s, d,
+                       nprob, total, g.alpha, g.beta);
+  else {
+    set_error("gemm_grouped: transA && transB not built");
+    return TNA_ERR_UNSUPPORTED;
+  }
+  if (name[0]) timer_end(name, g.flops, g.bytes, s);
+  TNA_LAUNCHED("gemm.grouped");
+  return TNA_OK;
+}
+
+template <typename T, typename TA, typename TB, typename TC>
+tna_status grouped_types(const GemmGroup &g, const GemmProb *d, int nprob, int total, hipStream_t s) {
+  if (g.tile == 128) return launch_grouped<T, TA, TB, TC, 128, 128>(g, d, nprob, total, s);
+  return launch_grouped<T, TA, TB, TC, 64, 64>(g, d, nprob, total, s);
+}
+
 }  // namespace
+
+int gemm_group_tiles(std::vector<GemmProb> &probs, int tile) {
+  int total = 0;
+  for (auto &p : probs) {
+    p.tile0 = total;
+    p.tiles_n = (p.N + tile - 1) / tile;
+    const int tm = (p.M + tile - 1) / tile;
+    total += (p.M > 0 && p.N > 0) ? tm * p.tiles_n : 0;
+  }
+  return total;
+}
+
+tna_status gemm_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int total, hipStream_t s) {
+  if (nprob < 1 || total < 1) return TNA_OK;
+  const int code = g.typeA * 4 + g.typeB * 2 + g.typeC;
+  if (g.compute == G_F64) {
+    if (code != 0) {
+      set_error("gemm_grouped: FP64 compute takes double operands");
+      return TNA_ERR_UNSUPPORTED;
+    }
+    return grouped_types<double, double, double, double>(g, d, nprob, total, s);
+  }
+  switch (code) {
+    case 0: return grouped_types<float, double, double, double>(g, d, nprob, total, s);
+    case 5: return grouped_types<float, float, double, float>(g, d, nprob, total, s);
+    case 6: return grouped_types<float, float, float, double>(g, d, nprob, total, s);
+    case 7: return grouped_types<float, float, float, float>(g, d, nprob, total, s);
+  }
+  set_error("gemm_grouped: FP32 operand combination not built");
+  return TNA_ERR_UNSUPPORTED;
+}
 
 tna_status gemm(const GemmArgs &a, hipStream_t s) {
   if (a.M < 0 || a.N < 0 || a.K < 0 || a.batch < 1) {

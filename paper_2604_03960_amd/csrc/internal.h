@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -72,6 +74,31 @@ struct GemmArgs {
 };
 tna_status gemm(const GemmArgs &g, hipStream_t s);
 
+// Grouped GEMM: one persistent launch for problems of different shapes that
+// share transposes, operand types and alpha/beta.  Descriptors live in device
+// memory; jB / jC (device ints, may be null) add (*jB) * jB_stride elements to
+// B and (*jC) * jC_stride to C at run time; active (device int, may be null)
+// skips the problem when zero.
+struct GemmProb {
+  int M, N, K, lda, ldb, ldc;
+  const void *A;
+  const void *B;
+  void *C;
+  const int *jB;
+  const int *jC;
+  const int *active;
+  int64_t jB_stride, jC_stride;
+  int tile0, tiles_n;  // filled by gemm_group_tiles
+};
+struct GemmGroup {
+  int transA, transB, typeA, typeB, typeC, compute, tile;
+  double alpha, beta;
+  double flops, bytes;  // algorithmic work of the whole launch (timing only)
+};
+// Assigns tile ranges for a square tile of the given size; returns the total.
+int gemm_group_tiles(std::vector<GemmProb> &probs, int tile);
+tna_status gemm_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int total, hipStream_t s);
+
 // ------------------------------------------------------------------ MPO mixing
 // out[o0*os0 + o1*os1 + ooff[j]] = sum_i M[j*I + i] * in[o0*is0 + o1*is1 + ioff[i]]
 // for o0 < n0, o1 < n1.  I, J <= 32.  in/out double or float.
@@ -116,40 +143,71 @@ tna_status copy_transpose(const void *A, int m, int n, int type, double *B, hipS
 tna_status set_identity(double *J, int n, int ld, int batch, int64_t stride, hipStream_t s);
 
 // ------------------------------------------------------------------ SVD
-struct SvdWork;
-struct SvdPlan {
-  int batch, m, n;
-  int R, C;       // working rows / row length (R = min(m,n))
-  int trans;      // 1 when m > n (rows of A^T are orthogonalised)
-  int nb;         // number of 32-row blocks (even)
-  int ksplit;     // Gram K split
-  int dtype;      // TNA_F64 / TNA_F32 of the working matrix
+// One truncated SVD (blocked one-sided Jacobi): shape, plan, work buffers,
+// input and outputs.  A group of them (one matrix, a uniform batch or
+// matrices of different shapes) runs through the same launches, one grid
+// z-slice per matrix.
+struct SvdMat {
+  int m, n, R, C, trans, nb, ksplit, active;  // R = min(m,n) rows of length C are orthogonalised
+  int k, dtype, out_type, scale_mode;         // kept rank; scale 0 none, 1 Vt rows, 2 U columns by S_j/|S_k|
+  double tol, eps_target;
+  const void *A;                               // m x n (dtype)
+  double *bw, *jt, *gram, *qt, *sig;           // work
+  double *S;                                   // R sorted values (output)
+  double *spec;                                // 24 doubles: Z, S_vN, eps, eps^2/Z, |S_k|, gap, k_needed, -, S_0..S_15
+  int *skip, *perm, *ctr;                      // work
+  void *U, *Vt;                                // m x k, k x n (out_type)
 };
-// Working storage for a batch of SVDs.
-struct SvdBuffers {
-  DevBuf bw, jt, gram, qt, flags, sig, perm, ctr, scratch;
+struct SvdGroup {
+  DevBuf desc, work_d, work_i;
+  void *host = nullptr;
+  size_t host_cap = 0;
+  int *host_ctr = nullptr;
+  void release();
 };
-tna_status svd_plan(int batch, int m, int n, int dtype, SvdPlan *p);
-// Loads A (or A^T) into the working buffers, runs Jacobi sweeps until none
-// rotates (one host read per sweep) or max_sweeps, then sorts the row norms.
-// Returns TNA_ERR_NOCONV on the cap.
-tna_status svd_run(const SvdPlan &p, SvdBuffers &wb, const void *A, int64_t strideA, int max_sweeps, int *sweeps,
-                   hipStream_t s, int *host_ctr);
-// Spectrum S (sorted) into S_out (stride), entropy/Z into spec (stride 6).
-tna_status svd_spectrum(const SvdPlan &p, SvdBuffers &wb, double *S_out, int64_t strideS, double *spec,
-                        hipStream_t s);
-// Truncation sums for k from the sorted spectrum S (device spec[2..5]).
-tna_status svd_trunc_S(const SvdPlan &p, const double *S, int64_t strideS, int k, double *spec, hipStream_t s);
-// Writes U (m x k) and Vt (k x n) from the working buffers, completes null
-// vectors, applies the sign gauge, then scale_mode 0 none, 1 scales Vt rows
-// by S_j/|S_k|, 2 scales U columns by S_j/|S_k| (|S_k| = spec[4]).
-tna_status svd_outputs_S(const SvdPlan &p, SvdBuffers &wb, const double *S, int64_t strideS, int k, void *U,
-                         int64_t strideU, void *Vt, int64_t strideVt, int out_type, int scale_mode,
-                         const double *spec, hipStream_t s);
+tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a);
+size_t svd_work_doubles(const SvdMat &a);
+size_t svd_work_ints(const SvdMat &a);
+void svd_bind_work(SvdMat *a, double *dw, int *iw);
+// Loads every A, runs Jacobi sweeps until a matrix's sweep rotates nothing
+// (one host read per sweep), then sorts and writes S, spec[0,1,6,8..23].
+// Returns TNA_ERR_NOCONV if any matrix hit max_sweeps.
+tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps, std::vector<int> &sweeps,
+                         hipStream_t s);
+// For each matrix's k: spec[2..5], U and Vt (completion of null vectors,
+// sign gauge, scaling).
+tna_status svd_group_outputs(std::vector<SvdMat> &mats, SvdGroup &g, hipStream_t s);
 
-// ------------------------------------------------------------------ spectrum
-tna_status spectrum_entropy(const double *S, int R, double *spec, int batch, int64_t strideS, hipStream_t s);
-tna_status spectrum_trunc(const double *S, int R, int k, double *spec, int batch, int64_t strideS, hipStream_t s);
+// ------------------------------------------------------------------ grouped (batched-chain) kernels
+struct MixProb {
+  int n0, n1;
+  const void *in;
+  void *out;
+  int64_t is0, is1, os0, os1;
+  int ich1, ich2, och1, och2;  // channel i = (i1, i2) sits at i1*ich1 + i2*ich2
+  const double *M;             // J x I
+  const int *active;           // device flag, may be null
+};
+tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, int I2, int J1, int J2, int f32,
+                       hipStream_t s);
+// One chain's Lanczos state for the current sweep step (device pointers).
+struct LzProb {
+  int64_t n;      // vector length
+  int G, nkeep;   // partial-sum blocks; Ritz vector length
+  double *V;      // (kmax+1) x n Krylov basis (V_{j+1} doubles as w)
+  double *theta;  // start vector in, normalised Ritz vector out
+  int *j, *active;
+  double *h1, *h2, *part1, *part2, *nrm2, *rec, *y;  // rec: {alpha_j, beta_j^2}
+};
+tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, hipStream_t s);
+tna_status lz_start(const LzProb *d, int nch, int maxG, hipStream_t s);
+tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s);
+struct CvtProb {
+  const double *src;
+  float *dst;
+  int64_t n;
+};
+tna_status convert_grouped(const CvtProb *d, int nprob, hipStream_t s);
 
 // ------------------------------------------------------------------ host-side steps (api.cpp)
 struct LanczosResult {
@@ -176,8 +234,31 @@ struct tna_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int timing = 0;
-  tna::DevBuf x, z, lf, rf, m12, part, misc;
-  tna::SvdBuffers svd;
+  tna::DevBuf x, z, lf, rf, m12, part, misc, spec;
+  tna::SvdGroup svd;
   int *host_ctr = nullptr;     // pinned
   double *host_scal = nullptr; // pinned, 64 doubles
+};
+
+// ------------------------------------------------------------------ DMRG chain state
+struct tna_dmrg_s {
+  tna_ctx ctx;
+  int N, d, D;
+  tna_pid_params pid;
+  tna_dmrg_opts opts;
+  std::vector<int> chi;                 // N-1 realised bond dims
+  std::vector<tna_pid_state> st;        // N-1 controllers
+  std::vector<tna::DevBuf> A, Le, Re;   // site tensors, left envs (site i), right envs (site i)
+  tna::DevBuf W, M12, Ml, Mr;           // MPO tensors and mixing matrices (device)
+  tna::DevBuf V, T1, T2, spec, S;       // Lanczos basis, env scratch, spectrum
+  int sweeps_done = 0;
+  double *host_stage = nullptr;         // pinned: per-visit readbacks
+  // learned scheduler
+  tna_mlp sched = nullptr;
+  std::vector<std::array<double, 8>> hist;  // last EMA entropies per bond (oldest first)
+  std::vector<int> nhist, pred;             // history length, pending proposal (0 = none)
+  tna::DevBuf feat_d, y_d;
+  float *host_feat = nullptr;               // pinned: 25 inputs + 1 output
+  int CL(int i) const { return i == 0 ? 1 : chi[i - 1]; }
+  int CR(int i) const { return i == N - 1 ? 1 : chi[i]; }
 };

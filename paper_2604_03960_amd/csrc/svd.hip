@@ -69,27 +69,27 @@ __device__ inline int block_rows(int R, int blk) {
   return r < 0 ? 0 : (r > BS ? BS : r);
 }
 
-struct SvdDev {
-  int R, C, nb, ksplit, step;
-  double *bw;   // batch x R x C
-  double *jt;   // batch x R x R
-  double *gram; // batch x npairs x ksplit x 64 x 64
-  double *qt;   // batch x npairs x 64 x 64
-  int *skip;    // batch x npairs
-  int *ctr;
-  double tol;
-};
+__device__ inline double bsum256(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
 
 // -------------------------------------------------------------- gram
-__global__ __launch_bounds__(256) void gram_kernel(SvdDev a) {
+// grid (pairs, ksplit, matrices)
+__global__ __launch_bounds__(256) void gram_kernel(const SvdMat *mats, int step) {
   constexpr int BK = 32;
   __shared__ double Ts[BK][64 + 1];
-  const int pair = blockIdx.x, ks = blockIdx.y, z = blockIdx.z;
-  const int npairs = a.nb / 2;
+  const SvdMat &a = mats[blockIdx.z];
+  const int pair = blockIdx.x, ks = blockIdx.y;
+  if (!a.active || step >= a.nb - 1 || pair >= a.nb / 2 || ks >= a.ksplit) return;
   int p, q;
-  rr_pair(a.nb, a.step, pair, p, q);
+  rr_pair(a.nb, step, pair, p, q);
   const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
-  const double *B = a.bw + (int64_t)z * a.R * a.C;
+  const double *B = a.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int qi = wave >> 1, qj = wave & 1;
@@ -98,7 +98,9 @@ __global__ __launch_bounds__(256) void gram_kernel(SvdDev a) {
   const int64_t kb = chunk * ks;
   const int64_t ke = kb + chunk < a.C ? kb + chunk : a.C;
   v4d acc[2][2];
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
   for (int64_t k0 = kb; k0 < ke; k0 += BK) {
 #pragma unroll
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(256) void gram_kernel(SvdDev a) {
     }
     __syncthreads();
   }
-  double *G = a.gram + (((int64_t)z * npairs + pair) * a.ksplit + ks) * 4096;
+  double *G = a.gram + ((int64_t)pair * a.ksplit + ks) * 4096;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -137,26 +139,28 @@ __global__ __launch_bounds__(256) void gram_kernel(SvdDev a) {
 }
 
 // -------------------------------------------------------------- eigen
-__global__ __launch_bounds__(256) void eigen_kernel(SvdDev a) {
+// grid (pairs, matrices)
+__global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step) {
   __shared__ double Gs[64][65];
   __shared__ double Qs[64][65];
   __shared__ double cs_[32], sn_[32];
   __shared__ int pi_[32], pj_[32];
   __shared__ int rot_any, need;
   __shared__ int slot_of[64];
-  const int pair = blockIdx.x, z = blockIdx.y;
-  const int npairs = a.nb / 2;
+  const SvdMat &a = mats[blockIdx.y];
+  const int pair = blockIdx.x;
+  if (!a.active || step >= a.nb - 1 || pair >= a.nb / 2) return;
   const int tid = threadIdx.x;
   int p, q;
-  rr_pair(a.nb, a.step, pair, p, q);
+  rr_pair(a.nb, step, pair, p, q);
   const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
-  int *skip = a.skip + (int64_t)z * npairs + pair;
+  int *skip = a.skip + pair;
   if (np + nq == 0) {
     if (tid == 0) *skip = 1;
     return;
   }
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
-  const double *Gp = a.gram + ((int64_t)z * npairs + pair) * a.ksplit * 4096;
+  const double *Gp = a.gram + (int64_t)pair * a.ksplit * 4096;
   for (int e = tid; e < 4096; e += 256) {
     const int i = e >> 6, j = e & 63;
     const int lo = i < j ? i : j, hi = i < j ? j : i;
@@ -167,7 +171,6 @@ __global__ __launch_bounds__(256) void eigen_kernel(SvdDev a) {
   }
   if (tid == 0) need = 0;
   __syncthreads();
-  // outer test on the fresh Gram
   {
     int loc = 0;
     for (int e = tid; e < 4096; e += 256) {
@@ -208,8 +211,7 @@ __global__ __launch_bounds__(256) void eigen_kernel(SvdDev a) {
         cs_[tid] = c; sn_[tid] = s; pi_[tid] = i; pj_[tid] = j;
       }
       __syncthreads();
-      // rows i, j of G
-      for (int e = tid; e < 32 * 64; e += 256) {
+      for (int e = tid; e < 32 * 64; e += 256) {  // rows i, j of G
         const int t = e >> 6, k = e & 63;
         const double s = sn_[t];
         if (s != 0.0) {
@@ -221,8 +223,7 @@ __global__ __launch_bounds__(256) void eigen_kernel(SvdDev a) {
         }
       }
       __syncthreads();
-      // columns i, j of G and of Q
-      for (int e = tid; e < 32 * 64; e += 256) {
+      for (int e = tid; e < 32 * 64; e += 256) {  // columns i, j of G and of Q
         const int t = e >> 6, k = e & 63;
         const double s = sn_[t];
         if (s != 0.0) {
@@ -244,10 +245,9 @@ __global__ __launch_bounds__(256) void eigen_kernel(SvdDev a) {
     const int any = rot_any;
     if (!any) break;
   }
-  // order eigenvalues descending (ties: lower slot first); invalid slots last
+  // eigenvalues descending (ties: lower slot first), larger ones to block p
   if (tid < 64) {
     const int r = tid;
-    int slot = -1;
     if (valid(r)) {
       const double lr_ = Gs[r][r];
       int rank = 0;
@@ -256,44 +256,43 @@ __global__ __launch_bounds__(256) void eigen_kernel(SvdDev a) {
         const double lo = Gs[o][o];
         if (lo > lr_ || (lo == lr_ && o < r)) ++rank;
       }
-      slot = rank < np ? rank : 32 + (rank - np);
+      slot_of[rank < np ? rank : 32 + (rank - np)] = r;
     }
-    if (slot >= 0) slot_of[slot] = r;
   }
   __syncthreads();
-  double *Qt = a.qt + ((int64_t)z * npairs + pair) * 4096;
+  double *Qt = a.qt + (int64_t)pair * 4096;
   for (int e = tid; e < 4096; e += 256) {
     const int so = e >> 6, ri = e & 63;
-    double v = 0.0;
-    if (valid(so) && valid(ri)) v = Qs[ri][slot_of[so]];
-    Qt[e] = v;
+    Qt[e] = (valid(so) && valid(ri)) ? Qs[ri][slot_of[so]] : 0.0;
   }
   if (tid == 0) *skip = 0;
 }
 
 // -------------------------------------------------------------- apply
-__global__ __launch_bounds__(256) void apply_kernel(SvdDev a, int ntile_b) {
+// grid (pairs, column tiles of B then of Jt, matrices)
+__global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step) {
   __shared__ double As[64][65];  // As[k][i] = Qt[i][k]
   __shared__ double Xs[64][65];  // Xs[k][j] = X[row(k)][c0 + j]
-  const int pair = blockIdx.x, tile = blockIdx.y, z = blockIdx.z;
-  const int npairs = a.nb / 2;
-  if (a.skip[(int64_t)z * npairs + pair]) return;
+  const SvdMat &a = mats[blockIdx.z];
+  const int pair = blockIdx.x, tile = blockIdx.y;
+  const int ntile_b = (a.C + 63) / 64, ntile_j = (a.R + 63) / 64;
+  if (!a.active || step >= a.nb - 1 || pair >= a.nb / 2 || tile >= ntile_b + ntile_j) return;
+  if (a.skip[pair]) return;
   int p, q;
-  rr_pair(a.nb, a.step, pair, p, q);
+  rr_pair(a.nb, step, pair, p, q);
   const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
   auto grow = [&](int r) { return r < 32 ? p * BS + r : q * BS + (r - 32); };
   double *X;
   int ld, c0;
-  if (tile < ntile_b) { X = a.bw + (int64_t)z * a.R * a.C; ld = a.C; c0 = tile * 64; }
-  else { X = a.jt + (int64_t)z * a.R * a.R; ld = a.R; c0 = (tile - ntile_b) * 64; }
-  const double *Qt = a.qt + ((int64_t)z * npairs + pair) * 4096;
+  if (tile < ntile_b) { X = a.bw; ld = a.C; c0 = tile * 64; }
+  else { X = a.jt; ld = a.R; c0 = (tile - ntile_b) * 64; }
+  const double *Qt = a.qt + (int64_t)pair * 4096;
   const int tid = threadIdx.x;
   for (int e = tid; e < 4096; e += 256) {
     const int i = e >> 6, k = e & 63;
     As[k][i] = Qt[e];
-    const int r = e >> 6, c = e & 63;
-    Xs[r][c] = (valid(r) && c0 + c < ld) ? X[(int64_t)grow(r) * ld + c0 + c] : 0.0;
+    Xs[i][k] = (valid(i) && c0 + k < ld) ? X[(int64_t)grow(i) * ld + c0 + k] : 0.0;
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
@@ -316,27 +315,74 @@ __global__ __launch_bounds__(256) void apply_kernel(SvdDev a, int ntile_b) {
     }
 }
 
-// -------------------------------------------------------------- finish
-__global__ __launch_bounds__(256) void norms_kernel(const double *bw, int R, int C, double *sig) {
-  const int z = blockIdx.y;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (r >= R) return;
-  const double *row = bw + ((int64_t)z * R + r) * C;
-  double s = 0.0;
-  for (int c = lane; c < C; c += 64) s += row[c] * row[c];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) sig[(int64_t)z * R + r] = sqrt(s);
+// -------------------------------------------------------------- load / init
+// grid (tiles, 1, matrices): rows of A (or of A^T) into bw as double; Jt = I
+__global__ __launch_bounds__(256) void load_kernel(const SvdMat *mats) {
+  __shared__ double tile[32][33];
+  const SvdMat &a = mats[blockIdx.z];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int ntj = (a.n + 31) / 32, nti = (a.m + 31) / 32;
+  const int t = blockIdx.x;
+  if (t < nti * ntj) {
+    const int by = (t / ntj) * 32, bx = (t % ntj) * 32;  // by over m, bx over n
+    for (int r = ty; r < 32; r += 8) {
+      const int i = by + r, j = bx + tx;
+      double v = 0.0;
+      if (i < a.m && j < a.n)
+        v = a.dtype == TNA_F64 ? static_cast<const double *>(a.A)[(int64_t)i * a.n + j]
+                               : (double)static_cast<const float *>(a.A)[(int64_t)i * a.n + j];
+      tile[r][tx] = v;
+    }
+    __syncthreads();
+    if (!a.trans) {
+      for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;
+        if (i < a.m && j < a.n) a.bw[(int64_t)i * a.n + j] = tile[r][tx];
+      }
+    } else {
+      for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;
+        if (j < a.n && i < a.m) a.bw[(int64_t)j * a.m + i] = tile[tx][r];
+      }
+    }
+  } else {
+    const int64_t e0 = (int64_t)(t - nti * ntj) * 1024, tot = (int64_t)a.R * a.R;
+    for (int64_t e = e0 + threadIdx.x; e < e0 + 1024 && e < tot; e += 256) {
+      const int64_t r = e / a.R, c = e - r * a.R;
+      a.jt[e] = (r == c) ? 1.0 : 0.0;
+    }
+  }
 }
 
-// bitonic sort of (sigma desc, index asc); P = power of two >= R, P <= 4096
-__global__ __launch_bounds__(1024) void sort_kernel(const double *sig, int R, int P, int *perm, double *S_out,
-                                                    int64_t strideS) {
+__global__ void zero_ctr_kernel(const SvdMat *mats, int nmat) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < nmat && mats[z].active) *mats[z].ctr = 0;
+}
+
+// -------------------------------------------------------------- finish
+// grid (ceil(R/4), 1, matrices): sigma_r = |row r|, one wave per row
+__global__ __launch_bounds__(256) void norms_kernel(const SvdMat *mats) {
+  const SvdMat &a = mats[blockIdx.z];
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= a.R) return;
+  const double *row = a.bw + (int64_t)r * a.C;
+  double s = 0.0;
+  for (int c = lane; c < a.C; c += 64) s += row[c] * row[c];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) a.sig[r] = sqrt(s);
+}
+
+// one block per matrix: bitonic sort of (sigma desc, index asc), then Z and the entropy
+__global__ __launch_bounds__(1024) void sort_kernel(const SvdMat *mats) {
   __shared__ double key[4096];
   __shared__ int idx[4096];
-  const int z = blockIdx.x;
+  __shared__ double red[16];
+  const SvdMat &a = mats[blockIdx.x];
+  int P = 1;
+  while (P < a.R) P <<= 1;
   for (int i = threadIdx.x; i < P; i += 1024) {
-    key[i] = i < R ? sig[(int64_t)z * R + i] : -1.0;
+    key[i] = i < a.R ? a.sig[i] : -1.0;
     idx[i] = i;
   }
   __syncthreads();
@@ -345,7 +391,6 @@ __global__ __launch_bounds__(1024) void sort_kernel(const double *sig, int R, in
       for (int i = threadIdx.x; i < P; i += 1024) {
         const int l = i ^ j;
         if (l > i) {
-          // "before(x, y)": x sorts ahead of y
           const bool i_before_l = key[i] > key[l] || (key[i] == key[l] && idx[i] < idx[l]);
           const bool up = (i & k) == 0;
           if (up ? !i_before_l : i_before_l) {
@@ -357,126 +402,196 @@ __global__ __launch_bounds__(1024) void sort_kernel(const double *sig, int R, in
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < R; i += 1024) {
-    perm[(int64_t)z * R + i] = idx[i];
-    S_out[(int64_t)z * strideS + i] = key[i];
+  for (int i = threadIdx.x; i < a.R; i += 1024) {
+    a.perm[i] = idx[i];
+    a.S[i] = key[i];
+  }
+  // Z = sum S^2 and S_vN = -sum p ln p (p = S^2 / Z), fixed-order block sums
+  double z2 = 0.0;
+  for (int i = threadIdx.x; i < a.R; i += 1024) z2 += key[i] * key[i];
+  for (int off = 32; off > 0; off >>= 1) z2 += __shfl_xor(z2, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = z2;
+  __syncthreads();
+  double Z = 0.0;
+  for (int w = 0; w < 16; ++w) Z += red[w];
+  __syncthreads();
+  double e = 0.0;
+  for (int i = threadIdx.x; i < a.R; i += 1024) {
+    const double p = key[i] * key[i] / Z;
+    if (p > 0.0) e -= p * log(p);
+  }
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ent = 0.0;
+    for (int w = 0; w < 16; ++w) ent += red[w];
+    a.spec[0] = Z;
+    a.spec[1] = ent;
+  }
+  if (threadIdx.x < 16) a.spec[8 + threadIdx.x] = (int)threadIdx.x < a.R ? key[threadIdx.x] : 0.0;
+  // spec[6]: smallest k >= 1 with sqrt(sum_{j>=k} S_j^2) <= eps_target (k = R always qualifies)
+  if (a.eps_target > 0.0) {
+    __shared__ double csum[1024];
+    __shared__ int best[16];
+    const int t = threadIdx.x, R = a.R;
+    const double eps2 = a.eps_target * a.eps_target;
+    const int L = (R + 1023) / 1024;
+    const int beg = t * L, end = beg + L < R ? beg + L : R;
+    double c = 0.0;
+    for (int j = beg; j < end; ++j) c += key[j] * key[j];
+    csum[t] = c;
+    __syncthreads();
+    double after = 0.0;
+    for (int u = 1023; u > t; --u) after += csum[u];
+    int kmin = R;
+    double tsum = after;
+    for (int j = end - 1; j >= beg; --j) {
+      tsum += key[j] * key[j];
+      if (tsum <= eps2) kmin = j;
+    }
+    if (kmin < 1) kmin = 1;
+    for (int off = 32; off > 0; off >>= 1) kmin = min(kmin, __shfl_xor(kmin, off, 64));
+    if ((t & 63) == 0) best[t >> 6] = kmin;
+    __syncthreads();
+    if (t == 0) {
+      int b = best[0];
+      for (int w = 1; w < 16; ++w) b = min(b, best[w]);
+      a.spec[6] = (double)b;
+    }
   }
 }
 
-struct OutDev {
-  int R, C, m, n, k, trans;
-  const double *bw, *jt, *S;  // S: sorted spectrum (stride strideS)
-  int64_t strideS;
-  const int *perm;
-  void *U; int64_t strideU;
-  void *Vt; int64_t strideVt;
-};
-
-// U (m x k) and Vt (k x n), unscaled; null Bw-derived vectors are zeroed
-template <typename T>
-__global__ __launch_bounds__(256) void write_u_kernel(OutDev o) {
-  const int z = blockIdx.y;
-  const int64_t total = (int64_t)o.m * o.k;
-  const double *S = o.S + (int64_t)z * o.strideS;
-  const double thr = EPS53 * S[0] * (o.m > o.n ? o.m : o.n);
-  T *U = static_cast<T *>(o.U) + (int64_t)z * o.strideU;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int i = (int)(e / o.k), j = (int)(e % o.k);
-    const int r = o.perm[(int64_t)z * o.R + j];
-    double v;
-    if (!o.trans) v = o.jt[((int64_t)z * o.R + r) * o.R + i];
-    else v = (S[j] > thr && S[j] > 0.0) ? o.bw[((int64_t)z * o.R + r) * o.C + i] / S[j] : 0.0;
-    U[e] = (T)v;
+// one block per matrix: spec[2..5] for the kept rank k
+__global__ __launch_bounds__(256) void trunc_kernel(const SvdMat *mats) {
+  __shared__ double red[4];
+  const SvdMat &a = mats[blockIdx.x];
+  if (a.k < 1) return;
+  const double *s = a.S;
+  const int R = a.R, k = a.k, t = threadIdx.x;
+  double tl = 0.0, hd = 0.0;
+  for (int i = t; i < R; i += 256) {
+    if (i >= k) tl += s[i] * s[i];
+    else hd += s[i] * s[i];
+  }
+  const double tail = bsum256(tl, red);
+  const double head = bsum256(hd, red);
+  if (t == 0) {
+    const double Z = a.spec[0];
+    a.spec[2] = sqrt(tail);
+    a.spec[3] = tail / Z;
+    a.spec[4] = sqrt(head);
+    a.spec[5] = (k < R && s[0] > 0.0) ? (s[k - 1] - s[k]) / s[0] : 1.0;
   }
 }
 
+// U (m x k) and Vt (k x n), unscaled; null Bw-derived vectors are zeroed.
+// grid (chunks, 2, matrices): y = 0 writes U, y = 1 writes Vt
 template <typename T>
-__global__ __launch_bounds__(256) void write_vt_kernel(OutDev o) {
-  const int z = blockIdx.y;
-  const int64_t total = (int64_t)o.k * o.n;
-  const double *S = o.S + (int64_t)z * o.strideS;
-  const double thr = EPS53 * S[0] * (o.m > o.n ? o.m : o.n);
-  T *Vt = static_cast<T *>(o.Vt) + (int64_t)z * o.strideVt;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int j = (int)(e / o.n), c = (int)(e % o.n);
-    const int r = o.perm[(int64_t)z * o.R + j];
-    double v;
-    if (o.trans) v = o.jt[((int64_t)z * o.R + r) * o.R + c];
-    else v = (S[j] > thr && S[j] > 0.0) ? o.bw[((int64_t)z * o.R + r) * o.C + c] / S[j] : 0.0;
-    Vt[e] = (T)v;
+__device__ inline void write_factors(const SvdMat &a, int which, int64_t e0, int64_t stride) {
+  const double thr = EPS53 * a.S[0] * (a.m > a.n ? a.m : a.n);
+  if (which == 0) {
+    T *U = static_cast<T *>(a.U);
+    const int64_t total = (int64_t)a.m * a.k;
+    for (int64_t e = e0; e < total; e += stride) {
+      const int i = (int)(e / a.k), j = (int)(e % a.k);
+      const int r = a.perm[j];
+      double v;
+      if (!a.trans) v = a.jt[(int64_t)r * a.R + i];
+      else v = (a.S[j] > thr && a.S[j] > 0.0) ? a.bw[(int64_t)r * a.C + i] / a.S[j] : 0.0;
+      U[e] = (T)v;
+    }
+  } else {
+    T *Vt = static_cast<T *>(a.Vt);
+    const int64_t total = (int64_t)a.k * a.n;
+    for (int64_t e = e0; e < total; e += stride) {
+      const int j = (int)(e / a.n), c = (int)(e % a.n);
+      const int r = a.perm[j];
+      double v;
+      if (a.trans) v = a.jt[(int64_t)r * a.R + c];
+      else v = (a.S[j] > thr && a.S[j] > 0.0) ? a.bw[(int64_t)r * a.C + c] / a.S[j] : 0.0;
+      Vt[e] = (T)v;
+    }
   }
+}
+
+__global__ __launch_bounds__(256) void write_kernel(const SvdMat *mats) {
+  const SvdMat &a = mats[blockIdx.z];
+  if (a.k < 1) return;
+  const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+  if (a.out_type == TNA_F64) write_factors<double>(a, blockIdx.y, e0, stride);
+  else write_factors<float>(a, blockIdx.y, e0, stride);
 }
 
 // Gram-Schmidt completion of kept null vectors with unit vectors e_0, e_1, ...
-// The completed factor is Vt (rows) when trans == 0, U (columns) when trans == 1.
+// (Vt rows when rows of A were orthogonalised, U columns otherwise); one block per matrix
 template <typename T>
-__global__ __launch_bounds__(256) void complete_kernel(OutDev o) {
-  __shared__ double vec[4096];
-  __shared__ double red[4];
-  __shared__ int ok;
-  const int z = blockIdx.x;
-  const double *S = o.S + (int64_t)z * o.strideS;
-  const double thr = EPS53 * S[0] * (o.m > o.n ? o.m : o.n);
-  const int L = o.trans ? o.m : o.n;  // vector length
+__device__ void complete_one(const SvdMat &a, double *vec, double *red, int *ok) {
+  const double thr = EPS53 * a.S[0] * (a.m > a.n ? a.m : a.n);
+  const int L = a.trans ? a.m : a.n;
   T *base;
-  int64_t es, vs;  // element stride, vector stride
-  if (o.trans) { base = static_cast<T *>(o.U) + (int64_t)z * o.strideU; es = o.k; vs = 1; }
-  else { base = static_cast<T *>(o.Vt) + (int64_t)z * o.strideVt; es = 1; vs = o.n; }
+  int64_t es, vs;
+  if (a.trans) { base = static_cast<T *>(a.U); es = a.k; vs = 1; }
+  else { base = static_cast<T *>(a.Vt); es = 1; vs = a.n; }
   const int tid = threadIdx.x;
-  auto bsum = [&](double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    const double r = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-    return r;
-  };
   int e = 0;
-  for (int j = 0; j < o.k; ++j) {
-    if (S[j] > thr && S[j] > 0.0) continue;
+  for (int j = 0; j < a.k; ++j) {
+    if (a.S[j] > thr && a.S[j] > 0.0) continue;
     for (; e < L; ++e) {
       for (int i = tid; i < L; i += 256) vec[i] = (i == e) ? 1.0 : 0.0;
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass)
-        for (int qv = 0; qv < o.k; ++qv) {
+        for (int qv = 0; qv < a.k; ++qv) {
           if (qv == j) continue;
-          if (!((S[qv] > thr && S[qv] > 0.0) || qv < j)) continue;
+          if (!((a.S[qv] > thr && a.S[qv] > 0.0) || qv < j)) continue;
           double h = 0.0;
           for (int i = tid; i < L; i += 256) h += (double)base[qv * vs + (int64_t)i * es] * vec[i];
-          h = bsum(h);
+          h = bsum256(h, red);
           for (int i = tid; i < L; i += 256) vec[i] -= h * (double)base[qv * vs + (int64_t)i * es];
           __syncthreads();
         }
       double nr = 0.0;
       for (int i = tid; i < L; i += 256) nr += vec[i] * vec[i];
-      nr = sqrt(bsum(nr));
-      if (tid == 0) ok = nr > 0.5;
+      nr = sqrt(bsum256(nr, red));
+      if (tid == 0) *ok = nr > 0.5;
       __syncthreads();
-      if (ok) {
+      const int good = *ok;
+      __syncthreads();
+      if (good) {
         for (int i = tid; i < L; i += 256) base[j * vs + (int64_t)i * es] = (T)(vec[i] / nr);
         __syncthreads();
         ++e;
         break;
       }
-      __syncthreads();
     }
   }
 }
 
-// sign gauge: largest-|.| entry of U[:, j] positive (ties: lowest row); then scaling
+__global__ __launch_bounds__(256) void complete_kernel(const SvdMat *mats) {
+  __shared__ double vec[4096];
+  __shared__ double red[4];
+  __shared__ int ok;
+  const SvdMat &a = mats[blockIdx.x];
+  if (a.k < 1) return;
+  // only matrices with a kept null vector do any work
+  const double thr = EPS53 * a.S[0] * (a.m > a.n ? a.m : a.n);
+  if (a.S[a.k - 1] > thr && a.S[a.k - 1] > 0.0) return;
+  if (a.out_type == TNA_F64) complete_one<double>(a, vec, red, &ok);
+  else complete_one<float>(a, vec, red, &ok);
+}
+
+// sign gauge (largest-|.| entry of U[:, j] positive, ties: lowest row), then
+// scaling by S_j/|S_k| of Vt rows (scale_mode 1) or U columns (scale_mode 2)
 template <typename T>
-__global__ __launch_bounds__(256) void gauge_kernel(OutDev o, int scale_mode, const double *spec) {
-  __shared__ double bv[4];
-  __shared__ int bi[4];
-  __shared__ double sgn;
-  const int j = blockIdx.x, z = blockIdx.y, tid = threadIdx.x;
-  T *U = static_cast<T *>(o.U) + (int64_t)z * o.strideU;
-  T *Vt = static_cast<T *>(o.Vt) + (int64_t)z * o.strideVt;
+__device__ void gauge_one(const SvdMat &a, int j, double *bv, int *bi, double *sgn) {
+  const int tid = threadIdx.x;
+  T *U = static_cast<T *>(a.U);
+  T *Vt = static_cast<T *>(a.Vt);
   double best = -1.0;
   int bidx = 0x7fffffff;
-  for (int i = tid; i < o.m; i += 256) {
-    const double v = fabs((double)U[(int64_t)i * o.k + j]);
-    if (v > best) { best = v; bidx = i; }  // ascending i: first max kept
+  for (int i = tid; i < a.m; i += 256) {
+    const double v = fabs((double)U[(int64_t)i * a.k + j]);
+    if (v > best) { best = v; bidx = i; }
   }
   for (int off = 32; off > 0; off >>= 1) {
     const double ov = __shfl_xor(best, off, 64);
@@ -490,95 +605,29 @@ __global__ __launch_bounds__(256) void gauge_kernel(OutDev o, int scale_mode, co
     int ii = bi[0];
     for (int w = 1; w < 4; ++w)
       if (bv[w] > b || (bv[w] == b && bi[w] < ii)) { b = bv[w]; ii = bi[w]; }
-    sgn = ((double)U[(int64_t)ii * o.k + j] < 0.0) ? -1.0 : 1.0;
+    *sgn = ((double)U[(int64_t)ii * a.k + j] < 0.0) ? -1.0 : 1.0;
   }
   __syncthreads();
-  const double *S = o.S + (int64_t)z * o.strideS;
-  const double nk = spec ? spec[(int64_t)z * 6 + 4] : 1.0;
-  const double f = (scale_mode != 0 && nk > 0.0) ? S[j] / nk : 1.0;
-  const double fu = sgn * (scale_mode == 2 ? f : 1.0);
-  const double fv = sgn * (scale_mode == 1 ? f : 1.0);
+  const double nk = a.spec[4];
+  const double f = (a.scale_mode != 0 && nk > 0.0) ? a.S[j] / nk : 1.0;
+  const double fu = *sgn * (a.scale_mode == 2 ? f : 1.0);
+  const double fv = *sgn * (a.scale_mode == 1 ? f : 1.0);
   if (fu != 1.0)
-    for (int i = tid; i < o.m; i += 256) U[(int64_t)i * o.k + j] = (T)((double)U[(int64_t)i * o.k + j] * fu);
+    for (int i = tid; i < a.m; i += 256) U[(int64_t)i * a.k + j] = (T)((double)U[(int64_t)i * a.k + j] * fu);
   if (fv != 1.0)
-    for (int c = tid; c < o.n; c += 256) Vt[(int64_t)j * o.n + c] = (T)((double)Vt[(int64_t)j * o.n + c] * fv);
+    for (int c = tid; c < a.n; c += 256) Vt[(int64_t)j * a.n + c] = (T)((double)Vt[(int64_t)j * a.n + c] * fv);
 }
 
-// -------------------------------------------------------------- spectrum sums
-__device__ inline double bsum256(double v, double *red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const double r = (red[0] + red[1]) + (red[2] + red[3]);
-  __syncthreads();
-  return r;
-}
-
-// spec[0] = Z = sum S^2, spec[1] = -sum p ln p
-__global__ __launch_bounds__(256) void entropy_kernel(const double *S, int R, int64_t strideS, double *spec) {
-  __shared__ double red[4];
-  const int z = blockIdx.x;
-  const double *s = S + (int64_t)z * strideS;
-  double a = 0.0;
-  for (int i = threadIdx.x; i < R; i += 256) a += s[i] * s[i];
-  const double Z = bsum256(a, red);
-  double e = 0.0;
-  for (int i = threadIdx.x; i < R; i += 256) {
-    const double p = s[i] * s[i] / Z;
-    if (p > 0.0) e -= p * log(p);
-  }
-  const double ent = bsum256(e, red);
-  if (threadIdx.x == 0) {
-    spec[(int64_t)z * 6 + 0] = Z;
-    spec[(int64_t)z * 6 + 1] = ent;
-  }
-}
-
-// spec[2] = eps = sqrt(sum_{j>=k} S^2), spec[3] = eps^2/Z, spec[4] = |S_0..k-1|, spec[5] = gap
-__global__ __launch_bounds__(256) void trunc_kernel(const double *S, int R, int k, int64_t strideS, double *spec) {
-  __shared__ double red[4];
-  const int z = blockIdx.x;
-  const double *s = S + (int64_t)z * strideS;
-  double t = 0.0, h = 0.0;
-  for (int i = threadIdx.x; i < R; i += 256) {
-    if (i >= k) t += s[i] * s[i];
-    else h += s[i] * s[i];
-  }
-  const double tail = bsum256(t, red);
-  const double head = bsum256(h, red);
-  if (threadIdx.x == 0) {
-    const double Z = spec[(int64_t)z * 6 + 0];
-    spec[(int64_t)z * 6 + 2] = sqrt(tail);
-    spec[(int64_t)z * 6 + 3] = tail / Z;
-    spec[(int64_t)z * 6 + 4] = sqrt(head);
-    spec[(int64_t)z * 6 + 5] = (k < R && s[0] > 0.0) ? (s[k - 1] - s[k]) / s[0] : 1.0;
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void load_rows_kernel(const T *A, int64_t strideA, double *bw, int64_t n) {
-  const int z = blockIdx.y;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-    bw[(int64_t)z * n + e] = (double)A[(int64_t)z * strideA + e];
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void load_trans_kernel(const T *A, int64_t strideA, int m, int n, double *bw) {
-  __shared__ double tile[32][33];
-  const int z = blockIdx.z;
-  const T *Az = A + (int64_t)z * strideA;
-  double *B = bw + (int64_t)z * m * n;
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int i = by + r, j = bx + tx;
-    tile[r][tx] = (i < m && j < n) ? (double)Az[(int64_t)i * n + j] : 0.0;
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int j = bx + r, i = by + tx;
-    if (j < n && i < m) B[(int64_t)j * m + i] = tile[tx][r];
-  }
+// grid (max k, 1, matrices)
+__global__ __launch_bounds__(256) void gauge_kernel(const SvdMat *mats) {
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  __shared__ double sgn;
+  const SvdMat &a = mats[blockIdx.z];
+  const int j = blockIdx.x;
+  if (j >= a.k) return;
+  if (a.out_type == TNA_F64) gauge_one<double>(a, j, bv, bi, &sgn);
+  else gauge_one<float>(a, j, bv, bi, &sgn);
 }
 
 int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -586,172 +635,183 @@ int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 }  // namespace
 
 // ====================================================================== host
-tna_status svd_plan(int batch, int m, int n, int dtype, SvdPlan *p) {
-  if (batch < 1 || m < 1 || n < 1) {
+tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
+  if (m < 1 || n < 1) {
     set_error("svd: dimensions must be positive");
     return TNA_ERR_ARG;
   }
-  p->batch = batch;
-  p->m = m;
-  p->n = n;
-  p->trans = m > n;
-  p->R = m < n ? m : n;
-  p->C = m < n ? n : m;
-  if (p->C > 4096) {
+  *a = SvdMat{};
+  a->m = m;
+  a->n = n;
+  a->trans = m > n;
+  a->R = m < n ? m : n;
+  a->C = m < n ? n : m;
+  a->dtype = dtype;
+  if (a->C > 4096) {
     set_error("svd: max(m,n) > 4096 is not supported");
     return TNA_ERR_UNSUPPORTED;
   }
-  int nb = (p->R + BS - 1) / BS;
+  int nb = (a->R + BS - 1) / BS;
   if (nb < 2) nb = 2;
   if (nb & 1) ++nb;
-  p->nb = nb;
+  a->nb = nb;
   const int npairs = nb / 2;
-  int ks = ceil_div(1024, (int64_t)npairs * batch);
-  const int kmax = ceil_div(p->C, 256);
+  int ks = ceil_div(1024, (int64_t)npairs * (batch_hint > 0 ? batch_hint : 1));
+  const int kmax = ceil_div(a->C, 256);
   if (ks > kmax) ks = kmax;
   if (ks < 1) ks = 1;
-  p->ksplit = ks;
-  p->dtype = dtype;
+  a->ksplit = ks;
+  a->tol = (double)a->C * EPS53;
+  a->active = 1;
   return TNA_OK;
 }
 
-static SvdDev make_dev(const SvdPlan &p, SvdBuffers &wb, double tol) {
-  SvdDev d;
-  d.R = p.R; d.C = p.C; d.nb = p.nb; d.ksplit = p.ksplit; d.step = 0;
-  d.bw = wb.bw.as<double>(); d.jt = wb.jt.as<double>(); d.gram = wb.gram.as<double>();
-  d.qt = wb.qt.as<double>(); d.skip = wb.flags.as<int>(); d.ctr = wb.ctr.as<int>();
-  d.tol = tol;
-  return d;
+size_t svd_work_doubles(const SvdMat &a) {
+  const size_t npairs = a.nb / 2;
+  return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R;
+}
+size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4; }
+
+void svd_bind_work(SvdMat *a, double *dw, int *iw) {
+  const size_t npairs = a->nb / 2;
+  a->bw = dw;
+  dw += (size_t)a->R * a->C;
+  a->jt = dw;
+  dw += (size_t)a->R * a->R;
+  a->gram = dw;
+  dw += npairs * a->ksplit * 4096;
+  a->qt = dw;
+  dw += npairs * 4096;
+  a->sig = dw;
+  a->skip = iw;
+  iw += npairs;
+  a->perm = iw;
+  iw += a->R;
+  a->ctr = iw;
 }
 
-tna_status svd_run(const SvdPlan &p, SvdBuffers &wb, const void *A, int64_t strideA, int max_sweeps, int *sweeps,
-                   hipStream_t s, int *host_ctr) {
-  const int B = p.batch, npairs = p.nb / 2;
-  TNA_TRY(wb.bw.ensure(sizeof(double) * (size_t)B * p.R * p.C));
-  TNA_TRY(wb.jt.ensure(sizeof(double) * (size_t)B * p.R * p.R));
-  TNA_TRY(wb.gram.ensure(sizeof(double) * (size_t)B * npairs * p.ksplit * 4096));
-  TNA_TRY(wb.qt.ensure(sizeof(double) * (size_t)B * npairs * 4096));
-  TNA_TRY(wb.flags.ensure(sizeof(int) * (size_t)B * npairs));
-  TNA_TRY(wb.sig.ensure(sizeof(double) * (size_t)B * p.R));
-  TNA_TRY(wb.perm.ensure(sizeof(int) * (size_t)B * p.R));
-  TNA_TRY(wb.ctr.ensure(sizeof(int) * 4));
-  // working rows
-  const int64_t rc = (int64_t)p.R * p.C;
-  if (!p.trans) {
-    dim3 g((unsigned)std::min<int64_t>(ceil_div(rc, 256), 4096), B);
-    if (p.dtype == TNA_F64)
-      hipLaunchKernelGGL(load_rows_kernel<double>, g, dim3(256), 0, s, static_cast<const double *>(A), strideA,
-                         wb.bw.as<double>(), rc);
-    else
-      hipLaunchKernelGGL(load_rows_kernel<float>, g, dim3(256), 0, s, static_cast<const float *>(A), strideA,
-                         wb.bw.as<double>(), rc);
-  } else {
-    dim3 g(ceil_div(p.n, 32), ceil_div(p.m, 32), B);
-    if (p.dtype == TNA_F64)
-      hipLaunchKernelGGL(load_trans_kernel<double>, g, dim3(256), 0, s, static_cast<const double *>(A), strideA, p.m,
-                         p.n, wb.bw.as<double>());
-    else
-      hipLaunchKernelGGL(load_trans_kernel<float>, g, dim3(256), 0, s, static_cast<const float *>(A), strideA, p.m,
-                         p.n, wb.bw.as<double>());
+static tna_status upload(const std::vector<SvdMat> &mats, SvdGroup &g, hipStream_t s) {
+  const size_t bytes = sizeof(SvdMat) * mats.size();
+  TNA_TRY(g.desc.ensure(bytes));
+  if (g.host_cap < bytes) {
+    if (g.host) (void)hipHostFree(g.host);
+    g.host = nullptr;
+    g.host_cap = 0;
+    TNA_HIP(hipHostMalloc(&g.host, bytes * 2, hipHostMallocDefault));
+    g.host_cap = bytes * 2;
   }
-  TNA_LAUNCHED("svd.hip:1");
-  TNA_TRY(set_identity(wb.jt.as<double>(), p.R, p.R, B, (int64_t)p.R * p.R, s));
-  SvdDev d = make_dev(p, wb, (double)p.C * EPS53);
-  const int ntile_b = ceil_div(p.C, 64), ntile_j = ceil_div(p.R, 64);
-  // algorithmic work of one step: every row of B meets its partner block once
-  // (Gram: 2 (2b)^2 C per pair), then [B;J] rows are rotated (2 (2b)^2 (C+R) per pair)
-  const double pairs = (double)npairs * B, b2 = 64.0 * 64.0;
-  const double gram_flops = 2.0 * b2 * p.C * pairs, gram_bytes = 8.0 * (double)p.R * p.C * B;
-  const double eig_bytes = 8.0 * b2 * pairs * (p.ksplit + 1);
-  const double apply_flops = 2.0 * b2 * (double)(p.C + p.R) * pairs;
-  const double apply_bytes = 16.0 * ((double)p.R * p.C + (double)p.R * p.R) * B;
-  int sw = 0;
-  bool conv = false;
-  for (sw = 1; sw <= max_sweeps; ++sw) {
-    TNA_TRY(fill_int(wb.ctr.as<int>(), 1, 0, s));
-    for (int step = 0; step < p.nb - 1; ++step) {
-      d.step = step;
+  // the previous upload may still be in flight from this staging buffer
+  TNA_HIP(hipStreamSynchronize(s));
+  std::memcpy(g.host, mats.data(), bytes);
+  TNA_HIP(hipMemcpyAsync(g.desc.ptr, g.host, bytes, hipMemcpyHostToDevice, s));
+  return TNA_OK;
+}
+
+tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps, std::vector<int> &sweeps,
+                         hipStream_t s) {
+  const int nm = (int)mats.size();
+  if (nm == 0) return TNA_OK;
+  sweeps.assign(nm, 0);
+  int max_tiles_load = 0, max_pairs = 0, max_ks = 0, max_tiles = 0, max_steps = 0, max_r4 = 0;
+  for (auto &a : mats) {
+    a.active = 1;
+    max_tiles_load = std::max(max_tiles_load, ceil_div(a.m, 32) * ceil_div(a.n, 32) + ceil_div((int64_t)a.R * a.R, 1024));
+    max_pairs = std::max(max_pairs, a.nb / 2);
+    max_ks = std::max(max_ks, a.ksplit);
+    max_tiles = std::max(max_tiles, ceil_div(a.C, 64) + ceil_div(a.R, 64));
+    max_steps = std::max(max_steps, a.nb - 1);
+    max_r4 = std::max(max_r4, ceil_div(a.R, 4));
+  }
+  TNA_TRY(upload(mats, g, s));
+  const SvdMat *d = g.desc.as<SvdMat>();
+  hipLaunchKernelGGL(load_kernel, dim3(max_tiles_load, 1, nm), dim3(256), 0, s, d);
+  TNA_LAUNCHED("svd.load");
+  if (!g.host_ctr) TNA_HIP(hipHostMalloc((void **)&g.host_ctr, sizeof(int) * 4096, hipHostMallocDefault));
+  if (nm > 4096) {
+    set_error("svd: at most 4096 matrices per group");
+    return TNA_ERR_ARG;
+  }
+  double gram_flops = 0, gram_bytes = 0, apply_flops = 0, apply_bytes = 0;
+  for (auto &a : mats) {
+    const double pairs = a.nb / 2, b2 = 4096.0;
+    gram_flops += 2.0 * b2 * a.C * pairs;
+    gram_bytes += 8.0 * (double)a.R * a.C;
+    apply_flops += 2.0 * b2 * (double)(a.C + a.R) * pairs;
+    apply_bytes += 16.0 * ((double)a.R * a.C + (double)a.R * a.R);
+  }
+  int active = nm;
+  for (int sw = 1; sw <= max_sweeps && active > 0; ++sw) {
+    hipLaunchKernelGGL(zero_ctr_kernel, dim3(ceil_div(nm, 64)), dim3(64), 0, s, d, nm);
+    for (int step = 0; step < max_steps; ++step) {
       timer_begin("svd.gram", s);
-      hipLaunchKernelGGL(gram_kernel, dim3(npairs, p.ksplit, B), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(gram_kernel, dim3(max_pairs, max_ks, nm), dim3(256), 0, s, d, step);
       timer_end("svd.gram", gram_flops, gram_bytes, s);
       timer_begin("svd.eigen", s);
-      hipLaunchKernelGGL(eigen_kernel, dim3(npairs, B), dim3(256), 0, s, d);
-      timer_end("svd.eigen", 0.0, eig_bytes, s);
+      hipLaunchKernelGGL(eigen_kernel, dim3(max_pairs, nm), dim3(256), 0, s, d, step);
+      timer_end("svd.eigen", 0.0, 0.0, s);
       timer_begin("svd.apply", s);
-      hipLaunchKernelGGL(apply_kernel, dim3(npairs, ntile_b + ntile_j, B), dim3(256), 0, s, d, ntile_b);
+      hipLaunchKernelGGL(apply_kernel, dim3(max_pairs, max_tiles, nm), dim3(256), 0, s, d, step);
       timer_end("svd.apply", apply_flops, apply_bytes, s);
     }
-    TNA_LAUNCHED("svd.hip:2");
-    TNA_HIP(hipMemcpyAsync(host_ctr, wb.ctr.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    TNA_LAUNCHED("svd.sweep");
+    for (int z = 0; z < nm; ++z)
+      if (mats[z].active)
+        TNA_HIP(hipMemcpyAsync(g.host_ctr + z, mats[z].ctr, sizeof(int), hipMemcpyDeviceToHost, s));
     TNA_HIP(hipStreamSynchronize(s));
-    if (*host_ctr == 0) {
-      conv = true;
-      break;
+    bool changed = false;
+    for (int z = 0; z < nm; ++z) {
+      if (!mats[z].active) continue;
+      sweeps[z] = sw;
+      if (g.host_ctr[z] == 0) {
+        mats[z].active = 0;
+        --active;
+        changed = true;
+      }
+    }
+    if (changed && active > 0) {
+      TNA_TRY(upload(mats, g, s));
+      max_steps = 0;
+      for (auto &a : mats)
+        if (a.active) max_steps = std::max(max_steps, a.nb - 1);
     }
   }
-  if (sweeps) *sweeps = conv ? sw : max_sweeps;
-  hipLaunchKernelGGL(norms_kernel, dim3(ceil_div(p.R, 4), B), dim3(256), 0, s, wb.bw.as<double>(), p.R, p.C,
-                     wb.sig.as<double>());
-  TNA_LAUNCHED("svd.hip:3");
-  if (!conv) {
-    set_error("svd: Jacobi sweep cap reached");
-    return TNA_ERR_NOCONV;
+  for (auto &a : mats) a.active = 1;  // finishing kernels run on every matrix
+  TNA_TRY(upload(mats, g, s));
+  hipLaunchKernelGGL(norms_kernel, dim3(max_r4, 1, nm), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(sort_kernel, dim3(nm), dim3(1024), 0, s, d);
+  TNA_LAUNCHED("svd.finish");
+  return active > 0 ? TNA_ERR_NOCONV : TNA_OK;
+}
+
+tna_status svd_group_outputs(std::vector<SvdMat> &mats, SvdGroup &g, hipStream_t s) {
+  const int nm = (int)mats.size();
+  if (nm == 0) return TNA_OK;
+  int max_k = 1;
+  int64_t max_el = 1;
+  for (auto &a : mats) {
+    max_k = std::max(max_k, a.k);
+    max_el = std::max<int64_t>(max_el, std::max<int64_t>((int64_t)a.m * a.k, (int64_t)a.k * a.n));
   }
+  TNA_TRY(upload(mats, g, s));
+  const SvdMat *d = g.desc.as<SvdMat>();
+  hipLaunchKernelGGL(trunc_kernel, dim3(nm), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(write_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(max_el, 256), 2048), 2, nm), dim3(256),
+                     0, s, d);
+  hipLaunchKernelGGL(complete_kernel, dim3(nm), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(gauge_kernel, dim3(max_k, 1, nm), dim3(256), 0, s, d);
+  TNA_LAUNCHED("svd.outputs");
   return TNA_OK;
 }
 
-tna_status svd_spectrum(const SvdPlan &p, SvdBuffers &wb, double *S_out, int64_t strideS, double *spec,
-                        hipStream_t s) {
-  int P = 1;
-  while (P < p.R) P <<= 1;
-  hipLaunchKernelGGL(sort_kernel, dim3(p.batch), dim3(1024), 0, s, wb.sig.as<double>(), p.R, P, wb.perm.as<int>(),
-                     S_out, strideS);
-  hipLaunchKernelGGL(entropy_kernel, dim3(p.batch), dim3(256), 0, s, S_out, p.R, strideS, spec);
-  TNA_LAUNCHED("svd.hip:4");
-  return TNA_OK;
-}
-
-tna_status svd_trunc_S(const SvdPlan &p, const double *S, int64_t strideS, int k, double *spec, hipStream_t s) {
-  hipLaunchKernelGGL(trunc_kernel, dim3(p.batch), dim3(256), 0, s, S, p.R, k, strideS, spec);
-  TNA_LAUNCHED("svd.hip:5");
-  return TNA_OK;
-}
-
-tna_status svd_outputs_S(const SvdPlan &p, SvdBuffers &wb, const double *S, int64_t strideS, int k, void *U,
-                         int64_t strideU, void *Vt, int64_t strideVt, int out_type, int scale_mode,
-                         const double *spec, hipStream_t s) {
-  OutDev o;
-  o.R = p.R; o.C = p.C; o.m = p.m; o.n = p.n; o.k = k; o.trans = p.trans;
-  o.bw = wb.bw.as<double>(); o.jt = wb.jt.as<double>(); o.S = S; o.strideS = strideS;
-  o.perm = wb.perm.as<int>(); o.U = U; o.strideU = strideU; o.Vt = Vt; o.strideVt = strideVt;
-  const int B = p.batch;
-  dim3 gu((unsigned)std::min<int64_t>(ceil_div((int64_t)p.m * k, 256), 4096), B);
-  dim3 gv((unsigned)std::min<int64_t>(ceil_div((int64_t)k * p.n, 256), 4096), B);
-  if (out_type == TNA_F64) {
-    hipLaunchKernelGGL(write_u_kernel<double>, gu, dim3(256), 0, s, o);
-    hipLaunchKernelGGL(write_vt_kernel<double>, gv, dim3(256), 0, s, o);
-    hipLaunchKernelGGL(complete_kernel<double>, dim3(B), dim3(256), 0, s, o);
-    hipLaunchKernelGGL(gauge_kernel<double>, dim3(k, B), dim3(256), 0, s, o, scale_mode, spec);
-  } else {
-    hipLaunchKernelGGL(write_u_kernel<float>, gu, dim3(256), 0, s, o);
-    hipLaunchKernelGGL(write_vt_kernel<float>, gv, dim3(256), 0, s, o);
-    hipLaunchKernelGGL(complete_kernel<float>, dim3(B), dim3(256), 0, s, o);
-    hipLaunchKernelGGL(gauge_kernel<float>, dim3(k, B), dim3(256), 0, s, o, scale_mode, spec);
-  }
-  TNA_LAUNCHED("svd.hip:6");
-  return TNA_OK;
-}
-
-tna_status spectrum_entropy(const double *S, int R, double *spec, int batch, int64_t strideS, hipStream_t s) {
-  hipLaunchKernelGGL(entropy_kernel, dim3(batch), dim3(256), 0, s, S, R, strideS, spec);
-  TNA_LAUNCHED("svd.hip:7");
-  return TNA_OK;
-}
-
-tna_status spectrum_trunc(const double *S, int R, int k, double *spec, int batch, int64_t strideS, hipStream_t s) {
-  hipLaunchKernelGGL(trunc_kernel, dim3(batch), dim3(256), 0, s, S, R, k, strideS, spec);
-  TNA_LAUNCHED("svd.hip:8");
-  return TNA_OK;
+void SvdGroup::release() {
+  desc.release();
+  work_d.release();
+  work_i.release();
+  if (host) (void)hipHostFree(host);
+  if (host_ctr) (void)hipHostFree(host_ctr);
+  host = nullptr;
+  host_ctr = nullptr;
+  host_cap = 0;
 }
 
 }  // namespace tna
