@@ -38,7 +38,107 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--roofline-kernel", default="", help="kernel-name prefix to time (default: auto)")
+    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd"], default="heisenberg100")
+    ap.add_argument("--chains", type=int, default=64)
+    ap.add_argument("--svd-batch", type=int, default=1)
+    ap.add_argument("--svd-dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--svd-tau", type=float, default=64.0)
     return ap.parse_args()
+
+
+def roofline_from(stats, dominant):
+    for r in stats:
+        if r["name"] == dominant and r["count"] > 0:
+            avg_ms = r["ms"] / r["count"]
+            fl, by = r["flops"] / r["count"], r["bytes"] / r["count"]
+            if fl > 0 and fl / max(by, 1.0) > 10.0:
+                peak = PEAK["f32_tflops"] if ".f32." in dominant else PEAK["f64_tflops"]
+                ach = fl / (avg_ms * 1e-3) / 1e12
+                roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
+            else:
+                ach = by / (avg_ms * 1e-3) / 1e9
+                roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                        "frac": ach / PEAK["hbm_gbs"]}
+            roof.update({"kernel": dominant, "launches": r["count"], "avg_us": 1e3 * avg_ms,
+                         "flops_per_launch": fl, "bytes_per_launch": by, "traffic": None})
+            return roof
+    return None
+
+
+def run_batch(a):
+    """64 XXZ chains (Delta ~ U[0,2], N from {32,48,64,96,128}) swept together, FP32 H_eff."""
+    import numpy as np
+    import torch
+
+    import paper_2604_03960_amd as tna
+    import synth
+    ctx = tna.Context(0)
+    chains = synth.xxz_chain_set(a.chains, 0)
+    Ws = [tna.mpo_build(tna.MODEL_XXZ, N, [1.0, dlt, 0.0]) for dlt, N in chains]
+    As, chis = [], []
+    for i, (dlt, N) in enumerate(chains):
+        A, chi, _ = synth.random_mps(N, 2, 8, seed=i)
+        As.append(A)
+        chis.append(chi)
+    pid = tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 8, 256)
+    prec = tna.HEFF_F32  # the batched-chain configuration runs the H_eff contractions in FP32
+    bt = tna.DmrgBatch(ctx, Ws, As, chis, pid, heff_prec=prec)
+    for _ in range(a.warmup):
+        bt.sweep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(a.steps):
+        E, per, stats, st = bt.sweep()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Ns = np.array([N for _, N in chains])
+    out = {"metric": "chain-sweeps/s (64 XXZ chains swept together)", "value": a.chains * a.steps / (t1 - t0),
+           "unit": "chain-sweeps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": 1e3 * (t1 - t0) / a.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32-heff+f64", "data": "synthetic",
+           "config": {"workload": f"xxz_batch{a.chains}_N32-128_chi8-256", "chains": a.chains,
+                      "N_total_sites": int(Ns.sum())},
+           "batch_stats": stats, "E_per_site": (E / Ns).tolist()[:8]}
+    print(json.dumps(out))
+
+
+def run_svd(a):
+    """Isolated truncated SVDs of n x n matrices with spectrum exp(-k/tau), keep n/2."""
+    import numpy as np
+    import torch
+
+    import paper_2604_03960_amd as tna
+    import synth
+    ctx = tna.Context(0)
+    n, B = a.svd_n, a.svd_batch
+    dt = torch.float64 if a.svd_dtype == "f64" else torch.float32
+    A = torch.stack([torch.from_numpy(synth.svd_test_matrix(n, a.svd_tau, seed=0, index=i)) for i in range(B)])
+    A = A.to(dt).cuda().contiguous()
+    sig = torch.from_numpy(synth.svd_test_spectrum(n, a.svd_tau)).cuda()
+    run = (lambda: ctx.svd_truncate(A[0], n // 2)) if B == 1 else (lambda: ctx.svd_truncate_batched(A, n // 2))
+    res = run()
+    torch.cuda.synchronize()
+    ctx.set_timing(True, "svd.apply")
+    t0 = time.perf_counter()
+    for _ in range(a.svd_reps):
+        res = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.kernel_stats(reset=True)
+    ctx.set_timing(False)
+    S = res[0]
+    err = (S.reshape(B, -1) - sig[None, :]).abs().max().item()
+    value = B * a.svd_reps / (t1 - t0)
+    nominal = 22.0 * n ** 3  # Golub-Reinsch count with thin U and V
+    out = {"metric": f"SVD/s at chi={n // 2} ({n}x{n}, {a.svd_dtype}, batch {B})", "value": value,
+           "unit": "SVD/s", "n_gpus": 1, "steps": a.svd_reps, "warmup": 1,
+           "ms_per_step": 1e3 * (t1 - t0) / a.svd_reps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": a.svd_dtype, "data": "synthetic",
+           "config": {"workload": f"svd_{n}x{n}_tau{a.svd_tau:g}_batch{B}", "n": n, "tau": a.svd_tau, "batch": B},
+           "max_abs_sigma_err": err, "nominal_tflops": value * nominal / 1e12,
+           "roofline": roofline_from(stats, "svd.apply")}
+    print(json.dumps(out))
 
 
 def main():
@@ -46,6 +146,10 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
+    if a.workload == "xxz_batch":
+        return run_batch(a)
+    if a.workload == "svd":
+        return run_svd(a)
     import numpy as np
     import torch
 
@@ -88,21 +192,7 @@ def main():
     ms_step = 1e3 * (t1 - t0) / a.steps
     chi_fin, _ = dm.state()
 
-    roof = None
-    for r in stats:
-        if r["name"] == dominant and r["count"] > 0:
-            avg_ms = r["ms"] / r["count"]
-            fl, by = r["flops"] / r["count"], r["bytes"] / r["count"]
-            if fl > 0 and fl / max(by, 1.0) > 10.0:
-                peak = PEAK["f64_tflops"] if ("f64" in dominant or dominant.startswith("svd")) else PEAK["f32_tflops"]
-                ach = fl / (avg_ms * 1e-3) / 1e12
-                roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
-            else:
-                ach = by / (avg_ms * 1e-3) / 1e9
-                roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                        "frac": ach / PEAK["hbm_gbs"]}
-            roof.update({"kernel": dominant, "launches": r["count"], "avg_us": 1e3 * avg_ms,
-                         "flops_per_launch": fl, "bytes_per_launch": by, "traffic": None})
+    roof = roofline_from(stats, dominant) if dominant else None
 
     # isolated SVD at chi = 2048 (4096 x 4096, FP64)
     svd = None

@@ -52,6 +52,8 @@ typedef struct tna_ctx_s *tna_ctx;
 /* Creates a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the null stream). */
 tna_status tna_create(tna_ctx *out, int device, void *hip_stream);
+/* Objects made from a context (DMRG runs, batches, networks) must be
+ * destroyed before the context. */
 void tna_destroy(tna_ctx ctx);
 tna_status tna_set_stream(tna_ctx ctx, void *hip_stream);
 /* Waits for all work the context enqueued.  Synchronises. */

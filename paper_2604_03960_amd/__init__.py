@@ -395,6 +395,7 @@ class DmrgBatch:
         _check(_lib.tna_dmrg_batch_create(ctx.h, n, self.N.ctypes.data_as(_ip), d, D, Wp, Ap, Cp, C.byref(pid),
                                           C.byref(self.opts), C.byref(h)))
         self.h, self.n = h, n
+        self.ctx = ctx  # the context must outlive the batch (its chains use its stream)
         self.offsets = np.concatenate([[0], np.cumsum(2 * (self.N - 1))]).astype(np.int64)
 
     def sweep(self):

@@ -145,7 +145,7 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
     int sw = 0;
     SvdMat mat;
     tna_status st = svd_start(dm.get(), m, n, dm->A[b].as<double>(), &mat, &sw);
-    if (st != TNA_OK) return st;
+    if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;  // a capped sweep count still gives a valid gauge
     const int k = R;
     TNA_TRY(svd_finish(dm.get(), mat, k, Ub.ptr, Vb.ptr, 2));
     const int ml = dm->CL(b - 1) * d;

@@ -661,7 +661,10 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
   if (ks > kmax) ks = kmax;
   if (ks < 1) ks = 1;
   a->ksplit = ks;
-  a->tol = (double)a->C * EPS53;
+  // Outer convergence: every off-diagonal |g_ij| <= tol sqrt(g_ii g_jj).  Applying a
+  // 64-row block rotation and re-forming the Gram leave a rounding floor of about
+  // (64 + C) ulps whatever C is, so the bound sits at twice that floor.
+  a->tol = 2.0 * (64.0 + (double)a->C) * EPS53;
   a->active = 1;
   return TNA_OK;
 }
