@@ -77,6 +77,12 @@ void drain_pending() {
 
 bool timing_on() { return g_tm.on; }
 
+bool timing_may_match(const char *name_prefix) {
+  if (!g_tm.on) return false;
+  const size_t a = g_tm.prefix.size(), b = std::strlen(name_prefix);
+  return a == 0 || std::strncmp(g_tm.prefix.c_str(), name_prefix, a < b ? a : b) == 0;
+}
+
 bool timing_wanted(const char *name) {
   if (!g_tm.on) return false;
   return g_tm.prefix.empty() || std::strncmp(name, g_tm.prefix.c_str(), g_tm.prefix.size()) == 0;
@@ -297,73 +303,6 @@ double tridiag_lowest_host(int n, const double *a, const double *b, double *y) {
   return lam;
 }
 
-// ---------------------------------------------------------------- Lanczos
-
-// Lowest eigenpair of H_eff from the start vector in `theta` (overwritten by
-// the normalised Ritz vector).  V holds kmax+1 vectors of length n.
-static tna_status lanczos(tna_ctx c, const HeffOp &op, int64_t n, double *theta, double *V, double tol, int kmax,
-                          int restarts, int fixed_iters, LanczosResult *res) {
-  hipStream_t s = c->stream;
-  double *scal = c->misc.as<double>();  // [0..kmax] h, [kmax+1] beta^2, [kmax+2..] y
-  double *part = c->part.as<double>();
-  double *h1 = scal, *h2 = scal + 128, *nb2 = scal + 256, *ydev = scal + 320, *nrm = scal + 300;
-  if (kmax > 120) kmax = 120;
-  if ((int64_t)kmax > n) kmax = (int)n;
-  if (fixed_iters > 0) kmax = (int)std::min<int64_t>(fixed_iters, std::min<int64_t>(n, 120));
-  std::vector<double> al(kmax + 1), be(kmax + 1), y(kmax + 1);
-  TNA_TRY(norm2(theta, n, nrm, part, s));
-  TNA_TRY(scale(theta, V, n, nrm, 0.0, s));
-  double *hs = c->host_scal;
-  int total = 0;
-  bool conv = false;
-  double E = 0.0;
-  for (int rs = 0; rs <= restarts && !conv; ++rs) {
-    int j = 0, nkeep = 0;
-    for (;;) {
-      double *vj = V + (int64_t)j * n;
-      double *w = V + (int64_t)(j + 1) * n;
-      TNA_TRY(heff_device(op, vj, w, s));
-      ++total;
-      TNA_TRY(multidot(V, n, j + 1, w, n, h1, part, s));
-      TNA_TRY(axpy_multi(V, n, j + 1, h1, w, n, nullptr, part, s));
-      TNA_TRY(multidot(V, n, j + 1, w, n, h2, part, s));
-      TNA_TRY(axpy_multi(V, n, j + 1, h2, w, n, nb2, part, s));
-      TNA_HIP(hipMemcpyAsync(hs, h1 + j, sizeof(double), hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipMemcpyAsync(hs + 1, nb2, sizeof(double), hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipStreamSynchronize(s));
-      al[j] = hs[0];
-      be[j] = std::sqrt(hs[1]);
-      if (!std::isfinite(al[j]) || !std::isfinite(be[j])) {
-        set_error("lanczos: non-finite coefficient");
-        return TNA_ERR_NONFINITE;
-      }
-      const int nn = j + 1;
-      E = tridiag_lowest_host(nn, al.data(), be.data(), y.data());
-      const double resid = std::fabs(be[j] * y[j]);
-      nkeep = nn;
-      if (fixed_iters > 0) {
-        if (nn >= kmax || be[j] < 1e-14) { conv = true; break; }
-      } else {
-        if (resid <= tol * std::max(1.0, std::fabs(E)) || be[j] < 1e-14) { conv = true; break; }
-        if (nn >= kmax) break;
-      }
-      TNA_TRY(scale(w, w, n, nullptr, 1.0 / be[j], s));
-      ++j;
-    }
-    // Ritz vector
-    TNA_HIP(hipMemcpyAsync(ydev, y.data(), sizeof(double) * nkeep, hipMemcpyHostToDevice, s));
-    TNA_TRY(combine(V, n, nkeep, ydev, theta, n, s));
-    TNA_TRY(norm2(theta, n, nrm, part, s));
-    TNA_TRY(scale(theta, theta, n, nrm, 0.0, s));
-    if (!conv) TNA_HIP(hipMemcpyAsync(V, theta, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    TNA_HIP(hipStreamSynchronize(s));  // y is pageable host memory
-  }
-  res->E = E;
-  res->iters = total;
-  res->converged = conv;
-  return TNA_OK;
-}
-
 // ---------------------------------------------------------------- controller
 #pragma clang fp contract(off)
 tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next,
@@ -427,27 +366,6 @@ tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, 
   return TNA_OK;
 }
 #pragma clang fp contract(on)
-
-tna_status heff_lanczos(tna_ctx c, int chl, int chr, int d, int D, const double *L, const double *R,
-                        const double *M12, int prec, double *theta, double *V, double tol, int kmax, int restarts,
-                        int fixed_iters, LanczosResult *res) {
-  hipStream_t s = c->stream;
-  const int64_t nx = (int64_t)D * d * d * chl * chr;
-  const size_t el = prec == TNA_HEFF_F64 ? sizeof(double) : sizeof(float);
-  TNA_TRY(c->x.ensure(el * nx));
-  TNA_TRY(c->z.ensure(el * nx));
-  HeffOp op{chl, chr, d, D, L, R, M12, c->x.ptr, c->z.ptr, prec};
-  if (prec != TNA_HEFF_F64) {
-    const int64_t nl = (int64_t)chl * D * chl, nr = (int64_t)chr * D * chr;
-    TNA_TRY(c->lf.ensure(sizeof(float) * nl));
-    TNA_TRY(c->rf.ensure(sizeof(float) * nr));
-    TNA_TRY(convert_f64_f32(L, c->lf.as<float>(), nl, s));
-    TNA_TRY(convert_f64_f32(R, c->rf.as<float>(), nr, s));
-    op.L = c->lf.ptr;
-    op.R = c->rf.ptr;
-  }
-  return lanczos(c, op, (int64_t)chl * d * d * chr, theta, V, tol, kmax, restarts, fixed_iters, res);
-}
 
 }  // namespace tna
 

@@ -14,6 +14,7 @@
 // Tile shapes of the grouped GEMMs are chosen by a measuring autotuner.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -44,63 +45,87 @@ Autotune g_tune;
 
 int flop_bucket(double f) { return f < 1.0 ? 0 : (int)std::floor(std::log2(f)); }
 
-struct Staging {
+
+// ------------------------------------------------------------------ descriptor arena
+// Descriptors of one step are bump-allocated in a pinned host buffer and
+// copied to the same offset of a device buffer; nothing is reused until the
+// step's final synchronisation, so no upload has to wait for an earlier one.
+struct Arena {
   char *host = nullptr;
-  size_t cap = 0;
   DevBuf dev;
+  size_t cap = 0, off = 0;
 };
 
-tna_status stage_upload(Staging &st, const void *src, size_t bytes, hipStream_t s) {
-  TNA_TRY(st.dev.ensure(bytes));
-  if (st.cap < bytes) {
-    TNA_HIP(hipStreamSynchronize(s));
-    if (st.host) (void)hipHostFree(st.host);
-    st.host = nullptr;
-    TNA_HIP(hipHostMalloc((void **)&st.host, bytes * 2, hipHostMallocDefault));
-    st.cap = bytes * 2;
-  }
-  TNA_HIP(hipStreamSynchronize(s));  // staging buffer may still feed an earlier copy
-  std::memcpy(st.host, src, bytes);
-  TNA_HIP(hipMemcpyAsync(st.dev.ptr, st.host, bytes, hipMemcpyHostToDevice, s));
+tna_status arena_reserve(Arena &a, size_t bytes) {
+  if (a.cap >= bytes) return TNA_OK;
+  if (a.host) (void)hipHostFree(a.host);
+  a.host = nullptr;
+  a.cap = 0;
+  TNA_HIP(hipHostMalloc((void **)&a.host, bytes, hipHostMallocDefault));
+  TNA_TRY(a.dev.ensure(bytes));
+  a.cap = bytes;
   return TNA_OK;
 }
 
-void stage_release(Staging &st) {
-  st.dev.release();
-  if (st.host) (void)hipHostFree(st.host);
-  st.host = nullptr;
-  st.cap = 0;
+template <class T>
+tna_status arena_push(Arena &a, const T *src, size_t n, hipStream_t s, const T **dev_out) {
+  const size_t bytes = sizeof(T) * n;
+  const size_t need = (a.off + bytes + 255) & ~(size_t)255;
+  if (need > a.cap) {
+    // out of room inside a step: wait for the copies in flight, then start over
+    TNA_HIP(hipStreamSynchronize(s));
+    a.off = 0;
+    if (bytes + 256 > a.cap) TNA_TRY(arena_reserve(a, 2 * (bytes + 256)));
+  }
+  char *h = a.host + a.off;
+  char *d = static_cast<char *>(a.dev.ptr) + a.off;
+  std::memcpy(h, src, bytes);
+  TNA_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+  a.off = (a.off + bytes + 255) & ~(size_t)255;
+  *dev_out = reinterpret_cast<const T *>(d);
+  return TNA_OK;
 }
 
-// grouped GEMM with tile choice by the autotuner (kind identifies the operation)
-tna_status tuned_gemm(int kind, GemmGroup g, std::vector<GemmProb> probs, Staging &st, hipStream_t s,
-                      bool allow_measure) {
+void arena_release(Arena &a) {
+  a.dev.release();
+  if (a.host) (void)hipHostFree(a.host);
+  a.host = nullptr;
+  a.cap = a.off = 0;
+}
+
+double group_flops(const std::vector<GemmProb> &probs) {
+  double f = 0.0;
+  for (auto &p : probs) f += 2.0 * p.M * (double)p.N * p.K;
+  return f;
+}
+
+// grouped GEMM with its tile picked by the autotuner (kind names the operation)
+tna_status tuned_gemm(int kind, GemmGroup g, std::vector<GemmProb> probs, Arena &ar, hipStream_t s, bool measure,
+                      int *tile_out = nullptr) {
   if (probs.empty()) return TNA_OK;
-  double fl = 0.0, by = 0.0;
   const int es = g.compute == G_F64 ? 8 : 4;
-  for (auto &p : probs) {
-    fl += 2.0 * p.M * (double)p.N * p.K;
-    by += (double)es * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N);
-  }
-  g.flops = fl;
+  double by = 0.0;
+  for (auto &p : probs) by += (double)es * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N);
+  g.flops = group_flops(probs);
   g.bytes = by;
-  const auto key = std::make_pair(kind, flop_bucket(fl));
+  const auto key = std::make_pair(kind, flop_bucket(g.flops));
   auto it = g_tune.table.find(key);
   int tile = 64;
   if (it != g_tune.table.end()) tile = it->second;
-  else if (allow_measure) {
+  else if (measure) {
     float best = 1e30f;
     for (int cand : {64, 128}) {
       std::vector<GemmProb> pr = probs;
       const int total = gemm_group_tiles(pr, cand);
-      TNA_TRY(stage_upload(st, pr.data(), sizeof(GemmProb) * pr.size(), s));
+      const GemmProb *d = nullptr;
+      TNA_TRY(arena_push(ar, pr.data(), pr.size(), s, &d));
       g.tile = cand;
       hipEvent_t a, b;
       TNA_HIP(hipEventCreate(&a));
       TNA_HIP(hipEventCreate(&b));
-      TNA_TRY(gemm_grouped(g, st.dev.as<GemmProb>(), (int)pr.size(), total, s));  // warm
+      TNA_TRY(gemm_grouped(g, d, (int)pr.size(), total, s));  // warm
       TNA_HIP(hipEventRecord(a, s));
-      TNA_TRY(gemm_grouped(g, st.dev.as<GemmProb>(), (int)pr.size(), total, s));
+      TNA_TRY(gemm_grouped(g, d, (int)pr.size(), total, s));
       TNA_HIP(hipEventRecord(b, s));
       TNA_HIP(hipEventSynchronize(b));
       float ms = 0.f;
@@ -115,10 +140,12 @@ tna_status tuned_gemm(int kind, GemmGroup g, std::vector<GemmProb> probs, Stagin
     g_tune.table[key] = tile;
     g_tune.measured += 1;
   }
+  if (tile_out) *tile_out = tile;
   g.tile = tile;
   const int total = gemm_group_tiles(probs, tile);
-  TNA_TRY(stage_upload(st, probs.data(), sizeof(GemmProb) * probs.size(), s));
-  return gemm_grouped(g, st.dev.as<GemmProb>(), (int)probs.size(), total, s);
+  const GemmProb *d = nullptr;
+  TNA_TRY(arena_push(ar, probs.data(), probs.size(), s, &d));
+  return gemm_grouped(g, d, (int)probs.size(), total, s);
 }
 
 int parts_for(int64_t n) {
@@ -126,29 +153,570 @@ int parts_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 512));
 }
 
+constexpr size_t LZ_SLOT = 128;             // per-chain h1/h2/y/nrm2 slots
+constexpr size_t LZ_PER = 3 * LZ_SLOT + 8;  // doubles per chain before the partials
+constexpr size_t LZ_PART = 128 * 512;       // partial-sum slots per chain and array
+
 }  // namespace
 
-struct tna_dmrg_batch_s {
-  tna_ctx ctx = nullptr;
+// ====================================================================== engine
+// One lockstep step of a set of chains: every chain does one bond visit.
+// Used with a single chain by tna_dmrg_sweep and with many by the batch.
+struct tna_engine_s {
   hipStream_t stream = nullptr;
-  int nch = 0, d = 2, D = 5, prec = 0, kmax = 100, restarts = 5;
-  double tol = 1e-12, eps_target = 1e-8;
-  std::vector<tna_dmrg> ch;
-  std::vector<int> nsteps;
+  int nslot = 0;
   std::vector<DevBuf> V, X, Z, Lf, Rf, T1, T2;
-  DevBuf ints, dbl, lzst;  // per-chain j/active; alpha/beta records; Lanczos scratch arena
-  Staging st_lz, st_g1, st_g2, st_mix, st_cvt, st_misc;
+  DevBuf ints, dbl, lzst, feat_d, y_d;
+  Arena ar;
   SvdGroup svd;
   DevBuf svd_wd, svd_wi, spec, S;
   int *h_ints = nullptr;
   double *h_dbl = nullptr;
-  int sweeps_done = 0;
-  long graph_launches = 0;
+  float *h_feat = nullptr;
+  long graph_launches = 0, lanczos_iters = 0;
+  double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
 };
 
-static const size_t LZ_SLOT = 128;              // per-chain h1/h2/y/nrm2 slots
-static const size_t LZ_PER = 3 * LZ_SLOT + 8;   // doubles per chain before the partials
-static const size_t LZ_PART = 128 * 512;        // partial-sum slots per chain and array
+namespace tna {
+
+tna_status engine_create(int nslot, tna_engine *out) {
+  auto e = std::make_unique<tna_engine_s>();
+  e->nslot = nslot;
+  TNA_HIP(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking));  // default priority
+  e->V.resize(nslot);
+  e->X.resize(nslot);
+  e->Z.resize(nslot);
+  e->Lf.resize(nslot);
+  e->Rf.resize(nslot);
+  e->T1.resize(nslot);
+  e->T2.resize(nslot);
+  TNA_TRY(e->ints.ensure(sizeof(int) * 2 * nslot));
+  TNA_TRY(e->dbl.ensure(sizeof(double) * 2 * nslot));
+  TNA_TRY(e->lzst.ensure(sizeof(double) * (LZ_PER + 2 * LZ_PART) * nslot));
+  TNA_TRY(e->spec.ensure(sizeof(double) * 24 * nslot));
+  TNA_TRY(e->feat_d.ensure(sizeof(float) * 32 * nslot));
+  TNA_TRY(e->y_d.ensure(sizeof(float) * 4 * nslot));
+  TNA_HIP(hipHostMalloc((void **)&e->h_ints, sizeof(int) * 2 * nslot, hipHostMallocDefault));
+  TNA_HIP(hipHostMalloc((void **)&e->h_dbl, sizeof(double) * (24 * nslot + 2 * nslot + 16), hipHostMallocDefault));
+  TNA_HIP(hipHostMalloc((void **)&e->h_feat, sizeof(float) * 32 * nslot, hipHostMallocDefault));
+  TNA_TRY(arena_reserve(e->ar, (size_t)1 << 22));
+  *out = e.release();
+  return TNA_OK;
+}
+
+void engine_destroy(tna_engine e) {
+  if (!e) return;
+  (void)hipStreamSynchronize(e->stream);
+  for (auto *vec : {&e->V, &e->X, &e->Z, &e->Lf, &e->Rf, &e->T1, &e->T2})
+    for (auto &b : *vec) b.release();
+  for (DevBuf *b : {&e->ints, &e->dbl, &e->lzst, &e->feat_d, &e->y_d, &e->svd_wd, &e->svd_wi, &e->spec, &e->S})
+    b->release();
+  arena_release(e->ar);
+  e->svd.release();
+  if (e->h_ints) (void)hipHostFree(e->h_ints);
+  if (e->h_dbl) (void)hipHostFree(e->h_dbl);
+  if (e->h_feat) (void)hipHostFree(e->h_feat);
+  if (e->stream) (void)hipStreamDestroy(e->stream);
+  delete e;
+}
+
+hipStream_t engine_stream(tna_engine e) { return e->stream; }
+void engine_stats(tna_engine e, tna_batch_stats *st) {
+  st->ms_lanczos = e->ms_lanczos;
+  st->ms_svd = e->ms_svd;
+  st->ms_env = e->ms_env;
+  st->lanczos_iters = e->lanczos_iters;
+  st->graph_launches = e->graph_launches;
+  st->autotune_entries = (int)g_tune.table.size();
+}
+
+// Chains ch[q] (slot slot[q]) each visit bond b[q] in direction half[q]
+// (0: left to right, 1: right to left).  Records go to logs[q] (may be null).
+tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std::vector<int> &slot,
+                       const std::vector<int> &bond, const std::vector<int> &half, std::vector<double> &E_out,
+                       std::vector<tna_visit_log *> &logs, tna_status *worst) {
+  hipStream_t s = en->stream;
+  const int nc = (int)ch.size();
+  if (nc == 0) return TNA_OK;
+  const int d = ch[0]->d, D = ch[0]->D;
+  const int I1 = D * d, I2 = D * d * d;
+  const int prec = ch[0]->opts.heff_prec;
+  const bool f32 = prec == TNA_HEFF_F32;
+  en->ar.off = 0;  // the previous step ended with a synchronisation
+  auto t0 = std::chrono::steady_clock::now();
+  struct Visit {
+    int b, half, chl, chm, chr, m, n, kmax, fixed;
+    int64_t nv;
+  };
+  std::vector<Visit> vs(nc);
+  for (int q = 0; q < nc; ++q) {
+    tna_dmrg dm = ch[q];
+    Visit &v = vs[q];
+    const int sl = slot[q];
+    v.b = bond[q];
+    v.half = half[q];
+    v.chl = dm->CL(v.b);
+    v.chm = dm->chi[v.b];
+    v.chr = dm->CR(v.b + 1);
+    v.m = v.chl * d;
+    v.n = d * v.chr;
+    v.nv = (int64_t)v.m * v.n;
+    v.fixed = dm->opts.lanczos_fixed_iters;
+    const int km = v.fixed > 0 ? v.fixed : dm->opts.lanczos_kmax;
+    v.kmax = (int)std::min<int64_t>(std::min(km, 120), v.nv);
+    const size_t el = f32 ? sizeof(float) : sizeof(double);
+    TNA_TRY(en->V[sl].ensure(sizeof(double) * (size_t)(v.kmax + 2) * v.nv));
+    TNA_TRY(en->X[sl].ensure(el * (size_t)D * d * d * v.chl * v.chr));
+    TNA_TRY(en->Z[sl].ensure(el * (size_t)D * d * d * v.chl * v.chr));
+    if (f32) {
+      TNA_TRY(en->Lf[sl].ensure(sizeof(float) * (size_t)v.chl * D * v.chl));
+      TNA_TRY(en->Rf[sl].ensure(sizeof(float) * (size_t)v.chr * D * v.chr));
+    }
+  }
+  int *j_dev = en->ints.as<int>(), *act_dev = j_dev + en->nslot;
+  double *rec_dev = en->dbl.as<double>();
+  auto theta_of = [&](int q) { return en->V[slot[q]].as<double>() + (int64_t)(vs[q].kmax + 1) * vs[q].nv; };
+  // ---- theta = A_b A_{b+1}
+  {
+    GemmGroup g{0, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
+    std::vector<GemmProb> pr;
+    for (int q = 0; q < nc; ++q) {
+      const Visit &v = vs[q];
+      pr.push_back(GemmProb{v.m, v.n, v.chm, v.chm, v.n, v.n, ch[q]->A[v.b].ptr, ch[q]->A[v.b + 1].ptr, theta_of(q),
+                            nullptr, nullptr, nullptr, 0, 0, 0, 0});
+    }
+    TNA_TRY(tuned_gemm(0, g, pr, en->ar, s, true));
+  }
+  if (f32) {
+    std::vector<CvtProb> cv;
+    for (int q = 0; q < nc; ++q) {
+      const Visit &v = vs[q];
+      cv.push_back(CvtProb{ch[q]->Le[v.b].as<double>(), en->Lf[slot[q]].as<float>(), (int64_t)v.chl * D * v.chl});
+      cv.push_back(CvtProb{ch[q]->Re[v.b + 1].as<double>(), en->Rf[slot[q]].as<float>(), (int64_t)v.chr * D * v.chr});
+    }
+    const CvtProb *dc = nullptr;
+    TNA_TRY(arena_push(en->ar, cv.data(), cv.size(), s, &dc));
+    TNA_TRY(convert_grouped(dc, (int)cv.size(), s));
+  }
+  // ---- Lanczos descriptors (slot-indexed j/active flags)
+  std::vector<LzProb> lp(nc);
+  int maxG = 1, maxk = 1;
+  for (int q = 0; q < nc; ++q) {
+    const Visit &v = vs[q];
+    const int sl = slot[q];
+    double *base = en->lzst.as<double>() + (LZ_PER + 2 * LZ_PART) * sl;
+    LzProb &p = lp[q];
+    p.n = v.nv;
+    p.G = parts_for(v.nv);
+    p.nkeep = 0;
+    p.V = en->V[sl].as<double>();
+    p.theta = theta_of(q);
+    p.j = j_dev + sl;
+    p.active = act_dev + sl;
+    p.h1 = base;
+    p.h2 = base + LZ_SLOT;
+    p.y = base + 2 * LZ_SLOT;
+    p.nrm2 = base + 3 * LZ_SLOT;
+    p.part1 = base + LZ_PER;
+    p.part2 = base + LZ_PER + LZ_PART;
+    p.rec = rec_dev + 2 * sl;
+    maxG = std::max(maxG, p.G);
+    maxk = std::max(maxk, v.kmax);
+  }
+  std::vector<GemmProb> s1, s4;
+  std::vector<MixProb> mx;
+  int64_t max_mix = 1;
+  for (int q = 0; q < nc; ++q) {
+    tna_dmrg dm = ch[q];
+    const Visit &v = vs[q];
+    const int sl = slot[q];
+    const void *L = f32 ? (const void *)en->Lf[sl].ptr : dm->Le[v.b].ptr;
+    const void *R = f32 ? (const void *)en->Rf[sl].ptr : dm->Re[v.b + 1].ptr;
+    // S1: X[(a,w)][(s',t',c')] = L[(a,w)][a'] V_j[a'][(s',t',c')]
+    s1.push_back(GemmProb{v.chl * D, d * d * v.chr, v.chl, v.chl, d * d * v.chr, d * d * v.chr, L, lp[q].V,
+                          en->X[sl].ptr, j_dev + sl, nullptr, act_dev + sl, v.nv, 0, 0, 0});
+    // S2: Z[a][(s,t)][w''][c'] = sum W12 X[a][w][(s',t')][c'];  channel strides per (a, c')
+    mx.push_back(MixProb{v.chl, v.chr, en->X[sl].ptr, en->Z[sl].ptr, (int64_t)D * d * d * v.chr, 1,
+                         (int64_t)d * d * D * v.chr, 1, d * d * v.chr, v.chr, D * v.chr, v.chr,
+                         dm->M12.as<double>() + (size_t)I2 * I2 * v.b, act_dev + sl});
+    // S4: V_{j+1}[(a,s,t)][c] = Z[(a,s,t)][(w'',c')] R[c][(w'',c')]
+    s4.push_back(GemmProb{v.chl * d * d, v.chr, D * v.chr, D * v.chr, D * v.chr, v.chr, en->Z[sl].ptr, R,
+                          lp[q].V + v.nv, nullptr, j_dev + sl, act_dev + sl, 0, v.nv, 0, 0});
+    max_mix = std::max<int64_t>(max_mix, (int64_t)v.chl * v.chr);
+  }
+  const int tc = f32 ? G_F32 : G_F64;
+  GemmGroup g1{0, 0, tc, G_F64, tc, tc, 64, 1.0, 0.0, 0.0, 0.0};
+  GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < nc; ++q) {
+    en->h_ints[slot[q]] = 0;
+    en->h_ints[en->nslot + slot[q]] = 1;
+  }
+  TNA_HIP(hipMemcpyAsync(j_dev, en->h_ints, sizeof(int) * 2 * en->nslot, hipMemcpyHostToDevice, s));
+  const LzProb *dlp = nullptr;
+  TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dlp));
+  TNA_TRY(lz_start(dlp, nc, maxG, s));
+  // tile choice for the two H_eff GEMMs, measured before capture (j = 0)
+  int tile1 = 64, tile4 = 64;
+  TNA_TRY(tuned_gemm(1, g1, s1, en->ar, s, true, &tile1));
+  TNA_TRY(tuned_gemm(2, g4, s4, en->ar, s, true, &tile4));
+  const MixProb *dmx = nullptr;
+  TNA_TRY(arena_push(en->ar, mx.data(), nc, s, &dmx));
+  std::vector<GemmProb> p1 = s1, p4 = s4;
+  g1.tile = tile1;
+  g4.tile = tile4;
+  g1.flops = group_flops(s1);
+  g4.flops = group_flops(s4);
+  const int tot1 = gemm_group_tiles(p1, tile1), tot4 = gemm_group_tiles(p4, tile4);
+  const GemmProb *dp1 = nullptr, *dp4 = nullptr;
+  TNA_TRY(arena_push(en->ar, p1.data(), nc, s, &dp1));
+  TNA_TRY(arena_push(en->ar, p4.data(), nc, s, &dp4));
+  // ---- capture one Lanczos iteration (H_eff + CGS2 + record + normalise + advance);
+  // with kernel timing on, the iteration is launched directly instead so that
+  // events can bracket single kernels
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const bool use_graph = !(timing_may_match("gemmg") || timing_may_match("mixg") || timing_may_match("lz."));
+  double lz_bytes = 0.0;  // one CGS pass at the current iteration, all chains (timing only)
+  auto lz_hint = [&](int it) {
+    double b = 0.0;
+    for (int q = 0; q < nc; ++q) b += 8.0 * (double)(std::min(it, vs[q].kmax) + 2) * vs[q].nv;
+    return b;
+  };
+  auto iterate_direct = [&]() -> tna_status {
+    TNA_TRY(gemm_grouped(g1, dp1, nc, tot1, s));
+    TNA_TRY(mix_grouped(dmx, nc, max_mix, D, d * d, d * d, D, f32, s));
+    TNA_TRY(gemm_grouped(g4, dp4, nc, tot4, s));
+    return lz_iteration(dlp, nc, maxG, maxk, lz_bytes, s);
+  };
+  if (use_graph) {
+    TNA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    tna_status cs = gemm_grouped(g1, dp1, nc, tot1, s);
+    if (cs == TNA_OK) cs = mix_grouped(dmx, nc, max_mix, D, d * d, d * d, D, f32, s);
+    if (cs == TNA_OK) cs = gemm_grouped(g4, dp4, nc, tot4, s);
+    if (cs == TNA_OK) cs = lz_iteration(dlp, nc, maxG, maxk, 0.0, s);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (cs != TNA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cs;
+    }
+    if (ce != hipSuccess) {
+      set_error(std::string("graph capture: ") + hipGetErrorString(ce));
+      return TNA_ERR_DEVICE;
+    }
+    hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
+      return TNA_ERR_DEVICE;
+    }
+  }
+  // ---- lockstep Lanczos: replay, read every chain's (alpha_j, beta_j^2), decide on the host
+  std::vector<std::vector<double>> al(nc), be(nc), yv(nc);
+  std::vector<int> conv(nc, 0), nkeep(nc, 0), iters(nc, 0), restart(nc, 0), act(nc, 1);
+  std::vector<double> Ec(nc, 0.0);
+  tna_status lst = TNA_OK;
+  for (;;) {
+    int live = 0;
+    for (int q = 0; q < nc; ++q) live += act[q];
+    if (live == 0) break;
+    hipError_t le = hipSuccess;
+    lz_bytes = lz_hint(iters.empty() ? 0 : *std::max_element(iters.begin(), iters.end()));
+    if (use_graph) le = hipGraphLaunch(gexec, s);
+    else if (iterate_direct() != TNA_OK) le = hipErrorLaunchFailure;
+    if (le == hipSuccess) le = hipMemcpyAsync(en->h_dbl, rec_dev, sizeof(double) * 2 * en->nslot,
+                                              hipMemcpyDeviceToHost, s);
+    if (le == hipSuccess) le = hipStreamSynchronize(s);
+    if (le != hipSuccess) {
+      set_error(std::string("lanczos iteration: ") + hipGetErrorString(le));
+      lst = TNA_ERR_DEVICE;
+      break;
+    }
+    if (use_graph) en->graph_launches += 1;
+    bool changed = false;
+    for (int q = 0; q < nc; ++q) {
+      if (!act[q]) continue;
+      const double a = en->h_dbl[2 * slot[q]], b2 = en->h_dbl[2 * slot[q] + 1];
+      if (!std::isfinite(a) || !std::isfinite(b2)) {
+        set_error("lanczos: non-finite coefficient");
+        lst = TNA_ERR_NONFINITE;
+        break;
+      }
+      al[q].push_back(a);
+      be[q].push_back(std::sqrt(b2));
+      iters[q] += 1;
+      const int nn = (int)al[q].size();
+      yv[q].assign(nn, 0.0);
+      Ec[q] = tridiag_lowest_host(nn, al[q].data(), be[q].data(), yv[q].data());
+      const double resid = std::fabs(be[q][nn - 1] * yv[q][nn - 1]);
+      bool stop = false;
+      if (vs[q].fixed > 0) {
+        if (nn >= vs[q].kmax || be[q][nn - 1] < 1e-14) stop = conv[q] = 1;
+      } else if (resid <= ch[q]->opts.lanczos_tol * std::max(1.0, std::fabs(Ec[q])) || be[q][nn - 1] < 1e-14) {
+        stop = conv[q] = 1;
+      } else if (nn >= vs[q].kmax) {
+        stop = true;
+      }
+      if (stop) {
+        nkeep[q] = nn;
+        act[q] = 0;
+        changed = true;
+      }
+    }
+    if (lst != TNA_OK) break;
+    if (!changed) continue;
+    // chains that stopped at kmax unconverged restart from their Ritz vector
+    std::vector<int> rs(nc, 0);
+    bool any = false;
+    for (int q = 0; q < nc; ++q) {
+      rs[q] = !act[q] && !conv[q] && nkeep[q] > 0 && restart[q] < ch[q]->opts.lanczos_restarts;
+      any = any || rs[q];
+    }
+    if (any) {
+      for (int q = 0; q < nc; ++q) {
+        en->h_ints[en->nslot + slot[q]] = rs[q];
+        lp[q].nkeep = rs[q] ? nkeep[q] : 0;
+        if (rs[q]) TNA_HIP(hipMemcpyAsync(lp[q].y, yv[q].data(), sizeof(double) * nkeep[q], hipMemcpyHostToDevice, s));
+      }
+      TNA_HIP(hipMemcpyAsync(act_dev, en->h_ints + en->nslot, sizeof(int) * en->nslot, hipMemcpyHostToDevice, s));
+      const LzProb *dr = nullptr;
+      TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dr));
+      TNA_TRY(lz_ritz(dr, nc, maxG, s));
+      TNA_TRY(lz_start(dr, nc, maxG, s));
+      for (int q = 0; q < nc; ++q) {
+        if (!rs[q]) continue;
+        restart[q] += 1;
+        al[q].clear();
+        be[q].clear();
+        nkeep[q] = 0;
+        act[q] = 1;
+        en->h_ints[slot[q]] = 0;
+        TNA_HIP(hipMemcpyAsync(j_dev + slot[q], en->h_ints + slot[q], sizeof(int), hipMemcpyHostToDevice, s));
+      }
+    }
+    for (int q = 0; q < nc; ++q) en->h_ints[en->nslot + slot[q]] = act[q];
+    TNA_HIP(hipMemcpyAsync(act_dev, en->h_ints + en->nslot, sizeof(int) * en->nslot, hipMemcpyHostToDevice, s));
+    TNA_HIP(hipStreamSynchronize(s));  // pinned flags are rewritten next round
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (lst != TNA_OK) return lst;
+  // ---- Ritz vectors
+  for (int q = 0; q < nc; ++q) {
+    lp[q].nkeep = nkeep[q];
+    en->h_ints[en->nslot + slot[q]] = 1;
+    en->lanczos_iters += iters[q];
+    if (!conv[q] && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
+    TNA_HIP(hipMemcpyAsync(lp[q].y, yv[q].data(), sizeof(double) * nkeep[q], hipMemcpyHostToDevice, s));
+  }
+  TNA_HIP(hipMemcpyAsync(act_dev, en->h_ints + en->nslot, sizeof(int) * en->nslot, hipMemcpyHostToDevice, s));
+  {
+    const LzProb *dr = nullptr;
+    TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dr));
+    TNA_TRY(lz_ritz(dr, nc, maxG, s));
+  }
+  TNA_HIP(hipStreamSynchronize(s));  // yv (pageable) copies done
+  auto t1 = std::chrono::steady_clock::now();
+  // ---- SVD of every theta, entropy of the full spectra, needed ranks
+  std::vector<SvdMat> mats(nc);
+  size_t nd = 0, ni = 0, ns = 0;
+  for (int q = 0; q < nc; ++q) {
+    TNA_TRY(svd_plan_mat(vs[q].m, vs[q].n, TNA_F64, nc, &mats[q]));
+    nd += svd_work_doubles(mats[q]);
+    ni += svd_work_ints(mats[q]);
+    ns += mats[q].R;
+  }
+  TNA_TRY(en->svd_wd.ensure(sizeof(double) * nd));
+  TNA_TRY(en->svd_wi.ensure(sizeof(int) * ni));
+  TNA_TRY(en->S.ensure(sizeof(double) * ns));
+  std::vector<double *> Sq(nc);
+  {
+    double *dw = en->svd_wd.as<double>(), *sp = en->S.as<double>();
+    int *iw = en->svd_wi.as<int>();
+    for (int q = 0; q < nc; ++q) {
+      SvdMat &a = mats[q];
+      svd_bind_work(&a, dw, iw);
+      dw += svd_work_doubles(a);
+      iw += svd_work_ints(a);
+      a.A = lp[q].theta;
+      a.S = sp;
+      Sq[q] = sp;
+      sp += a.R;
+      a.spec = en->spec.as<double>() + 24 * q;
+      a.eps_target = ch[q]->opts.eps_target > 0 ? ch[q]->opts.eps_target : 1e-8;
+      a.out_type = TNA_F64;
+    }
+  }
+  std::vector<int> sweeps;
+  tna_status sst = svd_group_run(mats, en->svd, ch[0]->opts.svd_max_sweeps, sweeps, s);
+  if (sst != TNA_OK && sst != TNA_ERR_NOCONV) return sst;
+  if (sst == TNA_ERR_NOCONV && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
+  TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
+  TNA_HIP(hipStreamSynchronize(s));
+  // ---- controllers, scheduler inputs, kept ranks
+  std::vector<double> terms(6 * nc);
+  std::vector<int> chi_next(nc), kk(nc), kneed(nc), chs(nc, 0), fb(nc, 0);
+  std::vector<int> want_pred;
+  for (int q = 0; q < nc; ++q) {
+    tna_dmrg dm = ch[q];
+    const Visit &v = vs[q];
+    const double *h = en->h_dbl + 24 * q;
+    const double Sent = h[1];
+    kneed[q] = (int)h[6];
+    TNA_TRY(pid_update(&dm->pid, &dm->st[v.b], Sent, &chi_next[q], &terms[6 * q]));
+    // scheduler inputs: EMA history (oldest first, padded with the oldest),
+    // 16 largest log sigma (floored at ln 1e-16), relative bond position
+    auto &hb = dm->hist[v.b];
+    if (dm->nhist[v.b] < 8) hb[dm->nhist[v.b]++] = terms[6 * q + 4];
+    else {
+      for (int r = 0; r < 7; ++r) hb[r] = hb[r + 1];
+      hb[7] = terms[6 * q + 4];
+    }
+    const int nh = dm->nhist[v.b];
+    float *f = en->h_feat + 32 * q;
+    for (int r = 0; r < 8; ++r) f[r] = (float)hb[r < 8 - nh ? 0 : r - (8 - nh)];
+    const double floor_ln = std::log(1e-16);
+    for (int r = 0; r < 16; ++r) {
+      const double sv = h[8 + r];
+      f[8 + r] = (float)(sv > 0 ? std::max(std::log(sv), floor_ln) : floor_ln);
+    }
+    f[24] = (float)((v.b + 1.0) / dm->N);
+    int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next[q];
+    if (dm->sched && dm->opts.fixed_chi <= 0 && dm->pred[v.b] > 0) {
+      chs[q] = dm->pred[v.b];
+      if (std::min(chs[q], mats[q].R) < std::min(kneed[q], mats[q].R)) fb[q] = 1;  // would miss eps_target
+      else keep = chs[q];
+    }
+    if (dm->sched) want_pred.push_back(q);
+    kk[q] = std::min(keep, mats[q].R);
+  }
+  // proposals for each bond's next visit (one forward per network)
+  if (!want_pred.empty()) {
+    TNA_HIP(hipMemcpyAsync(en->feat_d.ptr, en->h_feat, sizeof(float) * 32 * nc, hipMemcpyHostToDevice, s));
+    for (size_t i = 0; i < want_pred.size(); ++i) {
+      const int q = want_pred[i];
+      TNA_TRY(mlp_forward_dev(ch[q]->sched, 1, en->feat_d.as<float>() + 32 * q, en->y_d.as<float>() + 4 * q));
+    }
+    std::vector<float> yb(4 * nc);
+    TNA_HIP(hipMemcpyAsync(yb.data(), en->y_d.ptr, sizeof(float) * 4 * nc, hipMemcpyDeviceToHost, s));
+    TNA_HIP(hipStreamSynchronize(s));
+    for (int q : want_pred) {
+      tna_dmrg dm = ch[q];
+      const double yv1 = yb[4 * q];
+      double kp = std::isfinite(yv1) ? std::nearbyint(std::exp2(std::min(yv1, 30.0))) : dm->pid.chi_min;
+      kp = std::min<double>(std::max<double>(kp, dm->pid.chi_min), dm->pid.chi_max);
+      dm->pred[vs[q].b] = (int)kp;
+    }
+  }
+  for (int q = 0; q < nc; ++q) {
+    tna_dmrg dm = ch[q];
+    const Visit &v = vs[q];
+    SvdMat &a = mats[q];
+    a.k = kk[q];
+    TNA_TRY(dm->A[v.b].ensure(sizeof(double) * (size_t)v.m * kk[q]));
+    TNA_TRY(dm->A[v.b + 1].ensure(sizeof(double) * (size_t)kk[q] * v.n));
+    a.U = dm->A[v.b].ptr;
+    a.Vt = dm->A[v.b + 1].ptr;
+    a.scale_mode = v.half == 0 ? 1 : 2;
+  }
+  TNA_TRY(svd_group_outputs(mats, en->svd, s));
+  auto t2 = std::chrono::steady_clock::now();
+  // ---- environments: the left one grows on L->R visits, the right one on R->L
+  {
+    std::vector<GemmProb> l1, l3, r1, r3;
+    std::vector<MixProb> lm, rm;
+    int64_t maxl = 1, maxr = 1;
+    for (int q = 0; q < nc; ++q) {
+      tna_dmrg dm = ch[q];
+      const Visit &v = vs[q];
+      const int k = kk[q], sl = slot[q];
+      dm->chi[v.b] = k;
+      if (v.half == 0) {
+        const int chl = v.chl;
+        TNA_TRY(en->T1[sl].ensure(sizeof(double) * (size_t)chl * D * d * k));
+        TNA_TRY(en->T2[sl].ensure(sizeof(double) * (size_t)chl * D * d * k));
+        TNA_TRY(dm->Le[v.b + 1].ensure(sizeof(double) * (size_t)k * D * k));
+        l1.push_back(GemmProb{chl * D, d * k, chl, chl, d * k, d * k, dm->Le[v.b].ptr, dm->A[v.b].ptr, en->T1[sl].ptr,
+                              nullptr, nullptr, nullptr, 0, 0, 0, 0});
+        lm.push_back(MixProb{chl, k, en->T1[sl].ptr, en->T2[sl].ptr, (int64_t)D * d * k, 1, (int64_t)d * D * k, 1,
+                             d * k, k, D * k, k, dm->Ml.as<double>() + (size_t)I1 * I1 * v.b, nullptr});
+        l3.push_back(GemmProb{k, D * k, chl * d, k, D * k, D * k, dm->A[v.b].ptr, en->T2[sl].ptr, dm->Le[v.b + 1].ptr,
+                              nullptr, nullptr, nullptr, 0, 0, 0, 0});
+        maxl = std::max<int64_t>(maxl, (int64_t)chl * k);
+      } else {
+        const int chr = v.chr;
+        TNA_TRY(en->T1[sl].ensure(sizeof(double) * (size_t)chr * D * k * d));
+        TNA_TRY(en->T2[sl].ensure(sizeof(double) * (size_t)chr * D * k * d));
+        TNA_TRY(dm->Re[v.b].ensure(sizeof(double) * (size_t)k * D * k));
+        r1.push_back(GemmProb{chr * D, k * d, chr, chr, chr, k * d, dm->Re[v.b + 1].ptr, dm->A[v.b + 1].ptr,
+                              en->T1[sl].ptr, nullptr, nullptr, nullptr, 0, 0, 0, 0});
+        rm.push_back(MixProb{chr, k, en->T1[sl].ptr, en->T2[sl].ptr, (int64_t)D * k * d, d, (int64_t)D * k, 1, k * d, 1,
+                             chr * D * k, k, dm->Mr.as<double>() + (size_t)I1 * I1 * (v.b + 1), nullptr});
+        r3.push_back(GemmProb{k, D * k, d * chr, d * chr, D * k, D * k, dm->A[v.b + 1].ptr, en->T2[sl].ptr,
+                              dm->Re[v.b].ptr, nullptr, nullptr, nullptr, 0, 0, 0, 0});
+        maxr = std::max<int64_t>(maxr, (int64_t)chr * k);
+      }
+    }
+    GemmGroup nn{0, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
+    GemmGroup nt{0, 1, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
+    GemmGroup tn{1, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
+    if (!l1.empty()) {
+      TNA_TRY(tuned_gemm(3, nn, l1, en->ar, s, true));
+      const MixProb *dm_ = nullptr;
+      TNA_TRY(arena_push(en->ar, lm.data(), lm.size(), s, &dm_));
+      TNA_TRY(mix_grouped(dm_, (int)lm.size(), maxl, D, d, d, D, 0, s));
+      TNA_TRY(tuned_gemm(4, tn, l3, en->ar, s, true));
+    }
+    if (!r1.empty()) {
+      TNA_TRY(tuned_gemm(5, nt, r1, en->ar, s, true));
+      const MixProb *dm_ = nullptr;
+      TNA_TRY(arena_push(en->ar, rm.data(), rm.size(), s, &dm_));
+      TNA_TRY(mix_grouped(dm_, (int)rm.size(), maxr, D, d, d, D, 0, s));
+      TNA_TRY(tuned_gemm(6, nn, r3, en->ar, s, true));
+    }
+  }
+  // per-visit records: truncation sums of the outputs pass and the last kept value
+  TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
+  std::vector<double> slast(nc, 0.0);
+  for (int q = 0; q < nc; ++q)
+    TNA_HIP(hipMemcpyAsync(en->h_dbl + 24 * nc + q, Sq[q] + (kk[q] - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  TNA_HIP(hipStreamSynchronize(s));
+  auto t3 = std::chrono::steady_clock::now();
+  const double mL = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  const double mS = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  const double mE = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  en->ms_lanczos += mL;
+  en->ms_svd += mS;
+  en->ms_env += mE;
+  for (int q = 0; q < nc; ++q) {
+    E_out[q] = Ec[q];
+    tna_visit_log *rp = logs.empty() ? nullptr : logs[q];
+    if (!rp) continue;
+    tna_visit_log &r = *rp;
+    const double *h = en->h_dbl + 24 * q;
+    const double *tm = &terms[6 * q];
+    std::memset(&r, 0, sizeof r);
+    r.sweep = ch[q]->sweeps_done; r.dir = vs[q].half; r.bond = vs[q].b; r.m = vs[q].m; r.n = vs[q].n;
+    r.k = kk[q]; r.chi_ctrl = chi_next[q]; r.lanczos_iters = iters[q]; r.svd_sweeps = sweeps[q];
+    r.lanczos_ok = conv[q]; r.E = Ec[q]; r.S = h[1]; r.S_ema = tm[4]; r.eps = h[2]; r.wdisc = h[3];
+    r.gap = h[5]; r.P = tm[0]; r.I = tm[1]; r.D = tm[2]; r.u = tm[3]; r.sigma0 = h[8];
+    r.sigma_last = en->h_dbl[24 * nc + q];
+    r.ms_lanczos = mL; r.ms_svd = mS; r.ms_other = mE;
+    r.k_needed = kneed[q]; r.chi_sched = chs[q]; r.fallback = fb[q];
+    for (int i = 0; i < 25; ++i) r.feat[i] = en->h_feat[32 * q + i];
+  }
+  return TNA_OK;
+}
+
+}  // namespace tna
+
+// ====================================================================== batch ABI
+struct tna_dmrg_batch_s {
+  tna_ctx ctx = nullptr;
+  tna_engine en = nullptr;
+  std::vector<tna_dmrg> ch;
+  std::vector<int> nsteps;
+  int sweeps_done = 0;
+};
 
 extern "C" {
 
@@ -161,40 +729,21 @@ tna_status tna_dmrg_batch_create(tna_ctx c, int nch, const int *N, int d, int D,
   }
   auto b = std::make_unique<tna_dmrg_batch_s>();
   b->ctx = c;
-  b->nch = nch;
-  b->d = d;
-  b->D = D;
-  tna_dmrg_opts o{};
-  if (opts) o = *opts;
-  b->prec = o.heff_prec;
-  b->tol = o.lanczos_tol > 0 ? o.lanczos_tol : 1e-12;
-  b->kmax = o.lanczos_kmax > 0 ? std::min(o.lanczos_kmax, 120) : 100;
-  b->restarts = o.lanczos_restarts >= 0 ? o.lanczos_restarts : 5;
-  b->eps_target = o.eps_target > 0 ? o.eps_target : 1e-8;
-  if (b->prec != TNA_HEFF_F64 && b->prec != TNA_HEFF_F32) {
-    set_error("dmrg_batch_create: heff_prec must be F64 or F32");
-    return TNA_ERR_ARG;
-  }
-  TNA_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));  // default priority
   for (int i = 0; i < nch; ++i) {
     tna_dmrg dm = nullptr;
-    TNA_TRY(tna_dmrg_create(c, N[i], d, D, W_host[i], A_host[i], chi_init[i], pid, opts, &dm));
+    tna_status st = tna_dmrg_create(c, N[i], d, D, W_host[i], A_host[i], chi_init[i], pid, opts, &dm);
+    if (st != TNA_OK) {
+      for (tna_dmrg x : b->ch) tna_dmrg_destroy(x);
+      return st;
+    }
     b->ch.push_back(dm);
     b->nsteps.push_back(2 * (N[i] - 1));
   }
-  b->V.resize(nch);
-  b->X.resize(nch);
-  b->Z.resize(nch);
-  b->Lf.resize(nch);
-  b->Rf.resize(nch);
-  b->T1.resize(nch);
-  b->T2.resize(nch);
-  TNA_TRY(b->ints.ensure(sizeof(int) * 2 * nch));
-  TNA_TRY(b->dbl.ensure(sizeof(double) * 2 * nch));
-  TNA_TRY(b->lzst.ensure(sizeof(double) * (LZ_PER + 2 * LZ_PART) * nch));
-  TNA_HIP(hipHostMalloc((void **)&b->h_ints, sizeof(int) * 2 * nch, hipHostMallocDefault));
-  TNA_HIP(hipHostMalloc((void **)&b->h_dbl, sizeof(double) * (24 * nch + 2 * nch + 16), hipHostMallocDefault));
-  TNA_TRY(b->spec.ensure(sizeof(double) * 24 * nch));
+  tna_status st = engine_create(nch, &b->en);
+  if (st != TNA_OK) {
+    for (tna_dmrg x : b->ch) tna_dmrg_destroy(x);
+    return st;
+  }
   *out = b.release();
   return TNA_OK;
 }
@@ -205,407 +754,44 @@ tna_status tna_dmrg_batch_sweep(tna_dmrg_batch bt, double *E_out, tna_visit_log 
     set_error("dmrg_batch_sweep: null handle");
     return TNA_ERR_ARG;
   }
-  hipStream_t s = bt->stream;
-  const int nch = bt->nch, d = bt->d, D = bt->D;
-  const bool f32 = bt->prec == TNA_HEFF_F32;
-  const int I1 = D * d, I2 = D * d * d;
+  const int nch = (int)bt->ch.size();
   int maxsteps = 0;
   for (int v : bt->nsteps) maxsteps = std::max(maxsteps, v);
   std::vector<double> E(nch, 0.0);
   tna_status worst = TNA_OK;
-  int *j_dev = bt->ints.as<int>(), *act_dev = j_dev + nch;
-  double *rec_dev = bt->dbl.as<double>();
-  double *lz = bt->lzst.as<double>();
   auto t_start = std::chrono::steady_clock::now();
-  double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
-  long iters_total = 0;
+  TNA_HIP(hipStreamSynchronize(bt->ctx->stream));  // work the caller queued on the context stream
   for (int t = 0; t < maxsteps; ++t) {
-    auto t0 = std::chrono::steady_clock::now();
-    // ---- chains taking part in this step and their bond
-    std::vector<int> cs;
-    for (int i = 0; i < nch; ++i)
-      if (t < bt->nsteps[i]) cs.push_back(i);
-    const int nc = (int)cs.size();
-    if (nc == 0) break;
-    struct Visit {
-      int b, half, chl, chm, chr, m, n, kmax;
-      int64_t nv;
-    };
-    std::vector<Visit> vs(nc);
-    for (int q = 0; q < nc; ++q) {
-      tna_dmrg dm = bt->ch[cs[q]];
-      const int N = dm->N;
-      Visit &v = vs[q];
-      v.half = t < N - 1 ? 0 : 1;
-      v.b = v.half == 0 ? t : (N - 2) - (t - (N - 1));
-      v.chl = dm->CL(v.b);
-      v.chm = dm->chi[v.b];
-      v.chr = dm->CR(v.b + 1);
-      v.m = v.chl * d;
-      v.n = d * v.chr;
-      v.nv = (int64_t)v.m * v.n;
-      v.kmax = (int)std::min<int64_t>(bt->kmax, v.nv);
-      const size_t el = f32 ? sizeof(float) : sizeof(double);
-      TNA_TRY(bt->V[q].ensure(sizeof(double) * (size_t)(v.kmax + 2) * v.nv));
-      TNA_TRY(bt->X[q].ensure(el * (size_t)D * d * d * v.chl * v.chr));
-      TNA_TRY(bt->Z[q].ensure(el * (size_t)D * d * d * v.chl * v.chr));
-      if (f32) {
-        TNA_TRY(bt->Lf[q].ensure(sizeof(float) * (size_t)v.chl * D * v.chl));
-        TNA_TRY(bt->Rf[q].ensure(sizeof(float) * (size_t)v.chr * D * v.chr));
-      }
+    std::vector<tna_dmrg> cs;
+    std::vector<int> slot, bond, half;
+    std::vector<tna_visit_log *> lg;
+    for (int i = 0; i < nch; ++i) {
+      if (t >= bt->nsteps[i]) continue;
+      const int N = bt->ch[i]->N;
+      const int h = t < N - 1 ? 0 : 1;
+      cs.push_back(bt->ch[i]);
+      slot.push_back(i);
+      half.push_back(h);
+      bond.push_back(h == 0 ? t : (N - 2) - (t - (N - 1)));
+      if (logs && log_offsets) lg.push_back(logs + log_offsets[i] + t);
     }
-    auto theta_of = [&](int q) { return bt->V[q].as<double>() + (int64_t)(vs[q].kmax + 1) * vs[q].nv; };
-    // ---- theta = A_b A_{b+1}
-    {
-      GemmGroup g{0, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
-      std::vector<GemmProb> pr;
-      for (int q = 0; q < nc; ++q) {
-        tna_dmrg dm = bt->ch[cs[q]];
-        const Visit &v = vs[q];
-        pr.push_back(GemmProb{v.m, v.n, v.chm, v.chm, v.n, v.n, dm->A[v.b].ptr, dm->A[v.b + 1].ptr, theta_of(q),
-                              nullptr, nullptr, nullptr, 0, 0, 0, 0});
-      }
-      TNA_TRY(tuned_gemm(0, g, pr, bt->st_misc, s, true));
-    }
-    if (f32) {
-      std::vector<CvtProb> cv;
-      for (int q = 0; q < nc; ++q) {
-        tna_dmrg dm = bt->ch[cs[q]];
-        const Visit &v = vs[q];
-        cv.push_back(CvtProb{dm->Le[v.b].as<double>(), bt->Lf[q].as<float>(), (int64_t)v.chl * D * v.chl});
-        cv.push_back(CvtProb{dm->Re[v.b + 1].as<double>(), bt->Rf[q].as<float>(), (int64_t)v.chr * D * v.chr});
-      }
-      TNA_TRY(stage_upload(bt->st_cvt, cv.data(), sizeof(CvtProb) * cv.size(), s));
-      TNA_TRY(convert_grouped(bt->st_cvt.dev.as<CvtProb>(), (int)cv.size(), s));
-    }
-    // ---- Lanczos descriptors
-    std::vector<LzProb> lp(nc);
-    int maxG = 1, maxk = 1;
-    for (int q = 0; q < nc; ++q) {
-      const Visit &v = vs[q];
-      double *base = lz + (LZ_PER + 2 * LZ_PART) * q;
-      LzProb &p = lp[q];
-      p.n = v.nv;
-      p.G = parts_for(v.nv);
-      p.nkeep = 0;
-      p.V = bt->V[q].as<double>();
-      p.theta = theta_of(q);
-      p.j = j_dev + q;
-      p.active = act_dev + q;
-      p.h1 = base;
-      p.h2 = base + LZ_SLOT;
-      p.y = base + 2 * LZ_SLOT;
-      p.nrm2 = base + 3 * LZ_SLOT;
-      p.part1 = base + LZ_PER;
-      p.part2 = base + LZ_PER + LZ_PART;
-      p.rec = rec_dev + 2 * q;
-      maxG = std::max(maxG, p.G);
-      maxk = std::max(maxk, v.kmax);
-    }
-    // H_eff group descriptors (operand offsets follow each chain's j on the device)
-    std::vector<GemmProb> s1, s4;
-    std::vector<MixProb> mx;
-    int64_t max_mix = 1;
-    for (int q = 0; q < nc; ++q) {
-      tna_dmrg dm = bt->ch[cs[q]];
-      const Visit &v = vs[q];
-      const void *L = f32 ? (const void *)bt->Lf[q].ptr : dm->Le[v.b].ptr;
-      const void *R = f32 ? (const void *)bt->Rf[q].ptr : dm->Re[v.b + 1].ptr;
-      s1.push_back(GemmProb{v.chl * D, d * d * v.chr, v.chl, v.chl, d * d * v.chr, d * d * v.chr, L, lp[q].V,
-                            bt->X[q].ptr, j_dev + q, nullptr, act_dev + q, v.nv, 0, 0, 0});
-      mx.push_back(MixProb{v.chl, v.chr, bt->X[q].ptr, bt->Z[q].ptr, (int64_t)D * d * d * v.chr, 1,
-                           (int64_t)d * d * D * v.chr, 1, d * d * v.chr, v.chr, d * D * v.chr, v.chr,
-                           dm->M12.as<double>() + (size_t)I2 * I2 * v.b, act_dev + q});
-      // Z channels: j = (s*d + t)*D + w''  -> offset (s*d + t)*D*chr + w''*chr; J1 = d*d, J2 = D
-      mx.back().och1 = D * v.chr;
-      mx.back().och2 = v.chr;
-      s4.push_back(GemmProb{v.chl * d * d, v.chr, D * v.chr, D * v.chr, D * v.chr, v.chr, bt->Z[q].ptr, R,
-                            lp[q].V + v.nv, nullptr, j_dev + q, act_dev + q, 0, v.nv, 0, 0});
-      max_mix = std::max<int64_t>(max_mix, (int64_t)v.chl * v.chr);
-    }
-    // input channels of the two-site mixing: i = w*d^2 + (s'*d + t') -> w*d*d*chr + (s'*d+t')*chr
-    for (auto &m : mx) {
-      m.ich1 = d * d * m.n1;
-      m.ich2 = m.n1;
-    }
-    const int tc = f32 ? G_F32 : G_F64;
-    GemmGroup g1{0, 0, tc, G_F64, tc, tc, 64, 1.0, 0.0, 0.0, 0.0};
-    GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, 0.0, 0.0, 0.0};
-    // ---- start: j = 0, every chain of the step active, V_0 = theta/|theta|
-    for (int q = 0; q < nc; ++q) {
-      bt->h_ints[q] = 0;
-      bt->h_ints[nch + q] = 1;
-    }
-    TNA_HIP(hipMemcpyAsync(j_dev, bt->h_ints, sizeof(int) * 2 * nch, hipMemcpyHostToDevice, s));
-    std::vector<int> h_act(nc, 1);
-    TNA_TRY(stage_upload(bt->st_lz, lp.data(), sizeof(LzProb) * nc, s));
-    const LzProb *dlp = bt->st_lz.dev.as<LzProb>();
-    // tile choice for the two H_eff GEMMs (measured with j = 0 before capture)
-    TNA_TRY(lz_start(dlp, nc, maxG, s));
-    TNA_TRY(tuned_gemm(1, g1, s1, bt->st_g1, s, true));
-    TNA_TRY(tuned_gemm(2, g4, s4, bt->st_g2, s, true));
-    TNA_TRY(stage_upload(bt->st_mix, mx.data(), sizeof(MixProb) * nc, s));
-    // capture one Lanczos iteration
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    {
-      std::vector<GemmProb> p1 = s1, p4 = s4;
-      double f1 = 0, f4 = 0;
-      for (auto &p : s1) f1 += 2.0 * p.M * (double)p.N * p.K;
-      for (auto &p : s4) f4 += 2.0 * p.M * (double)p.N * p.K;
-      g1.tile = g_tune.table.count(std::make_pair(1, flop_bucket(f1))) ? g_tune.table[std::make_pair(1, flop_bucket(f1))] : 64;
-      g4.tile = g_tune.table.count(std::make_pair(2, flop_bucket(f4))) ? g_tune.table[std::make_pair(2, flop_bucket(f4))] : 64;
-      g1.flops = f1;
-      g4.flops = f4;
-      const int tot1 = gemm_group_tiles(p1, g1.tile), tot4 = gemm_group_tiles(p4, g4.tile);
-      TNA_TRY(stage_upload(bt->st_g1, p1.data(), sizeof(GemmProb) * nc, s));
-      TNA_TRY(stage_upload(bt->st_g2, p4.data(), sizeof(GemmProb) * nc, s));
-      TNA_HIP(hipStreamSynchronize(s));
-      TNA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      tna_status cs1 = gemm_grouped(g1, bt->st_g1.dev.as<GemmProb>(), nc, tot1, s);
-      if (cs1 == TNA_OK) cs1 = mix_grouped(bt->st_mix.dev.as<MixProb>(), nc, max_mix, D, d * d, d * d, D, f32, s);
-      if (cs1 == TNA_OK) cs1 = gemm_grouped(g4, bt->st_g2.dev.as<GemmProb>(), nc, tot4, s);
-      if (cs1 == TNA_OK) cs1 = lz_iteration(dlp, nc, maxG, maxk, s);
-      hipError_t ce = hipStreamEndCapture(s, &graph);
-      if (cs1 != TNA_OK) return cs1;
-      if (ce != hipSuccess) {
-        set_error(std::string("graph capture: ") + hipGetErrorString(ce));
-        return TNA_ERR_DEVICE;
-      }
-      TNA_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-    }
-    // ---- lockstep Lanczos
-    std::vector<std::vector<double>> al(nc), be(nc), yv(nc);
-    std::vector<int> conv(nc, 0), nkeep(nc, 0), iters(nc, 0), restart(nc, 0);
-    std::vector<double> Ec(nc, 0.0);
-    for (;;) {
-      int live = 0;
-      for (int q = 0; q < nc; ++q) live += h_act[q];
-      if (live == 0) break;
-      TNA_HIP(hipGraphLaunch(gexec, s));
-      bt->graph_launches += 1;
-      TNA_HIP(hipMemcpyAsync(bt->h_dbl, rec_dev, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipStreamSynchronize(s));
-      bool act_changed = false;
-      for (int q = 0; q < nc; ++q) {
-        if (!h_act[q]) continue;
-        const double a = bt->h_dbl[2 * q], b2 = bt->h_dbl[2 * q + 1];
-        if (!std::isfinite(a) || !std::isfinite(b2)) {
-          set_error("batch lanczos: non-finite coefficient");
-          return TNA_ERR_NONFINITE;
-        }
-        al[q].push_back(a);
-        be[q].push_back(std::sqrt(b2));
-        iters[q] += 1;
-        const int nn = (int)al[q].size();
-        yv[q].assign(nn, 0.0);
-        Ec[q] = tridiag_lowest_host(nn, al[q].data(), be[q].data(), yv[q].data());
-        const double resid = std::fabs(be[q][nn - 1] * yv[q][nn - 1]);
-        bool stop = false;
-        if (resid <= bt->tol * std::max(1.0, std::fabs(Ec[q])) || be[q][nn - 1] < 1e-14) {
-          conv[q] = 1;
-          stop = true;
-        } else if (nn >= vs[q].kmax) {
-          stop = true;
-        }
-        if (stop) {
-          nkeep[q] = nn;
-          h_act[q] = 0;
-          act_changed = true;
-        }
-      }
-      if (!act_changed) continue;
-      // chains that stopped at kmax unconverged restart from their Ritz vector
-      std::vector<int> rs(nc, 0);
-      bool any_restart = false;
-      for (int q = 0; q < nc; ++q) {
-        rs[q] = !h_act[q] && !conv[q] && nkeep[q] > 0 && restart[q] < bt->restarts;
-        any_restart = any_restart || rs[q];
-      }
-      if (any_restart) {
-        for (int q = 0; q < nc; ++q) {
-          bt->h_ints[nch + q] = rs[q];  // only restarting chains take part in the Ritz step
-          lp[q].nkeep = rs[q] ? nkeep[q] : 0;
-          if (rs[q]) TNA_HIP(hipMemcpyAsync(lp[q].y, yv[q].data(), sizeof(double) * nkeep[q], hipMemcpyHostToDevice, s));
-        }
-        TNA_HIP(hipMemcpyAsync(act_dev, bt->h_ints + nch, sizeof(int) * nch, hipMemcpyHostToDevice, s));
-        TNA_TRY(stage_upload(bt->st_lz, lp.data(), sizeof(LzProb) * nc, s));
-        TNA_TRY(lz_ritz(dlp, nc, maxG, s));
-        TNA_TRY(lz_start(dlp, nc, maxG, s));
-        for (int q = 0; q < nc; ++q) {
-          if (!rs[q]) continue;
-          restart[q] += 1;
-          al[q].clear();
-          be[q].clear();
-          nkeep[q] = 0;
-          h_act[q] = 1;
-          bt->h_ints[q] = 0;  // j = 0
-          TNA_HIP(hipMemcpyAsync(j_dev + q, bt->h_ints + q, sizeof(int), hipMemcpyHostToDevice, s));
-        }
-      }
-      for (int q = 0; q < nc; ++q) bt->h_ints[nch + q] = h_act[q];
-      TNA_HIP(hipMemcpyAsync(act_dev, bt->h_ints + nch, sizeof(int) * nch, hipMemcpyHostToDevice, s));
-      TNA_HIP(hipStreamSynchronize(s));
-    }
-    (void)hipGraphExecDestroy(gexec);
-    (void)hipGraphDestroy(graph);
-    // ---- Ritz vectors of every chain of the step
-    for (int q = 0; q < nc; ++q) {
-      lp[q].nkeep = nkeep[q];
-      bt->h_ints[nch + q] = 1;
-      iters_total += iters[q];
-      if (!conv[q] && worst == TNA_OK) worst = TNA_ERR_NOCONV;
-      TNA_HIP(hipMemcpyAsync(lp[q].y, yv[q].data(), sizeof(double) * nkeep[q], hipMemcpyHostToDevice, s));
-    }
-    TNA_HIP(hipMemcpyAsync(act_dev, bt->h_ints + nch, sizeof(int) * nch, hipMemcpyHostToDevice, s));
-    TNA_TRY(stage_upload(bt->st_lz, lp.data(), sizeof(LzProb) * nc, s));
-    TNA_TRY(lz_ritz(dlp, nc, maxG, s));
-    auto t1 = std::chrono::steady_clock::now();
-    // ---- SVD of every theta
-    std::vector<SvdMat> mats(nc);
-    size_t nd = 0, ni = 0, ns = 0;
-    for (int q = 0; q < nc; ++q) {
-      TNA_TRY(svd_plan_mat(vs[q].m, vs[q].n, TNA_F64, nc, &mats[q]));
-      nd += svd_work_doubles(mats[q]);
-      ni += svd_work_ints(mats[q]);
-      ns += mats[q].R;
-    }
-    TNA_TRY(bt->svd_wd.ensure(sizeof(double) * nd));
-    TNA_TRY(bt->svd_wi.ensure(sizeof(int) * ni));
-    TNA_TRY(bt->S.ensure(sizeof(double) * ns));
-    {
-      double *dw = bt->svd_wd.as<double>(), *sp = bt->S.as<double>();
-      int *iw = bt->svd_wi.as<int>();
-      for (int q = 0; q < nc; ++q) {
-        SvdMat &a = mats[q];
-        svd_bind_work(&a, dw, iw);
-        dw += svd_work_doubles(a);
-        iw += svd_work_ints(a);
-        a.A = lp[q].theta;
-        a.S = sp;
-        sp += a.R;
-        a.spec = bt->spec.as<double>() + 24 * q;
-        a.eps_target = bt->eps_target;
-        a.out_type = TNA_F64;
-      }
-    }
-    std::vector<int> sweeps;
-    tna_status sst = svd_group_run(mats, bt->svd, 60, sweeps, s);
-    if (sst != TNA_OK && sst != TNA_ERR_NOCONV) return sst;
-    if (sst == TNA_ERR_NOCONV && worst == TNA_OK) worst = TNA_ERR_NOCONV;
-    TNA_HIP(hipMemcpyAsync(bt->h_dbl, bt->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
-    TNA_HIP(hipStreamSynchronize(s));
-    std::vector<double> terms(6 * nc);
-    std::vector<int> chi_next(nc), kk(nc);
-    for (int q = 0; q < nc; ++q) {
-      tna_dmrg dm = bt->ch[cs[q]];
-      const double Sent = bt->h_dbl[24 * q + 1];
-      TNA_TRY(pid_update(&dm->pid, &dm->st[vs[q].b], Sent, &chi_next[q], &terms[6 * q]));
-      const int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next[q];
-      kk[q] = std::min(keep, mats[q].R);
-      SvdMat &a = mats[q];
-      a.k = kk[q];
-      TNA_TRY(dm->A[vs[q].b].ensure(sizeof(double) * (size_t)vs[q].m * kk[q]));
-      TNA_TRY(dm->A[vs[q].b + 1].ensure(sizeof(double) * (size_t)kk[q] * vs[q].n));
-      a.U = dm->A[vs[q].b].ptr;
-      a.Vt = dm->A[vs[q].b + 1].ptr;
-      a.scale_mode = vs[q].half == 0 ? 1 : 2;
-    }
-    TNA_TRY(svd_group_outputs(mats, bt->svd, s));
-    auto t2 = std::chrono::steady_clock::now();
-    // ---- environments: left grows for L->R chains, right for R->L chains
-    {
-      std::vector<GemmProb> l1, l3, r1, r3;
-      std::vector<MixProb> lm, rm;
-      int64_t maxl = 1, maxr = 1;
-      for (int q = 0; q < nc; ++q) {
-        tna_dmrg dm = bt->ch[cs[q]];
-        const Visit &v = vs[q];
-        const int k = kk[q];
-        dm->chi[v.b] = k;
-        if (v.half == 0) {
-          const int chl = v.chl;
-          TNA_TRY(bt->T1[q].ensure(sizeof(double) * (size_t)chl * D * d * k));
-          TNA_TRY(bt->T2[q].ensure(sizeof(double) * (size_t)chl * D * d * k));
-          TNA_TRY(dm->Le[v.b + 1].ensure(sizeof(double) * (size_t)k * D * k));
-          l1.push_back(GemmProb{chl * D, d * k, chl, chl, d * k, d * k, dm->Le[v.b].ptr, dm->A[v.b].ptr, bt->T1[q].ptr,
-                                nullptr, nullptr, nullptr, 0, 0, 0, 0});
-          lm.push_back(MixProb{chl, k, bt->T1[q].ptr, bt->T2[q].ptr, (int64_t)D * d * k, 1, (int64_t)d * D * k, 1,
-                               d * k, k, D * k, k, dm->Ml.as<double>() + (size_t)I1 * I1 * v.b, nullptr});
-          l3.push_back(GemmProb{k, D * k, chl * d, k, D * k, D * k, dm->A[v.b].ptr, bt->T2[q].ptr,
-                                dm->Le[v.b + 1].ptr, nullptr, nullptr, nullptr, 0, 0, 0, 0});
-          maxl = std::max<int64_t>(maxl, (int64_t)chl * k);
-        } else {
-          const int chr = v.chr;
-          TNA_TRY(bt->T1[q].ensure(sizeof(double) * (size_t)chr * D * k * d));
-          TNA_TRY(bt->T2[q].ensure(sizeof(double) * (size_t)chr * D * k * d));
-          TNA_TRY(dm->Re[v.b].ensure(sizeof(double) * (size_t)k * D * k));
-          r1.push_back(GemmProb{chr * D, k * d, chr, chr, chr, k * d, dm->Re[v.b + 1].ptr, dm->A[v.b + 1].ptr,
-                                bt->T1[q].ptr, nullptr, nullptr, nullptr, 0, 0, 0, 0});
-          rm.push_back(MixProb{chr, k, bt->T1[q].ptr, bt->T2[q].ptr, (int64_t)D * k * d, d, (int64_t)D * k, 1, k * d,
-                               1, chr * D * k, k, dm->Mr.as<double>() + (size_t)I1 * I1 * (v.b + 1), nullptr});
-          r3.push_back(GemmProb{k, D * k, d * chr, d * chr, D * k, D * k, dm->A[v.b + 1].ptr, bt->T2[q].ptr,
-                                dm->Re[v.b].ptr, nullptr, nullptr, nullptr, 0, 0, 0, 0});
-          maxr = std::max<int64_t>(maxr, (int64_t)chr * k);
-        }
-      }
-      GemmGroup nn{0, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
-      GemmGroup nt{0, 1, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
-      GemmGroup tn{1, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
-      if (!l1.empty()) {
-        TNA_TRY(tuned_gemm(3, nn, l1, bt->st_misc, s, true));
-        TNA_TRY(stage_upload(bt->st_mix, lm.data(), sizeof(MixProb) * lm.size(), s));
-        TNA_TRY(mix_grouped(bt->st_mix.dev.as<MixProb>(), (int)lm.size(), maxl, D, d, d, D, 0, s));
-        TNA_TRY(tuned_gemm(4, tn, l3, bt->st_misc, s, true));
-      }
-      if (!r1.empty()) {
-        TNA_TRY(tuned_gemm(5, nt, r1, bt->st_misc, s, true));
-        TNA_TRY(stage_upload(bt->st_mix, rm.data(), sizeof(MixProb) * rm.size(), s));
-        TNA_TRY(mix_grouped(bt->st_mix.dev.as<MixProb>(), (int)rm.size(), maxr, D, d, d, D, 0, s));
-        TNA_TRY(tuned_gemm(6, nn, r3, bt->st_misc, s, true));
-      }
-    }
-    // per-visit records (truncation sums of the outputs pass)
-    TNA_HIP(hipMemcpyAsync(bt->h_dbl, bt->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
-    TNA_HIP(hipStreamSynchronize(s));
-    auto t3 = std::chrono::steady_clock::now();
-    ms_lanczos += std::chrono::duration<double, std::milli>(t1 - t0).count();
-    ms_svd += std::chrono::duration<double, std::milli>(t2 - t1).count();
-    ms_env += std::chrono::duration<double, std::milli>(t3 - t2).count();
-    for (int q = 0; q < nc; ++q) {
-      const int cidx = cs[q];
-      E[cidx] = Ec[q];
-      if (logs && log_offsets) {
-        tna_visit_log &r = logs[log_offsets[cidx] + t];
-        const double *h = bt->h_dbl + 24 * q;
-        const double *tm = &terms[6 * q];
-        std::memset(&r, 0, sizeof r);
-        r.sweep = bt->sweeps_done; r.dir = vs[q].half; r.bond = vs[q].b; r.m = vs[q].m; r.n = vs[q].n;
-        r.k = kk[q]; r.chi_ctrl = chi_next[q]; r.lanczos_iters = iters[q]; r.svd_sweeps = sweeps[q];
-        r.lanczos_ok = conv[q]; r.E = Ec[q]; r.S = h[1]; r.S_ema = tm[4]; r.eps = h[2]; r.wdisc = h[3];
-        r.gap = h[5]; r.P = tm[0]; r.I = tm[1]; r.D = tm[2]; r.u = tm[3]; r.sigma0 = h[8];
-        r.k_needed = (int)h[6];
-      }
-    }
+    std::vector<double> Es(cs.size());
+    TNA_TRY(engine_step(bt->en, cs, slot, bond, half, Es, lg, &worst));
+    for (size_t q = 0; q < cs.size(); ++q) E[slot[q]] = Es[q];
   }
   for (tna_dmrg dm : bt->ch) dm->sweeps_done += 1;
   bt->sweeps_done += 1;
   if (E_out) std::memcpy(E_out, E.data(), sizeof(double) * nch);
   if (stats) {
+    engine_stats(bt->en, stats);
     stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    stats->ms_lanczos = ms_lanczos;
-    stats->ms_svd = ms_svd;
-    stats->ms_env = ms_env;
-    stats->lanczos_iters = iters_total;
-    stats->graph_launches = bt->graph_launches;
-    stats->autotune_entries = (int)g_tune.table.size();
     stats->steps = maxsteps;
   }
   return worst;
 }
 
 tna_status tna_dmrg_batch_get_state(tna_dmrg_batch bt, int chain, int *chi, tna_pid_state *pid) {
-  if (!bt || chain < 0 || chain >= bt->nch) {
+  if (!bt || chain < 0 || chain >= (int)bt->ch.size()) {
     set_error("dmrg_batch_get_state: bad chain");
     return TNA_ERR_ARG;
   }
@@ -614,16 +800,8 @@ tna_status tna_dmrg_batch_get_state(tna_dmrg_batch bt, int chain, int *chi, tna_
 
 void tna_dmrg_batch_destroy(tna_dmrg_batch bt) {
   if (!bt) return;
-  (void)hipStreamSynchronize(bt->stream);
+  engine_destroy(bt->en);
   for (tna_dmrg dm : bt->ch) tna_dmrg_destroy(dm);
-  for (auto *vec : {&bt->V, &bt->X, &bt->Z, &bt->Lf, &bt->Rf, &bt->T1, &bt->T2})
-    for (auto &b : *vec) b.release();
-  for (DevBuf *b : {&bt->ints, &bt->dbl, &bt->lzst, &bt->svd_wd, &bt->svd_wi, &bt->spec, &bt->S}) b->release();
-  for (Staging *st : {&bt->st_lz, &bt->st_g1, &bt->st_g2, &bt->st_mix, &bt->st_cvt, &bt->st_misc}) stage_release(*st);
-  bt->svd.release();
-  if (bt->h_ints) (void)hipHostFree(bt->h_ints);
-  if (bt->h_dbl) (void)hipHostFree(bt->h_dbl);
-  if (bt->stream) (void)hipStreamDestroy(bt->stream);
   delete bt;
 }
 

@@ -221,20 +221,27 @@ tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, i
     return TNA_ERR_ARG;
   }
   dim3 grid((unsigned)((max_elems + NT - 1) / NT), nprob);
+  const char *name = f32 ? "mixg.f32" : "mixg.f64";
+  timer_begin(name, s);
   if (f32) hipLaunchKernelGGL(mix_grouped_kernel<float>, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
   else hipLaunchKernelGGL(mix_grouped_kernel<double>, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
+  timer_end(name, 2.0 * I1 * I2 * J1 * J2 * (double)max_elems * nprob,
+            (double)(f32 ? 4 : 8) * (I1 * I2 + J1 * J2) * (double)max_elems * nprob, s);
   TNA_LAUNCHED("mix.grouped");
   return TNA_OK;
 }
 
-tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, hipStream_t s) {
+tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, double bytes_hint, hipStream_t s) {
   const dim3 g(maxG, nch), r(kmax + 1, nch), one(1, nch);
-  hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, 0);
-  hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, 0);
-  hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, 0, 0);
-  hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, 1);
-  hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, 1);
-  hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, 1, 1);
+  for (int pass = 0; pass < 2; ++pass) {
+    timer_begin("lz.dot", s);
+    hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, pass);
+    timer_end("lz.dot", bytes_hint / 4.0, bytes_hint, s);
+    hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, pass);
+    timer_begin("lz.axpy", s);
+    hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, pass, pass);
+    timer_end("lz.axpy", bytes_hint / 4.0, bytes_hint, s);
+  }
   hipLaunchKernelGGL(lz_record_kernel, one, dim3(NT), 0, s, d);
   hipLaunchKernelGGL(lz_normalize_kernel, g, dim3(NT), 0, s, d);
   hipLaunchKernelGGL(lz_advance_kernel, dim3((nch + 63) / 64), dim3(64), 0, s, d, nch);

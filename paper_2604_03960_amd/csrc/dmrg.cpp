@@ -105,12 +105,9 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
   dm->Re.resize(N);
   hipStream_t s = c->stream;
   TNA_HIP(hipHostMalloc((void **)&dm->host_stage, sizeof(double) * 64, hipHostMallocDefault));
-  TNA_HIP(hipHostMalloc((void **)&dm->host_feat, sizeof(float) * 32, hipHostMallocDefault));
   dm->hist.assign(N - 1, std::array<double, 8>{});
   dm->nhist.assign(N - 1, 0);
   dm->pred.assign(N - 1, 0);
-  TNA_TRY(dm->feat_d.ensure(sizeof(float) * 32));
-  TNA_TRY(dm->y_d.ensure(sizeof(float) * 4));
   // MPO and mixing matrices
   const size_t wsz = (size_t)D * D * d * d;
   TNA_TRY(dm->W.ensure(sizeof(double) * wsz * N));
@@ -196,137 +193,23 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
     set_error("dmrg_sweep: null handle");
     return TNA_ERR_ARG;
   }
-  tna_ctx c = dm->ctx;
-  hipStream_t s = c->stream;
-  const int N = dm->N, d = dm->d, D = dm->D;
-  const int I1 = D * d, I2 = D * d * d;
+  if (!dm->engine) TNA_TRY(engine_create(1, &dm->engine));
+  TNA_HIP(hipStreamSynchronize(dm->ctx->stream));  // work the caller queued on the context stream
+  const int N = dm->N;
   tna_status worst = TNA_OK;
   double E = 0.0;
-  int rec = 0;
-  for (int half = 0; half < 2; ++half) {
+  std::vector<tna_dmrg> cs{dm};
+  std::vector<int> slot{0}, bond{0}, half{0};
+  std::vector<double> Es(1, 0.0);
+  std::vector<tna_visit_log *> lg(log ? 1 : 0, nullptr);
+  for (int h = 0; h < 2; ++h)
     for (int step = 0; step < N - 1; ++step) {
-      const int b = half == 0 ? step : N - 2 - step;
-      const int chl = dm->CL(b), chm = dm->chi[b], chr = dm->CR(b + 1);
-      const int m = chl * d, n = d * chr;
-      const int64_t nv = (int64_t)m * n;
-      const int kmax = std::min<int64_t>(dm->opts.lanczos_fixed_iters > 0 ? dm->opts.lanczos_fixed_iters
-                                                                          : dm->opts.lanczos_kmax,
-                                         std::min<int64_t>(nv, 120));
-      TNA_TRY(dm->V.ensure(sizeof(double) * (size_t)(kmax + 2) * nv));
-      double *theta = dm->V.as<double>() + (int64_t)(kmax + 1) * nv;
-      auto t0 = std::chrono::steady_clock::now();
-      // theta = A_b A_{b+1}
-      GemmArgs g{};
-      g.M = m; g.N = n; g.K = chm;
-      g.A = dm->A[b].ptr; g.lda = chm; g.B = dm->A[b + 1].ptr; g.ldb = n; g.C = theta; g.ldc = n;
-      g.alpha = 1.0; g.batch = 1; g.compute = G_F64;
-      TNA_TRY(gemm(g, s));
-      LanczosResult lr{};
-      tna_status st = heff_lanczos(c, chl, chr, d, D, dm->Le[b].as<double>(), dm->Re[b + 1].as<double>(),
-                                        dm->M12.as<double>() + (size_t)I2 * I2 * b, dm->opts.heff_prec, theta,
-                                        dm->V.as<double>(), dm->opts.lanczos_tol, kmax, dm->opts.lanczos_restarts,
-                                        dm->opts.lanczos_fixed_iters, &lr);
-      if (st != TNA_OK) return st;
-      if (!lr.converged && worst == TNA_OK) worst = TNA_ERR_NOCONV;
-      auto t1 = std::chrono::steady_clock::now();
-      // SVD of theta, entropy of the full spectrum, needed rank, leading values
-      int sw = 0;
-      SvdMat mat;
-      st = svd_start(dm, m, n, theta, &mat, &sw);
-      if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
-      if (st == TNA_ERR_NOCONV && worst == TNA_OK) worst = TNA_ERR_NOCONV;
-      const int Rk = mat.R;
-      double *spec = dm->spec.as<double>();
-      TNA_HIP(hipMemcpyAsync(dm->host_stage, spec, sizeof(double) * 24, hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipStreamSynchronize(s));
-      const double S_ent = dm->host_stage[1];
-      const int k_needed = (int)dm->host_stage[6];
-      double terms[6];
-      int chi_next = 0;
-      TNA_TRY(pid_update(&dm->pid, &dm->st[b], S_ent, &chi_next, terms));
-      // scheduler inputs: EMA history (oldest first, padded with the oldest),
-      // 16 largest log sigma (floored at ln 1e-16), relative bond position
-      {
-        auto &hb = dm->hist[b];
-        if (dm->nhist[b] < 8) hb[dm->nhist[b]++] = terms[4];
-        else {
-          for (int q = 0; q < 7; ++q) hb[q] = hb[q + 1];
-          hb[7] = terms[4];
-        }
-        const int nh = dm->nhist[b];
-        float *f = dm->host_feat;
-        for (int q = 0; q < 8; ++q) f[q] = (float)hb[q < 8 - nh ? 0 : q - (8 - nh)];
-        const double floor_ln = std::log(1e-16);
-        for (int q = 0; q < 16; ++q) {
-          const double sv = dm->host_stage[8 + q];
-          f[8 + q] = (float)(sv > 0 ? std::max(std::log(sv), floor_ln) : floor_ln);
-        }
-        f[24] = (float)((b + 1.0) / N);
-      }
-      int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next;
-      int chi_sched = 0, fallback = 0;
-      if (dm->sched && dm->opts.fixed_chi <= 0 && dm->pred[b] > 0) {
-        chi_sched = dm->pred[b];
-        if (std::min(chi_sched, Rk) < std::min(k_needed, Rk)) fallback = 1;  // would miss eps_target
-        else keep = chi_sched;
-      }
-      if (dm->sched) {  // proposal for this bond's next visit
-        TNA_HIP(hipMemcpyAsync(dm->feat_d.ptr, dm->host_feat, sizeof(float) * 25, hipMemcpyHostToDevice, s));
-        TNA_TRY(mlp_forward_dev(dm->sched, 1, dm->feat_d.as<float>(), dm->y_d.as<float>()));
-        TNA_HIP(hipMemcpyAsync(dm->host_feat + 28, dm->y_d.ptr, sizeof(float), hipMemcpyDeviceToHost, s));
-        TNA_HIP(hipStreamSynchronize(s));
-        const double yv = dm->host_feat[28];
-        double kp = std::isfinite(yv) ? std::nearbyint(std::exp2(std::min(yv, 30.0))) : dm->pid.chi_min;
-        kp = std::min<double>(std::max<double>(kp, dm->pid.chi_min), dm->pid.chi_max);
-        dm->pred[b] = (int)kp;
-      }
-      const int k = std::min(keep, Rk);
-      TNA_TRY(dm->A[b].ensure(sizeof(double) * (size_t)m * k));
-      TNA_TRY(dm->A[b + 1].ensure(sizeof(double) * (size_t)k * n));
-      TNA_TRY(svd_finish(dm, mat, k, dm->A[b].ptr, dm->A[b + 1].ptr, half == 0 ? 1 : 2));
-      dm->chi[b] = k;
-      auto t2 = std::chrono::steady_clock::now();
-      // grow the environment past the moved centre
-      if (half == 0) {
-        TNA_TRY(dm->T1.ensure(sizeof(double) * (size_t)chl * D * d * k));
-        TNA_TRY(dm->T2.ensure(sizeof(double) * (size_t)chl * D * d * k));
-        TNA_TRY(dm->Le[b + 1].ensure(sizeof(double) * (size_t)k * D * k));
-        TNA_TRY(env_left(chl, k, d, D, dm->Le[b].as<double>(), dm->Ml.as<double>() + (size_t)I1 * I1 * b,
-                              dm->A[b].as<double>(), dm->T1.as<double>(), dm->T2.as<double>(),
-                              dm->Le[b + 1].as<double>(), s));
-      } else {
-        TNA_TRY(dm->T1.ensure(sizeof(double) * (size_t)chr * D * k * d));
-        TNA_TRY(dm->T2.ensure(sizeof(double) * (size_t)chr * D * k * d));
-        TNA_TRY(dm->Re[b].ensure(sizeof(double) * (size_t)k * D * k));
-        TNA_TRY(env_right(k, chr, d, D, dm->Re[b + 1].as<double>(), dm->Mr.as<double>() + (size_t)I1 * I1 * (b + 1),
-                               dm->A[b + 1].as<double>(), dm->T1.as<double>(), dm->T2.as<double>(),
-                               dm->Re[b].as<double>(), s));
-      }
-      // per-visit readback of the truncation sums and the first/last kept value
-      TNA_HIP(hipMemcpyAsync(dm->host_stage + 32, spec, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
-      TNA_HIP(hipMemcpyAsync(dm->host_stage + 40, dm->S.as<double>() + (k - 1), sizeof(double), hipMemcpyDeviceToHost,
-                             s));
-      TNA_HIP(hipStreamSynchronize(s));
-      auto t3 = std::chrono::steady_clock::now();
-      E = lr.E;
-      if (log) {
-        tna_visit_log &r = log[rec];
-        const double *h = dm->host_stage;
-        r.sweep = dm->sweeps_done; r.dir = half; r.bond = b; r.m = m; r.n = n; r.k = k; r.chi_ctrl = chi_next;
-        r.lanczos_iters = lr.iters; r.svd_sweeps = sw; r.lanczos_ok = lr.converged;
-        r.E = lr.E; r.S = S_ent; r.S_ema = terms[4]; r.eps = h[32 + 2]; r.wdisc = h[32 + 3]; r.gap = h[32 + 5];
-        r.P = terms[0]; r.I = terms[1]; r.D = terms[2]; r.u = terms[3]; r.sigma0 = h[8]; r.sigma_last = h[40];
-        r.ms_lanczos = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        r.ms_svd = std::chrono::duration<double, std::milli>(t2 - t1).count();
-        r.ms_other = std::chrono::duration<double, std::milli>(t3 - t2).count();
-        r.k_needed = k_needed;
-        r.chi_sched = chi_sched;
-        r.fallback = fallback;
-        for (int q = 0; q < 25; ++q) r.feat[q] = dm->host_feat[q];
-      }
-      ++rec;
+      bond[0] = h == 0 ? step : N - 2 - step;
+      half[0] = h;
+      if (log) lg[0] = log + h * (N - 1) + step;
+      TNA_TRY(engine_step(dm->engine, cs, slot, bond, half, Es, lg, &worst));
+      E = Es[0];
     }
-  }
   dm->sweeps_done += 1;
   if (E_out) *E_out = E;
   return worst;
@@ -383,8 +266,7 @@ void tna_dmrg_destroy(tna_dmrg dm) {
   for (auto &b : dm->Re) b.release();
   for (DevBuf *b : {&dm->W, &dm->M12, &dm->Ml, &dm->Mr, &dm->V, &dm->T1, &dm->T2, &dm->spec, &dm->S}) b->release();
   if (dm->host_stage) (void)hipHostFree(dm->host_stage);
-  if (dm->host_feat) (void)hipHostFree(dm->host_feat);
-  for (DevBuf *b : {&dm->feat_d, &dm->y_d}) b->release();
+  engine_destroy(dm->engine);
   delete dm;
 }
 

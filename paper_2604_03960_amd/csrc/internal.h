@@ -13,6 +13,8 @@
 
 #include "../../include/tna.h"
 
+struct tna_engine_s;
+
 namespace tna {
 
 // ------------------------------------------------------------------ errors
@@ -41,6 +43,8 @@ tna_status post_launch(const char *what);
 // reports per-name launch count, total milliseconds and the algorithmic
 // flops and bytes the launch sites declare.
 bool timing_on();
+// true when timing is on and its filter could match a kernel whose name starts with name_prefix
+bool timing_may_match(const char *name_prefix);
 bool timing_wanted(const char *name);
 void timer_begin(const char *name, hipStream_t s);
 void timer_end(const char *name, double flops, double bytes, hipStream_t s);
@@ -157,6 +161,7 @@ struct SvdMat {
   double *spec;                                // 24 doubles: Z, S_vN, eps, eps^2/Z, |S_k|, gap, k_needed, -, S_0..S_15
   int *skip, *perm, *ctr;                      // work
   void *U, *Vt;                                // m x k, k x n (out_type)
+  double *fro2;                                // work: |A|_F^2 (device scalar)
 };
 struct SvdGroup {
   DevBuf desc, work_d, work_i;
@@ -199,7 +204,8 @@ struct LzProb {
   int *j, *active;
   double *h1, *h2, *part1, *part2, *nrm2, *rec, *y;  // rec: {alpha_j, beta_j^2}
 };
-tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, hipStream_t s);
+// bytes_hint: algorithmic bytes of one dot (or update) pass, for kernel timing
+tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, double bytes_hint, hipStream_t s);
 tna_status lz_start(const LzProb *d, int nch, int maxG, hipStream_t s);
 tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s);
 struct CvtProb {
@@ -209,17 +215,19 @@ struct CvtProb {
 };
 tna_status convert_grouped(const CvtProb *d, int nprob, hipStream_t s);
 
+// ------------------------------------------------------------------ step engine (batch.cpp)
+// One lockstep bond visit of a set of chains (a single chain is a set of one).
+typedef ::tna_engine_s *tna_engine;
+tna_status engine_create(int nslot, tna_engine *out);
+void engine_destroy(tna_engine e);
+hipStream_t engine_stream(tna_engine e);
+void engine_stats(tna_engine e, tna_batch_stats *st);
+tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std::vector<int> &slot,
+                       const std::vector<int> &bond, const std::vector<int> &half, std::vector<double> &E_out,
+                       std::vector<tna_visit_log *> &logs, tna_status *worst);
+double tridiag_lowest_host(int n, const double *a, const double *b, double *y);
+
 // ------------------------------------------------------------------ host-side steps (api.cpp)
-struct LanczosResult {
-  double E = 0.0;
-  int iters = 0;
-  int converged = 0;
-};
-// Lowest eigenpair of H_eff (FP64 Lanczos, full CGS2 reorthogonalisation)
-// starting from theta (overwritten by the normalised Ritz vector).
-tna_status heff_lanczos(tna_ctx c, int chl, int chr, int d, int D, const double *L, const double *R,
-                        const double *M12, int prec, double *theta, double *V, double tol, int kmax, int restarts,
-                        int fixed_iters, LanczosResult *res);
 tna_status env_left(int chl, int k, int d, int D, const double *L, const double *Ml, const double *A, double *T1,
                     double *T2, double *Ln, hipStream_t s);
 tna_status env_right(int k, int chr, int d, int D, const double *R, const double *Mr, const double *B, double *T1,
@@ -257,8 +265,7 @@ struct tna_dmrg_s {
   tna_mlp sched = nullptr;
   std::vector<std::array<double, 8>> hist;  // last EMA entropies per bond (oldest first)
   std::vector<int> nhist, pred;             // history length, pending proposal (0 = none)
-  tna::DevBuf feat_d, y_d;
-  float *host_feat = nullptr;               // pinned: 25 inputs + 1 output
+  tna::tna_engine engine = nullptr;          // the step engine this chain's sweeps run on
   int CL(int i) const { return i == 0 ? 1 : chi[i - 1]; }
   int CR(int i) const { return i == N - 1 ? 1 : chi[i]; }
 };

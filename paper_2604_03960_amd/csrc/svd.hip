@@ -18,6 +18,9 @@
 // sweep).  Afterwards sigma_r = |row r|, a bitonic sort orders them, and the
 // factors are written with the sign gauge (largest-magnitude entry of each
 // left vector positive) and Gram-Schmidt completion of null vectors.
+#include <cstdio>
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace tna {
@@ -170,6 +173,11 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
     Qs[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (tid == 0) need = 0;
+  // Couplings below eps |A|_F^2 cannot move any singular value by more than
+  // about eps |A|_F; rows at the rounding floor never meet a relative test, so
+  // both the outer test and the inner rotations ignore them.
+  const double fro2 = *a.fro2;
+  const double floor_out = 4.0 * EPS53 * fro2, floor_in = EPS53 * fro2;
   __syncthreads();
   {
     int loc = 0;
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
       const int i = e >> 6, j = e & 63;
       if (i < j) {
         const double gii = Gs[i][i], gjj = Gs[j][j], gij = Gs[i][j];
-        if (gii > 0.0 && gjj > 0.0 && fabs(gij) > a.tol * sqrt(gii * gjj)) loc = 1;
+        if (gii > 0.0 && gjj > 0.0 && fabs(gij) > a.tol * sqrt(gii * gjj) && fabs(gij) > floor_out) loc = 1;
       }
     }
     if (__any(loc) && (tid & 63) == 0) atomicOr(&need, 1);
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
         if (i > j) { const int t = i; i = j; j = t; }
         const double gii = Gs[i][i], gjj = Gs[j][j], gij = Gs[i][j];
         double c = 1.0, s = 0.0;
-        if (gij != 0.0 && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
+        if (fabs(gij) > floor_in && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
           const double zeta = (gjj - gii) / (2.0 * gij);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -352,6 +360,17 @@ __global__ __launch_bounds__(256) void load_kernel(const SvdMat *mats) {
       a.jt[e] = (r == c) ? 1.0 : 0.0;
     }
   }
+}
+
+// |A|_F^2 of the loaded rows; one block per matrix, fixed order
+__global__ __launch_bounds__(256) void fro_kernel(const SvdMat *mats) {
+  __shared__ double red[4];
+  const SvdMat &a = mats[blockIdx.x];
+  const int64_t tot = (int64_t)a.R * a.C;
+  double v = 0.0;
+  for (int64_t e = threadIdx.x; e < tot; e += 256) v += a.bw[e] * a.bw[e];
+  v = bsum256(v, red);
+  if (threadIdx.x == 0) *a.fro2 = v;
 }
 
 __global__ void zero_ctr_kernel(const SvdMat *mats, int nmat) {
@@ -671,7 +690,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
 
 size_t svd_work_doubles(const SvdMat &a) {
   const size_t npairs = a.nb / 2;
-  return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R;
+  return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R + 8;
 }
 size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4; }
 
@@ -686,6 +705,8 @@ void svd_bind_work(SvdMat *a, double *dw, int *iw) {
   a->qt = dw;
   dw += npairs * 4096;
   a->sig = dw;
+  dw += a->R;
+  a->fro2 = dw;
   a->skip = iw;
   iw += npairs;
   a->perm = iw;
@@ -728,6 +749,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
   TNA_TRY(upload(mats, g, s));
   const SvdMat *d = g.desc.as<SvdMat>();
   hipLaunchKernelGGL(load_kernel, dim3(max_tiles_load, 1, nm), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(fro_kernel, dim3(nm), dim3(256), 0, s, d);
   TNA_LAUNCHED("svd.load");
   if (!g.host_ctr) TNA_HIP(hipHostMalloc((void **)&g.host_ctr, sizeof(int) * 4096, hipHostMallocDefault));
   if (nm > 4096) {
@@ -761,6 +783,11 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       if (mats[z].active)
         TNA_HIP(hipMemcpyAsync(g.host_ctr + z, mats[z].ctr, sizeof(int), hipMemcpyDeviceToHost, s));
     TNA_HIP(hipStreamSynchronize(s));
+    static const int dbg = [] {
+      const char *e = std::getenv("TNA_DEBUG_SVD");
+      return e && e[0] == '1';
+    }();
+    if (dbg) std::fprintf(stderr, "svd sweep %d: rotating pairs of matrix 0 = %d\n", sw, g.host_ctr[0]);
     bool changed = false;
     for (int z = 0; z < nm; ++z) {
       if (!mats[z].active) continue;

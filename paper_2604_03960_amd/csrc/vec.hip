@@ -120,6 +120,18 @@ __global__ __launch_bounds__(NT) void multidot_kernel(const double *V, int64_t l
   }
 }
 
+// h[i] = <V_i, w> with one block per vector (short vectors), fixed order
+__global__ __launch_bounds__(NT) void multidot_small_kernel(const double *V, int64_t ldv, const double *w, int64_t n,
+                                                            double *h) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
+  const double *v = V + (int64_t)i * ldv;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += NT) acc += v[e] * w[e];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) h[i] = acc;
+}
+
 // out[i] = sum_b part[i*G + b], one block per i, fixed tree
 __global__ __launch_bounds__(NT) void reduce_parts_kernel(const double *part, int G, double *out) {
   __shared__ double sh[4];
@@ -272,6 +284,13 @@ tna_status multidot(const double *V, int64_t ldv, int nv, const double *w, int64
                     hipStream_t s) {
   if (nv <= 0) return TNA_OK;
   int G = n_parts(n);
+  if (n <= 65536) {  // short vectors: a block per vector, no second pass
+    timer_begin("vec.multidot", s);
+    hipLaunchKernelGGL(multidot_small_kernel, dim3(nv), dim3(NT), 0, s, V, ldv, w, n, h);
+    timer_end("vec.multidot", 2.0 * nv * (double)n, 8.0 * (nv + 1) * (double)n, s);
+    TNA_LAUNCHED("vec.multidot");
+    return TNA_OK;
+  }
   timer_begin("vec.multidot", s);
   hipLaunchKernelGGL(multidot_kernel, dim3(G), dim3(NT), 0, s, V, ldv, nv, w, n, part);
   timer_end("vec.multidot", 2.0 * nv * (double)n, 8.0 * (nv + 1) * (double)n, s);
