@@ -38,7 +38,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--roofline-kernel", default="", help="kernel-name prefix to time (default: auto)")
-    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd"], default="heisenberg100")
+    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd", "fixed_chi"], default="heisenberg100")
+    ap.add_argument("--chi", type=int, default=256, help="fixed_chi: bond dimension")
+    ap.add_argument("--matvecs", type=int, default=20, help="fixed_chi: H_eff applications per visit")
     ap.add_argument("--chains", type=int, default=64)
     ap.add_argument("--svd-batch", type=int, default=1)
     ap.add_argument("--svd-dtype", choices=["f64", "f32"], default="f64")
@@ -103,6 +105,49 @@ def run_batch(a):
     print(json.dumps(out))
 
 
+def run_fixed_chi(a):
+    """Throughput mode: chi_min = chi_max = chi (capped by the rank each bond allows), a fixed number
+    of matvecs per visit; reports sweeps/s and the H_eff GEMM rate."""
+    import numpy as np
+    import torch
+
+    import paper_2604_03960_amd as tna
+    import synth
+    ctx = tna.Context(0)
+    N = a.N
+    W = tna.mpo_build(tna.MODEL_XXZ, N, [1.0, 1.0, 0.0])
+    A, chi, _ = synth.random_mps(N, 2, a.chi, seed=0)
+    prec = tna.HEFF_F64 if a.prec == "f64" else tna.HEFF_F32
+    dm = tna.Dmrg(ctx, W, A, chi, tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 16, a.chi), heff_prec=prec,
+                  fixed_iters=a.matvecs, fixed_chi=a.chi)
+    for _ in range(a.warmup):
+        dm.sweep()
+    gname = "gemmg." + ("f64" if a.prec == "f64" else "f32")
+    ctx.set_timing(True, gname)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        E, recs, st = dm.sweep()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.kernel_stats(reset=True)
+    ctx.set_timing(False)
+    fl = sum(r["flops"] for r in stats)
+    ms = sum(r["ms"] for r in stats)
+    dom = max(stats, key=lambda r: r["ms"])["name"] if stats else ""
+    chis = np.array([r["k"] for r in recs])
+    out = {"metric": f"DMRG sweeps/s at fixed chi={a.chi}", "value": a.steps / (t1 - t0), "unit": "sweeps/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * (t1 - t0) / a.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": a.prec, "data": "synthetic",
+           "config": {"workload": f"heisenberg_obc_N{N}_fixed_chi{a.chi}_{a.matvecs}matvecs", "N": N, "chi": a.chi,
+                      "matvecs_per_visit": a.matvecs, "heff_prec": a.prec},
+           "E_per_site": E / N, "k_max": int(chis.max()), "k_mean": float(chis.mean()),
+           "heff_gemm_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
+           "roofline": roofline_from(stats, dom) if dom else None,
+           "phase_ms": {"lanczos": sum(r["ms_lanczos"] for r in recs), "svd": sum(r["ms_svd"] for r in recs)}}
+    print(json.dumps(out))
+
+
 def run_svd(a):
     """Isolated truncated SVDs of n x n matrices with spectrum exp(-k/tau), keep n/2."""
     import numpy as np
@@ -129,6 +174,15 @@ def run_svd(a):
     ctx.set_timing(False)
     S = res[0]
     err = (S.reshape(B, -1) - sig[None, :]).abs().max().item()
+    sweeps = res[5] if B == 1 else res[4]
+    # one more call with every svd kernel timed, for the per-kernel breakdown
+    ctx.set_timing(True, "svd.")
+    run()
+    torch.cuda.synchronize()
+    brk = sorted(ctx.kernel_stats(reset=True), key=lambda r: -r["ms"])
+    ctx.set_timing(False)
+    breakdown = {r["name"]: {"ms": r["ms"], "launches": r["count"], "avg_us": 1e3 * r["ms"] / max(r["count"], 1)}
+                 for r in brk}
     value = B * a.svd_reps / (t1 - t0)
     nominal = 22.0 * n ** 3  # Golub-Reinsch count with thin U and V
     out = {"metric": f"SVD/s at chi={n // 2} ({n}x{n}, {a.svd_dtype}, batch {B})", "value": value,
@@ -136,7 +190,8 @@ def run_svd(a):
            "ms_per_step": 1e3 * (t1 - t0) / a.svd_reps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": a.svd_dtype, "data": "synthetic",
            "config": {"workload": f"svd_{n}x{n}_tau{a.svd_tau:g}_batch{B}", "n": n, "tau": a.svd_tau, "batch": B},
-           "max_abs_sigma_err": err, "nominal_tflops": value * nominal / 1e12,
+           "max_abs_sigma_err": err, "nominal_tflops": value * nominal / 1e12, "jacobi_sweeps": sweeps,
+           "breakdown_one_call": breakdown,
            "roofline": roofline_from(stats, "svd.apply")}
     print(json.dumps(out))
 
@@ -150,6 +205,8 @@ def main():
         return run_batch(a)
     if a.workload == "svd":
         return run_svd(a)
+    if a.workload == "fixed_chi":
+        return run_fixed_chi(a)
     import numpy as np
     import torch
 

@@ -197,6 +197,7 @@ typedef struct tna_dmrg_batch_s *tna_dmrg_batch;
 typedef struct {
   double ms_total, ms_lanczos, ms_svd, ms_env;
   long lanczos_iters, graph_launches;
+  long small_launches;   /* launches of the single-workgroup Lanczos path (short theta) */
   int autotune_entries, steps;
 } tna_batch_stats;
 tna_status tna_dmrg_batch_create(tna_ctx ctx, int nchains, const int *N, int d, int D, const double *const *W_host,
@@ -215,6 +216,8 @@ void tna_dmrg_batch_destroy(tna_dmrg_batch b);
 tna_status tna_autotune_save(const char *path);
 tna_status tna_autotune_load(const char *path);
 int tna_autotune_entries(void);
+/* Empties the table (the next launches measure again). */
+void tna_autotune_clear(void);
 
 /* ---------------------------------------------------------------- learned scheduler */
 /* A 25 -> 64 -> 64 -> 1 perceptron (tanh hidden units, linear output), the

@@ -35,6 +35,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_03960_amd.build` "
                       "(the GPU path has no fallback)")
 
+# torch is loaded before the library so that the process has one HIP runtime: the one torch
+# ships, which libtna.so's libamdhip64 dependency then resolves to.  Loaded the other way round,
+# a second runtime comes up beside torch's and may not see the device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 
@@ -65,7 +70,8 @@ class VisitLog(C.Structure):
 
 class BatchStats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_lanczos", C.c_double), ("ms_svd", C.c_double), ("ms_env", C.c_double),
-                ("lanczos_iters", C.c_long), ("graph_launches", C.c_long), ("autotune_entries", C.c_int),
+                ("lanczos_iters", C.c_long), ("graph_launches", C.c_long), ("small_launches", C.c_long),
+                ("autotune_entries", C.c_int),
                 ("steps", C.c_int)]
 
 
@@ -107,6 +113,7 @@ _SIGS = {
     "tna_autotune_save": ([C.c_char_p], C.c_int),
     "tna_autotune_load": ([C.c_char_p], C.c_int),
     "tna_autotune_entries": ([], C.c_int),
+    "tna_autotune_clear": ([], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -445,3 +452,7 @@ def autotune_load(path: str):
 
 def autotune_entries() -> int:
     return _lib.tna_autotune_entries()
+
+
+def autotune_clear():
+    _lib.tna_autotune_clear()

@@ -47,50 +47,74 @@ int flop_bucket(double f) { return f < 1.0 ? 0 : (int)std::floor(std::log2(f)); 
 
 
 // ------------------------------------------------------------------ descriptor arena
-// Descriptors of one step are bump-allocated in a pinned host buffer and
-// copied to the same offset of a device buffer; nothing is reused until the
-// step's final synchronisation, so no upload has to wait for an earlier one.
-struct Arena {
+// Everything a step uploads (descriptors, flags, small vectors) is copied into
+// a fresh slice of a pinned host block and from there to the same offset of a
+// device block.  Nothing is reused before the step's final synchronisation, so
+// no host write can race a copy still in flight and every device pointer
+// handed out stays valid for the whole step (a captured graph keeps using
+// them); a full block is followed by a new one.
+struct ArenaBlock {
   char *host = nullptr;
-  DevBuf dev;
-  size_t cap = 0, off = 0;
+  void *dev = nullptr;
+  size_t cap = 0;
+};
+struct Arena {
+  std::vector<ArenaBlock> blocks;
+  size_t cur = 0, off = 0;
 };
 
-tna_status arena_reserve(Arena &a, size_t bytes) {
-  if (a.cap >= bytes) return TNA_OK;
-  if (a.host) (void)hipHostFree(a.host);
-  a.host = nullptr;
-  a.cap = 0;
-  TNA_HIP(hipHostMalloc((void **)&a.host, bytes, hipHostMallocDefault));
-  TNA_TRY(a.dev.ensure(bytes));
-  a.cap = bytes;
-  return TNA_OK;
+void arena_begin(Arena &a) {
+  a.cur = 0;
+  a.off = 0;
 }
 
 template <class T>
 tna_status arena_push(Arena &a, const T *src, size_t n, hipStream_t s, const T **dev_out) {
   const size_t bytes = sizeof(T) * n;
-  const size_t need = (a.off + bytes + 255) & ~(size_t)255;
-  if (need > a.cap) {
-    // out of room inside a step: wait for the copies in flight, then start over
-    TNA_HIP(hipStreamSynchronize(s));
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  while (a.cur < a.blocks.size() && a.off + need > a.blocks[a.cur].cap) {
+    ++a.cur;
     a.off = 0;
-    if (bytes + 256 > a.cap) TNA_TRY(arena_reserve(a, 2 * (bytes + 256)));
   }
-  char *h = a.host + a.off;
-  char *d = static_cast<char *>(a.dev.ptr) + a.off;
-  std::memcpy(h, src, bytes);
-  TNA_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
-  a.off = (a.off + bytes + 255) & ~(size_t)255;
+  if (a.cur == a.blocks.size()) {
+    ArenaBlock b;
+    b.cap = std::max<size_t>((size_t)4 << 20, 2 * need);
+    TNA_HIP(hipHostMalloc((void **)&b.host, b.cap, hipHostMallocDefault));
+    if (hipMalloc(&b.dev, b.cap) != hipSuccess) {
+      (void)hipHostFree(b.host);
+      set_error("arena: device allocation failed");
+      return TNA_ERR_NOMEM;
+    }
+    a.blocks.push_back(b);
+    a.off = 0;
+  }
+  ArenaBlock &b = a.blocks[a.cur];
+  char *h = b.host + a.off;
+  char *d = static_cast<char *>(b.dev) + a.off;
+  if (bytes) std::memcpy(h, src, bytes);
+  if (bytes) TNA_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+  a.off += need;
   *dev_out = reinterpret_cast<const T *>(d);
   return TNA_OK;
 }
 
+// host values -> device location, staged through the arena
+template <class T>
+tna_status put_dev(Arena &a, const T *src, size_t n, T *dst, hipStream_t s) {
+  if (n == 0) return TNA_OK;
+  const T *d = nullptr;
+  TNA_TRY(arena_push(a, src, n, s, &d));
+  TNA_HIP(hipMemcpyAsync(dst, d, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+  return TNA_OK;
+}
+
 void arena_release(Arena &a) {
-  a.dev.release();
-  if (a.host) (void)hipHostFree(a.host);
-  a.host = nullptr;
-  a.cap = a.off = 0;
+  for (auto &b : a.blocks) {
+    if (b.dev) (void)hipFree(b.dev);
+    if (b.host) (void)hipHostFree(b.host);
+  }
+  a.blocks.clear();
+  a.cur = a.off = 0;
 }
 
 double group_flops(const std::vector<GemmProb> &probs) {
@@ -153,6 +177,8 @@ int parts_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 512));
 }
 
+constexpr int LZ_SMALL_N = 4096;            // longest theta of the single-workgroup Lanczos path
+constexpr int NT_SMALL = 256;               // its workgroup size
 constexpr size_t LZ_SLOT = 128;             // per-chain h1/h2/y/nrm2 slots
 constexpr size_t LZ_PER = 3 * LZ_SLOT + 8;  // doubles per chain before the partials
 constexpr size_t LZ_PART = 128 * 512;       // partial-sum slots per chain and array
@@ -166,13 +192,16 @@ struct tna_engine_s {
   hipStream_t stream = nullptr;
   int nslot = 0;
   std::vector<DevBuf> V, X, Z, Lf, Rf, T1, T2;
-  DevBuf ints, dbl, lzst, feat_d, y_d;
+  DevBuf ints, dbl, lzst, feat_d, y_d, recs;
   Arena ar;
   SvdGroup svd;
   DevBuf svd_wd, svd_wi, spec, S;
-  int *h_ints = nullptr;
+  std::vector<int> hflags;  // j (nslot) then active (nslot) of the last upload
   double *h_dbl = nullptr;
   float *h_feat = nullptr;
+  double *h_rec = nullptr;  // per slot 2 LZ_HMAX: alpha_j, beta_j^2 of the single-workgroup path
+  int *h_j = nullptr;
+  long small_launches = 0;
   long graph_launches = 0, lanczos_iters = 0;
   double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
 };
@@ -196,10 +225,12 @@ tna_status engine_create(int nslot, tna_engine *out) {
   TNA_TRY(e->spec.ensure(sizeof(double) * 24 * nslot));
   TNA_TRY(e->feat_d.ensure(sizeof(float) * 32 * nslot));
   TNA_TRY(e->y_d.ensure(sizeof(float) * 4 * nslot));
-  TNA_HIP(hipHostMalloc((void **)&e->h_ints, sizeof(int) * 2 * nslot, hipHostMallocDefault));
+  e->hflags.assign(2 * (size_t)nslot, 0);
   TNA_HIP(hipHostMalloc((void **)&e->h_dbl, sizeof(double) * (24 * nslot + 2 * nslot + 16), hipHostMallocDefault));
   TNA_HIP(hipHostMalloc((void **)&e->h_feat, sizeof(float) * 32 * nslot, hipHostMallocDefault));
-  TNA_TRY(arena_reserve(e->ar, (size_t)1 << 22));
+  TNA_TRY(e->recs.ensure(sizeof(double) * 2 * LZ_HMAX * nslot));
+  TNA_HIP(hipHostMalloc((void **)&e->h_rec, sizeof(double) * 2 * LZ_HMAX * nslot, hipHostMallocDefault));
+  TNA_HIP(hipHostMalloc((void **)&e->h_j, sizeof(int) * nslot, hipHostMallocDefault));
   *out = e.release();
   return TNA_OK;
 }
@@ -209,13 +240,15 @@ void engine_destroy(tna_engine e) {
   (void)hipStreamSynchronize(e->stream);
   for (auto *vec : {&e->V, &e->X, &e->Z, &e->Lf, &e->Rf, &e->T1, &e->T2})
     for (auto &b : *vec) b.release();
-  for (DevBuf *b : {&e->ints, &e->dbl, &e->lzst, &e->feat_d, &e->y_d, &e->svd_wd, &e->svd_wi, &e->spec, &e->S})
+  for (DevBuf *b : {&e->ints, &e->dbl, &e->lzst, &e->feat_d, &e->y_d, &e->recs, &e->svd_wd, &e->svd_wi, &e->spec,
+                    &e->S})
     b->release();
   arena_release(e->ar);
   e->svd.release();
-  if (e->h_ints) (void)hipHostFree(e->h_ints);
   if (e->h_dbl) (void)hipHostFree(e->h_dbl);
   if (e->h_feat) (void)hipHostFree(e->h_feat);
+  if (e->h_rec) (void)hipHostFree(e->h_rec);
+  if (e->h_j) (void)hipHostFree(e->h_j);
   if (e->stream) (void)hipStreamDestroy(e->stream);
   delete e;
 }
@@ -227,6 +260,7 @@ void engine_stats(tna_engine e, tna_batch_stats *st) {
   st->ms_env = e->ms_env;
   st->lanczos_iters = e->lanczos_iters;
   st->graph_launches = e->graph_launches;
+  st->small_launches = e->small_launches;
   st->autotune_entries = (int)g_tune.table.size();
 }
 
@@ -242,7 +276,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   const int I1 = D * d, I2 = D * d * d;
   const int prec = ch[0]->opts.heff_prec;
   const bool f32 = prec == TNA_HEFF_F32;
-  en->ar.off = 0;  // the previous step ended with a synchronisation
+  arena_begin(en->ar);  // the previous step ended with a synchronisation
   auto t0 = std::chrono::steady_clock::now();
   struct Visit {
     int b, half, chl, chm, chr, m, n, kmax, fixed;
@@ -348,31 +382,38 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   GemmGroup g1{0, 0, tc, G_F64, tc, tc, 64, 1.0, 0.0, 0.0, 0.0};
   GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, 0.0, 0.0, 0.0};
   for (int q = 0; q < nc; ++q) {
-    en->h_ints[slot[q]] = 0;
-    en->h_ints[en->nslot + slot[q]] = 1;
+    en->hflags[slot[q]] = 0;
+    en->hflags[en->nslot + slot[q]] = 1;
   }
-  TNA_HIP(hipMemcpyAsync(j_dev, en->h_ints, sizeof(int) * 2 * en->nslot, hipMemcpyHostToDevice, s));
+  auto push_act = [&]() { return put_dev(en->ar, en->hflags.data() + en->nslot, (size_t)en->nslot, act_dev, s); };
+  TNA_TRY(put_dev(en->ar, en->hflags.data(), 2 * (size_t)en->nslot, j_dev, s));
   const LzProb *dlp = nullptr;
   TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dlp));
   TNA_TRY(lz_start(dlp, nc, maxG, s));
-  // tile choice for the two H_eff GEMMs, measured before capture (j = 0)
+  // ---- which visits run whole Lanczos iterations inside one workgroup (short theta, all of
+  // H_eff's operands in LDS); the rest go through the grouped GEMM/mixing/CGS2 launches
+  std::vector<int> small(nc, 0), sm_ac(nc, 1);
+  int nsmall = 0;
+  size_t lds_small = 0;
+  if (d == 2 && (D == 3 || D == 5 || D == 8)) {
+    for (int q = 0; q < nc; ++q) {
+      const Visit &v = vs[q];
+      if (v.nv > LZ_SMALL_N) continue;
+      int ac = std::max(1, std::min(v.chl, NT_SMALL / std::max(1, v.chr)));
+      while (ac > 1 && lz_small_lds(v.chl, v.chr, d, D, ac) > LZ_SMALL_LDS_MAX) ac /= 2;
+      const size_t need = lz_small_lds(v.chl, v.chr, d, D, ac);
+      if (need > LZ_SMALL_LDS_MAX) continue;
+      small[q] = 1;
+      sm_ac[q] = ac;
+      lds_small = std::max(lds_small, need);
+      ++nsmall;
+    }
+  }
+  const int nbig = nc - nsmall;
   int tile1 = 64, tile4 = 64;
-  TNA_TRY(tuned_gemm(1, g1, s1, en->ar, s, true, &tile1));
-  TNA_TRY(tuned_gemm(2, g4, s4, en->ar, s, true, &tile4));
   const MixProb *dmx = nullptr;
-  TNA_TRY(arena_push(en->ar, mx.data(), nc, s, &dmx));
-  std::vector<GemmProb> p1 = s1, p4 = s4;
-  g1.tile = tile1;
-  g4.tile = tile4;
-  g1.flops = group_flops(s1);
-  g4.flops = group_flops(s4);
-  const int tot1 = gemm_group_tiles(p1, tile1), tot4 = gemm_group_tiles(p4, tile4);
   const GemmProb *dp1 = nullptr, *dp4 = nullptr;
-  TNA_TRY(arena_push(en->ar, p1.data(), nc, s, &dp1));
-  TNA_TRY(arena_push(en->ar, p4.data(), nc, s, &dp4));
-  // ---- capture one Lanczos iteration (H_eff + CGS2 + record + normalise + advance);
-  // with kernel timing on, the iteration is launched directly instead so that
-  // events can bracket single kernels
+  int tot1 = 0, tot4 = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   const bool use_graph = !(timing_may_match("gemmg") || timing_may_match("mixg") || timing_may_match("lz."));
@@ -388,33 +429,177 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     TNA_TRY(gemm_grouped(g4, dp4, nc, tot4, s));
     return lz_iteration(dlp, nc, maxG, maxk, lz_bytes, s);
   };
-  if (use_graph) {
-    TNA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    tna_status cs = gemm_grouped(g1, dp1, nc, tot1, s);
-    if (cs == TNA_OK) cs = mix_grouped(dmx, nc, max_mix, D, d * d, d * d, D, f32, s);
-    if (cs == TNA_OK) cs = gemm_grouped(g4, dp4, nc, tot4, s);
-    if (cs == TNA_OK) cs = lz_iteration(dlp, nc, maxG, maxk, 0.0, s);
-    hipError_t ce = hipStreamEndCapture(s, &graph);
-    if (cs != TNA_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return cs;
+  if (nbig > 0) {
+    // small visits take no part in the grouped launches (their active flag is off here)
+    if (nsmall > 0) {
+      for (int q = 0; q < nc; ++q) en->hflags[en->nslot + slot[q]] = !small[q];
+      TNA_TRY(push_act());
     }
-    if (ce != hipSuccess) {
-      set_error(std::string("graph capture: ") + hipGetErrorString(ce));
-      return TNA_ERR_DEVICE;
-    }
-    hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-    if (ie != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
-      return TNA_ERR_DEVICE;
+    // tile choice for the two H_eff GEMMs, measured before capture (j = 0)
+    std::vector<GemmProb> b1, b4;
+    for (int q = 0; q < nc; ++q)
+      if (!small[q]) {
+        b1.push_back(s1[q]);
+        b4.push_back(s4[q]);
+      }
+    TNA_TRY(tuned_gemm(1, g1, b1, en->ar, s, true, &tile1));
+    TNA_TRY(tuned_gemm(2, g4, b4, en->ar, s, true, &tile4));
+    TNA_TRY(arena_push(en->ar, mx.data(), nc, s, &dmx));
+    std::vector<GemmProb> p1 = s1, p4 = s4;
+    g1.tile = tile1;
+    g4.tile = tile4;
+    g1.flops = group_flops(b1);
+    g4.flops = group_flops(b4);
+    tot1 = gemm_group_tiles(p1, tile1);
+    tot4 = gemm_group_tiles(p4, tile4);
+    TNA_TRY(arena_push(en->ar, p1.data(), nc, s, &dp1));
+    TNA_TRY(arena_push(en->ar, p4.data(), nc, s, &dp4));
+    // capture one Lanczos iteration (H_eff + CGS2 + record + normalise + advance); with
+    // kernel timing on, the iteration is launched directly so that events can bracket
+    // single kernels
+    if (use_graph) {
+      TNA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      tna_status cs = gemm_grouped(g1, dp1, nc, tot1, s);
+      if (cs == TNA_OK) cs = mix_grouped(dmx, nc, max_mix, D, d * d, d * d, D, f32, s);
+      if (cs == TNA_OK) cs = gemm_grouped(g4, dp4, nc, tot4, s);
+      if (cs == TNA_OK) cs = lz_iteration(dlp, nc, maxG, maxk, 0.0, s);
+      hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (cs != TNA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cs;
+      }
+      if (ce != hipSuccess) {
+        set_error(std::string("graph capture: ") + hipGetErrorString(ce));
+        return TNA_ERR_DEVICE;
+      }
+      hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
+        return TNA_ERR_DEVICE;
+      }
     }
   }
-  // ---- lockstep Lanczos: replay, read every chain's (alpha_j, beta_j^2), decide on the host
+  // ---- per-chain decisions on each new (alpha_j, beta_j^2), as in the single-chain method
   std::vector<std::vector<double>> al(nc), be(nc), yv(nc);
-  std::vector<int> conv(nc, 0), nkeep(nc, 0), iters(nc, 0), restart(nc, 0), act(nc, 1);
+  std::vector<int> conv(nc, 0), nkeep(nc, 0), iters(nc, 0), restart(nc, 0), act(nc, 0);
   std::vector<double> Ec(nc, 0.0);
   tna_status lst = TNA_OK;
+  // returns true when chain q stops (converged, breakdown or kmax)
+  auto take = [&](int q, double a, double b2) -> bool {
+    al[q].push_back(a);
+    be[q].push_back(std::sqrt(b2));
+    iters[q] += 1;
+    const int nn = (int)al[q].size();
+    yv[q].assign(nn, 0.0);
+    Ec[q] = tridiag_lowest_host(nn, al[q].data(), be[q].data(), yv[q].data());
+    const double resid = std::fabs(be[q][nn - 1] * yv[q][nn - 1]);
+    bool stop = false;
+    if (vs[q].fixed > 0) {
+      if (nn >= vs[q].kmax || be[q][nn - 1] < 1e-14) stop = conv[q] = 1;
+    } else if (resid <= ch[q]->opts.lanczos_tol * std::max(1.0, std::fabs(Ec[q])) || be[q][nn - 1] < 1e-14) {
+      stop = conv[q] = 1;
+    } else if (nn >= vs[q].kmax) {
+      stop = true;
+    }
+    if (stop) {
+      nkeep[q] = nn;
+      act[q] = 0;
+    }
+    return stop;
+  };
+  // chains in `set` that stopped at kmax unconverged restart from their Ritz vector
+  auto restart_stopped = [&](const std::vector<int> &set) -> tna_status {
+    std::vector<int> rs(nc, 0);
+    bool any = false;
+    for (int q = 0; q < nc; ++q) {
+      rs[q] = set[q] && !act[q] && !conv[q] && nkeep[q] > 0 && restart[q] < ch[q]->opts.lanczos_restarts;
+      any = any || rs[q];
+    }
+    if (!any) return TNA_OK;
+    for (int q = 0; q < nc; ++q) {
+      en->hflags[en->nslot + slot[q]] = rs[q];
+      lp[q].nkeep = rs[q] ? nkeep[q] : 0;
+      if (rs[q]) TNA_TRY(put_dev(en->ar, yv[q].data(), (size_t)nkeep[q], lp[q].y, s));
+    }
+    TNA_TRY(push_act());
+    const LzProb *dr = nullptr;
+    TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dr));
+    TNA_TRY(lz_ritz(dr, nc, maxG, s));
+    TNA_TRY(lz_start(dr, nc, maxG, s));
+    for (int q = 0; q < nc; ++q) {
+      if (!rs[q]) continue;
+      restart[q] += 1;
+      al[q].clear();
+      be[q].clear();
+      nkeep[q] = 0;
+      act[q] = 1;
+      en->hflags[slot[q]] = 0;
+      TNA_TRY(put_dev(en->ar, en->hflags.data() + slot[q], 1, j_dev + slot[q], s));
+    }
+    return TNA_OK;
+  };
+  // ---- single-workgroup path: launches of several iterations, then one read of the records
+  if (nsmall > 0) {
+    std::vector<LzSmall> sp;
+    std::vector<int> sq;  // chain of each descriptor
+    double *rec_small = en->recs.as<double>();
+    for (int q = 0; q < nc; ++q) {
+      if (!small[q]) continue;
+      const Visit &v = vs[q];
+      const int sl = slot[q];
+      tna_dmrg dm = ch[q];
+      sp.push_back(LzSmall{v.chl, v.chr, v.kmax, sm_ac[q], dm->Le[v.b].as<double>(), dm->Re[v.b + 1].as<double>(),
+                           dm->M12.as<double>() + (size_t)I2 * I2 * v.b, lp[q].V, j_dev + sl, act_dev + sl,
+                           rec_small + (size_t)2 * LZ_HMAX * sl});
+      sq.push_back(q);
+      act[q] = 1;
+    }
+    const LzSmall *dsp = nullptr;
+    TNA_TRY(arena_push(en->ar, sp.data(), sp.size(), s, &dsp));
+    std::vector<int> start(nc, 0);
+    int chunk = 16;
+    for (;;) {
+      bool live = false;
+      for (int q : sq) live = live || act[q];
+      if (!live) break;
+      for (int q = 0; q < nc; ++q) en->hflags[en->nslot + slot[q]] = small[q] && act[q];
+      TNA_TRY(push_act());
+      TNA_TRY(lz_small(dsp, (int)sp.size(), D, d * d, chunk, lds_small, s));
+      en->small_launches += 1;
+      TNA_HIP(hipMemcpyAsync(en->h_j, j_dev, sizeof(int) * en->nslot, hipMemcpyDeviceToHost, s));
+      TNA_HIP(hipMemcpyAsync(en->h_rec, rec_small, sizeof(double) * 2 * LZ_HMAX * en->nslot, hipMemcpyDeviceToHost,
+                             s));
+      TNA_HIP(hipStreamSynchronize(s));
+      for (int q : sq) {
+        if (!act[q]) continue;
+        start[q] = (int)al[q].size();
+        const double *r = en->h_rec + (size_t)2 * LZ_HMAX * slot[q];
+        const int jn = en->h_j[slot[q]];
+        for (int t = (int)al[q].size(); t < jn && act[q]; ++t) {
+          if (!std::isfinite(r[2 * t]) || !std::isfinite(r[2 * t + 1])) {
+            set_error("lanczos: non-finite coefficient");
+            return TNA_ERR_NONFINITE;
+          }
+          take(q, r[2 * t], r[2 * t + 1]);
+        }
+        if (act[q] && jn <= start[q]) {
+          set_error("lanczos (single-workgroup path): no progress");
+          return TNA_ERR_DEVICE;
+        }
+      }
+      TNA_TRY(restart_stopped(small));
+      chunk = 8;
+    }
+  }
+  // ---- lockstep grouped path: replay, read every chain's (alpha_j, beta_j^2), decide on the host
+  for (int q = 0; q < nc; ++q) act[q] = !small[q];
+  std::vector<int> bigset(nc);
+  for (int q = 0; q < nc; ++q) bigset[q] = !small[q];
+  if (nbig > 0 && nsmall > 0) {
+    for (int q = 0; q < nc; ++q) en->hflags[en->nslot + slot[q]] = act[q];
+    TNA_TRY(push_act());
+  }
   for (;;) {
     int live = 0;
     for (int q = 0; q < nc; ++q) live += act[q];
@@ -441,61 +626,14 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
         lst = TNA_ERR_NONFINITE;
         break;
       }
-      al[q].push_back(a);
-      be[q].push_back(std::sqrt(b2));
-      iters[q] += 1;
-      const int nn = (int)al[q].size();
-      yv[q].assign(nn, 0.0);
-      Ec[q] = tridiag_lowest_host(nn, al[q].data(), be[q].data(), yv[q].data());
-      const double resid = std::fabs(be[q][nn - 1] * yv[q][nn - 1]);
-      bool stop = false;
-      if (vs[q].fixed > 0) {
-        if (nn >= vs[q].kmax || be[q][nn - 1] < 1e-14) stop = conv[q] = 1;
-      } else if (resid <= ch[q]->opts.lanczos_tol * std::max(1.0, std::fabs(Ec[q])) || be[q][nn - 1] < 1e-14) {
-        stop = conv[q] = 1;
-      } else if (nn >= vs[q].kmax) {
-        stop = true;
-      }
-      if (stop) {
-        nkeep[q] = nn;
-        act[q] = 0;
-        changed = true;
-      }
+      changed = take(q, a, b2) || changed;
     }
     if (lst != TNA_OK) break;
     if (!changed) continue;
-    // chains that stopped at kmax unconverged restart from their Ritz vector
-    std::vector<int> rs(nc, 0);
-    bool any = false;
-    for (int q = 0; q < nc; ++q) {
-      rs[q] = !act[q] && !conv[q] && nkeep[q] > 0 && restart[q] < ch[q]->opts.lanczos_restarts;
-      any = any || rs[q];
-    }
-    if (any) {
-      for (int q = 0; q < nc; ++q) {
-        en->h_ints[en->nslot + slot[q]] = rs[q];
-        lp[q].nkeep = rs[q] ? nkeep[q] : 0;
-        if (rs[q]) TNA_HIP(hipMemcpyAsync(lp[q].y, yv[q].data(), sizeof(double) * nkeep[q], hipMemcpyHostToDevice, s));
-      }
-      TNA_HIP(hipMemcpyAsync(act_dev, en->h_ints + en->nslot, sizeof(int) * en->nslot, hipMemcpyHostToDevice, s));
-      const LzProb *dr = nullptr;
-      TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dr));
-      TNA_TRY(lz_ritz(dr, nc, maxG, s));
-      TNA_TRY(lz_start(dr, nc, maxG, s));
-      for (int q = 0; q < nc; ++q) {
-        if (!rs[q]) continue;
-        restart[q] += 1;
-        al[q].clear();
-        be[q].clear();
-        nkeep[q] = 0;
-        act[q] = 1;
-        en->h_ints[slot[q]] = 0;
-        TNA_HIP(hipMemcpyAsync(j_dev + slot[q], en->h_ints + slot[q], sizeof(int), hipMemcpyHostToDevice, s));
-      }
-    }
-    for (int q = 0; q < nc; ++q) en->h_ints[en->nslot + slot[q]] = act[q];
-    TNA_HIP(hipMemcpyAsync(act_dev, en->h_ints + en->nslot, sizeof(int) * en->nslot, hipMemcpyHostToDevice, s));
-    TNA_HIP(hipStreamSynchronize(s));  // pinned flags are rewritten next round
+    lst = restart_stopped(bigset);
+    if (lst != TNA_OK) break;
+    for (int q = 0; q < nc; ++q) en->hflags[en->nslot + slot[q]] = act[q];
+    TNA_TRY(push_act());
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
   if (graph) (void)hipGraphDestroy(graph);
@@ -503,12 +641,12 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   // ---- Ritz vectors
   for (int q = 0; q < nc; ++q) {
     lp[q].nkeep = nkeep[q];
-    en->h_ints[en->nslot + slot[q]] = 1;
+    en->hflags[en->nslot + slot[q]] = 1;
     en->lanczos_iters += iters[q];
     if (!conv[q] && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
-    TNA_HIP(hipMemcpyAsync(lp[q].y, yv[q].data(), sizeof(double) * nkeep[q], hipMemcpyHostToDevice, s));
+    TNA_TRY(put_dev(en->ar, yv[q].data(), (size_t)nkeep[q], lp[q].y, s));
   }
-  TNA_HIP(hipMemcpyAsync(act_dev, en->h_ints + en->nslot, sizeof(int) * en->nslot, hipMemcpyHostToDevice, s));
+  TNA_TRY(push_act());
   {
     const LzProb *dr = nullptr;
     TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dr));
@@ -591,7 +729,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   }
   // proposals for each bond's next visit (one forward per network)
   if (!want_pred.empty()) {
-    TNA_HIP(hipMemcpyAsync(en->feat_d.ptr, en->h_feat, sizeof(float) * 32 * nc, hipMemcpyHostToDevice, s));
+    TNA_TRY(put_dev(en->ar, en->h_feat, (size_t)32 * nc, en->feat_d.as<float>(), s));
     for (size_t i = 0; i < want_pred.size(); ++i) {
       const int q = want_pred[i];
       TNA_TRY(mlp_forward_dev(ch[q]->sched, 1, en->feat_d.as<float>() + 32 * q, en->y_d.as<float>() + 4 * q));
@@ -830,5 +968,10 @@ tna_status tna_autotune_load(const char *path) {
 }
 
 int tna_autotune_entries(void) { return (int)g_tune.table.size(); }
+
+void tna_autotune_clear(void) {
+  g_tune.table.clear();
+  g_tune.measured = 0;
+}
 
 }  // extern "C"

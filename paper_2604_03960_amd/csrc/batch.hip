@@ -206,6 +206,120 @@ __global__ __launch_bounds__(NT) void lz_combine_kernel(const LzProb *probs) {
   }
 }
 
+// ------------------------------------------------------------------ single-workgroup Lanczos
+// Whole Lanczos iterations of one short theta inside one workgroup (grid x =
+// chain).  H_eff (Eq. 1's contraction in the order L, W_i W_{i+1}, R) reads
+// L, R^T and the two-site mixing matrix from LDS: the left and mixing stages
+// are fused per (a, c') with the DD = D d^2 channels in registers, the right
+// stage sums over (w'', c').  CGS2 against the basis in global memory follows;
+// alpha_j, beta_j^2 of every iteration go to rec[2j], rec[2j+1].  A workgroup
+// stops at kmax, after `iters` iterations, or when beta_j is negligible.
+template <int D, int DD>
+__global__ __launch_bounds__(NT) void lz_small_kernel(const LzSmall *probs, int iters) {
+  extern __shared__ double lds[];
+  const LzSmall &p = probs[blockIdx.x];
+  if (!*p.active) return;
+  constexpr int dd = DD / D;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int chl = p.chl, chr = p.chr, ac = p.ac;
+  const int n = chl * dd * chr;
+  double *th = lds;                                  // n: V_j
+  double *wv = th + n;                               // n: H V_j, then orthogonalised
+  double *Ls = wv + n;                               // L[a][w][a']
+  double *RT = Ls + (size_t)chl * D * chl;           // RT[(w'' chr + c') chr + c] = R[c][w''][c']
+  double *Ms = RT + (size_t)chr * D * chr;           // M[(s t w'')][(w s' t')]
+  double *Zc = Ms + DD * DD;                         // Zc[al][(s t w'')][c'] for a chunk of ac rows
+  double *hb = Zc + (size_t)ac * DD * chr;           // h of the two CGS passes
+  double *red = hb + 2 * LZ_HMAX;
+  for (int e = tid; e < chl * D * chl; e += NT) Ls[e] = p.L[e];
+  for (int e = tid; e < chr * D * chr; e += NT) {
+    const int c = e / (D * chr), r = e - c * (D * chr);
+    RT[(size_t)r * chr + c] = p.R[e];
+  }
+  for (int e = tid; e < DD * DD; e += NT) Ms[e] = p.M[e];
+  int j = *p.j;
+  for (int it = 0; it < iters && j < p.kmax; ++it) {
+    const double *vj = p.V + (int64_t)j * n;
+    double *vn = p.V + (int64_t)(j + 1) * n;
+    __syncthreads();  // previous iteration done with th, wv and hb
+    for (int e = tid; e < n; e += NT) th[e] = vj[e];
+    __syncthreads();
+    for (int a0 = 0; a0 < chl; a0 += ac) {
+      const int na = chl - a0 < ac ? chl - a0 : ac;
+      for (int e = tid; e < na * chr; e += NT) {
+        const int al = e / chr, cp = e - al * chr;
+        const double *La = Ls + (size_t)(a0 + al) * D * chl;
+        double x[DD];
+#pragma unroll
+        for (int i = 0; i < DD; ++i) x[i] = 0.0;
+        for (int ap = 0; ap < chl; ++ap) {
+          double tv[dd];
+#pragma unroll
+          for (int st = 0; st < dd; ++st) tv[st] = th[(ap * dd + st) * chr + cp];
+#pragma unroll
+          for (int w = 0; w < D; ++w) {
+            const double l = La[w * chl + ap];
+#pragma unroll
+            for (int st = 0; st < dd; ++st) x[w * dd + st] += l * tv[st];
+          }
+        }
+        double *z = Zc + (size_t)al * DD * chr + cp;
+#pragma unroll
+        for (int o = 0; o < DD; ++o) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < DD; ++i) acc += Ms[o * DD + i] * x[i];
+          z[(size_t)o * chr] = acc;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < na * dd * chr; e += NT) {
+        const int al = e / (dd * chr), r = e - al * (dd * chr), st = r / chr, c = r - st * chr;
+        const double *z = Zc + ((size_t)al * DD + st * D) * chr;
+        double acc = 0.0;
+        for (int q = 0; q < D * chr; ++q) acc += z[q] * RT[(size_t)q * chr + c];
+        wv[((a0 + al) * dd + st) * chr + c] = acc;
+      }
+      __syncthreads();
+    }
+    // CGS2 against V_0..V_j
+    double b2 = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double *h = hb + pass * LZ_HMAX;
+      for (int i = wave; i <= j; i += NT / 64) {
+        const double *vi = p.V + (int64_t)i * n;
+        double acc = 0.0;
+        for (int e = lane; e < n; e += 64) acc += vi[e] * wv[e];
+        acc = wave_sum(acc);
+        if (lane == 0) h[i] = acc;
+      }
+      __syncthreads();
+      double loc = 0.0;
+      for (int e = tid; e < n; e += NT) {
+        double acc = 0.0;
+        for (int i = 0; i <= j; ++i) acc += h[i] * p.V[(int64_t)i * n + e];
+        const double v = wv[e] - acc;
+        wv[e] = v;
+        loc += v * v;
+      }
+      if (pass == 1) b2 = block_sum(loc, red);
+      else __syncthreads();
+    }
+    if (tid == 0) {
+      p.rec[2 * j] = hb[j];  // alpha_j from the first pass
+      p.rec[2 * j + 1] = b2;
+    }
+    // the host stops a chain at beta_j < 1e-14 (or a non-finite record): same predicate here
+    const double beta = sqrt(b2);
+    const bool stop = !(beta >= 1e-14);
+    const double f = stop ? 1.0 : 1.0 / beta;
+    for (int e = tid; e < n; e += NT) vn[e] = wv[e] * f;
+    ++j;
+    if (stop) break;
+  }
+  if (tid == 0) *p.j = j;
+}
+
 __global__ __launch_bounds__(NT) void convert_grouped_kernel(const CvtProb *probs) {
   const CvtProb &p = probs[blockIdx.y];
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < p.n; e += (int64_t)gridDim.x * NT) p.dst[e] = (float)p.src[e];
@@ -265,6 +379,45 @@ tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s) {
   hipLaunchKernelGGL(lz_norm_kernel, dim3(1, nch), dim3(NT), 0, s, d, 1, 1);
   hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 3, 1);
   TNA_LAUNCHED("lanczos.ritz");
+  return TNA_OK;
+}
+
+size_t lz_small_lds(int chl, int chr, int d, int D, int ac) {
+  const size_t n = (size_t)chl * d * d * chr, DD = (size_t)D * d * d;
+  return sizeof(double) * (2 * n + (size_t)chl * D * chl + (size_t)chr * D * chr + DD * DD + (size_t)ac * DD * chr +
+                           2 * LZ_HMAX + 8);
+}
+
+tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, hipStream_t s) {
+  if (nch < 1) return TNA_OK;
+  if (dsq != 4) {
+    set_error("lz_small: physical dimension 2 only");
+    return TNA_ERR_UNSUPPORTED;
+  }
+  void (*k)(const LzSmall *, int) = nullptr;
+  switch (D) {
+    case 3: k = lz_small_kernel<3, 12>; break;
+    case 5: k = lz_small_kernel<5, 20>; break;
+    case 8: k = lz_small_kernel<8, 32>; break;
+    default:
+      set_error("lz_small: MPO bond dimension must be 3, 5 or 8");
+      return TNA_ERR_UNSUPPORTED;
+  }
+  static bool attr_set[3] = {false, false, false};
+  const int slot = D == 3 ? 0 : (D == 5 ? 1 : 2);
+  if (!attr_set[slot]) {
+    TNA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)LZ_SMALL_LDS_MAX));
+    attr_set[slot] = true;
+  }
+  if (lds > LZ_SMALL_LDS_MAX) {
+    set_error("lz_small: LDS need above the limit");
+    return TNA_ERR_ARG;
+  }
+  timer_begin("lz.small", s);
+  hipLaunchKernelGGL(k, dim3(nch), dim3(NT), lds, s, d, iters);
+  timer_end("lz.small", 0.0, 0.0, s);
+  TNA_LAUNCHED("lanczos.small");
   return TNA_OK;
 }
 

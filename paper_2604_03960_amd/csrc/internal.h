@@ -154,6 +154,7 @@ tna_status set_identity(double *J, int n, int ld, int batch, int64_t stride, hip
 struct SvdMat {
   int m, n, R, C, trans, nb, ksplit, active;  // R = min(m,n) rows of length C are orthogonalised
   int k, dtype, out_type, scale_mode;         // kept rank; scale 0 none, 1 Vt rows, 2 U columns by S_j/|S_k|
+  int inner_max, fused;                        // cap on inner Jacobi sweeps; whole Jacobi in one workgroup
   double tol, eps_target;
   const void *A;                               // m x n (dtype)
   double *bw, *jt, *gram, *qt, *sig;           // work
@@ -162,6 +163,9 @@ struct SvdMat {
   int *skip, *perm, *ctr;                      // work
   void *U, *Vt;                                // m x k, k x n (out_type)
   double *fro2;                                // work: |A|_F^2 (device scalar)
+  int precond, pad2_;                          // 1: rows start from the R factor of a pivoted QR
+  double *hv, *cn;                             // work: Householder vector (R + 1, beta last), column norms (C)
+  int *cperm, *pinv;                           // work: original column at position c, and its inverse (C each)
 };
 struct SvdGroup {
   DevBuf desc, work_d, work_i;
@@ -208,6 +212,20 @@ struct LzProb {
 tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, double bytes_hint, hipStream_t s);
 tna_status lz_start(const LzProb *d, int nch, int maxG, hipStream_t s);
 tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s);
+// Single-workgroup Lanczos for short vectors (all of H_eff's operands in LDS).
+constexpr int LZ_HMAX = 128;                       // >= kmax + 1
+constexpr size_t LZ_SMALL_LDS_MAX = 160 * 1024;    // LDS of one gfx950 workgroup
+struct LzSmall {
+  int chl, chr, kmax, ac;  // ac: left indices per pass of the fused left/mixing stage
+  const double *L, *R, *M; // L[a][w][a'], R[c][w''][c'], mixing matrix (D d^2)^2
+  double *V;               // Krylov basis, V_0 set
+  int *j;
+  const int *active;
+  double *rec;             // 2 (kmax + 1): alpha_j, beta_j^2
+};
+size_t lz_small_lds(int chl, int chr, int d, int D, int ac);
+// Runs up to `iters` iterations for every active chain; lds = max over chains.
+tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, hipStream_t s);
 struct CvtProb {
   const double *src;
   float *dst;

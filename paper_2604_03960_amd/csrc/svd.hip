@@ -82,33 +82,23 @@ __device__ inline double bsum256(double v, double *red) {
 }
 
 // -------------------------------------------------------------- gram
-// grid (pairs, ksplit, matrices)
-__global__ __launch_bounds__(256) void gram_kernel(const SvdMat *mats, int step) {
-  constexpr int BK = 32;
-  __shared__ double Ts[BK][64 + 1];
-  const SvdMat &a = mats[blockIdx.z];
-  const int pair = blockIdx.x, ks = blockIdx.y;
-  if (!a.active || step >= a.nb - 1 || pair >= a.nb / 2 || ks >= a.ksplit) return;
-  int p, q;
-  rr_pair(a.nb, step, pair, p, q);
-  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
+// 64 x 64 Gram of the rows of blocks p and q over columns [kb, ke) on MFMA:
+// wave (qi, qj) holds the 32 x 32 quadrant (qi, qj) as 2 x 2 16 x 16 tiles.
+constexpr int GBK = 32;
+__device__ inline void gram_acc(const SvdMat &a, int p, int q, int np, int nq, int64_t kb, int64_t ke,
+                                double (*Ts)[65], v4d acc[2][2]) {
   const double *B = a.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int qi = wave >> 1, qj = wave & 1;
-  int64_t chunk = (a.C + a.ksplit - 1) / a.ksplit;
-  chunk = (chunk + BK - 1) / BK * BK;
-  const int64_t kb = chunk * ks;
-  const int64_t ke = kb + chunk < a.C ? kb + chunk : a.C;
-  v4d acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int col = tid % BK, r = tid / BK + 8 * u;
+      const int col = tid % GBK, r = tid / GBK + 8 * u;
       const bool valid = r < 32 ? (r < np) : (r - 32 < nq);
       const int grow = r < 32 ? p * BS + r : q * BS + (r - 32);
       const int64_t gc = k0 + col;
@@ -116,7 +106,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const SvdMat *mats, int step)
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    for (int kk = 0; kk < GBK; kk += 4) {
       double av[2], bv[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) av[i] = Ts[kk + lk][32 * qi + 16 * i + lr];
@@ -129,30 +119,182 @@ __global__ __launch_bounds__(256) void gram_kernel(const SvdMat *mats, int step)
     }
     __syncthreads();
   }
-  double *G = a.gram + ((int64_t)pair * a.ksplit + ks) * 4096;
+}
+
+// G[row * 64 + col] = acc (f64 result layout)
+__device__ inline void gram_store(const v4d acc[2][2], double *G, int ldg) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qi = wave >> 1, qj = wave & 1;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 32 * qi + 16 * i + 4 * r + lk, col = 32 * qj + 16 * j + lr;  // f64 result layout
-        G[row * 64 + col] = acc[i][j][r];
+        const int row = 32 * qi + 16 * i + 4 * r + lk, col = 32 * qj + 16 * j + lr;
+        G[row * ldg + col] = acc[i][j][r];
       }
 }
 
+// grid (pairs, ksplit, matrices)
+__global__ __launch_bounds__(256) void gram_kernel(const SvdMat *mats, int step) {
+  __shared__ double Ts[GBK][64 + 1];
+  const SvdMat &a = mats[blockIdx.z];
+  const int pair = blockIdx.x, ks = blockIdx.y;
+  if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2 || ks >= a.ksplit) return;
+  int p, q;
+  rr_pair(a.nb, step, pair, p, q);
+  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
+  int64_t chunk = (a.C + a.ksplit - 1) / a.ksplit;
+  chunk = (chunk + GBK - 1) / GBK * GBK;
+  const int64_t kb = chunk * ks;
+  const int64_t ke = kb + chunk < a.C ? kb + chunk : a.C;
+  v4d acc[2][2];
+  gram_acc(a, p, q, np, nq, kb, ke, Ts, acc);
+  gram_store(acc, a.gram + ((int64_t)pair * a.ksplit + ks) * 4096, 64);
+}
+
 // -------------------------------------------------------------- eigen
+// Two-sided cyclic Jacobi on the 64 x 64 Gram of a block pair, in LDS.
+struct EigLds {
+  double G[64][65];
+  double Q[64][65];
+  double cs[32], sn[32];
+  int pi[32], pj[32];
+  int rot_any, need;
+  int slot_of[64];
+};
+
+// Rows whose squared norm is at or below row_floor2 = (0.1 eps C)^2 |A|_F^2 are at the
+// rounding level of the rotations: their directions are noise, so pairs with such a
+// row are neither tested nor rotated (the relative test could never settle on them).
+// Skipping a coupling g_ij <= sigma_i sigma_floor moves sigma_i by at most
+// sigma_floor^2 / sigma_i; kept vectors below the floor are completed afterwards.
+// After the pivoted-QR start the rows are graded and even rows at the rounding level
+// settle under the relative test, so no floor is used there.
+__device__ inline double row_floor2(const SvdMat &a, double fro2) {
+  if (a.precond) return 0.0;
+  const double f = 0.1 * EPS53 * (double)a.C;
+  return f * f * fro2;
+}
+
+// Outer test: does any pair of rows above the floor fail |g_ij| <= tol sqrt(g_ii g_jj)?
+__device__ inline bool eig_needs_rotation(EigLds &L, double tol, double floor2) {
+  const int tid = threadIdx.x;
+  if (tid == 0) L.need = 0;
+  __syncthreads();
+  int loc = 0;
+  for (int e = tid; e < 4096; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (i < j) {
+      const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
+      if (gii > floor2 && gjj > floor2 && gii > 0.0 && gjj > 0.0 && fabs(gij) > tol * sqrt(gii * gjj)) loc = 1;
+    }
+  }
+  if (__any(loc) && (tid & 63) == 0) atomicOr(&L.need, 1);
+  __syncthreads();
+  return L.need != 0;
+}
+
+// Q <- Q J over sweeps of the round-robin ordering until a sweep rotates nothing
+// (or inner_max sweeps); the diagonal of G ends as the eigenvalues.
+__device__ inline void eig_inner(EigLds &L, int inner_max, double floor2) {
+  const int tid = threadIdx.x;
+  const double tol_in = 4.0 * EPS53;
+  for (int sweep = 0; sweep < inner_max; ++sweep) {
+    __syncthreads();  // every thread has read rot_any of the previous sweep
+    if (tid == 0) L.rot_any = 0;
+    __syncthreads();
+    for (int rr = 0; rr < 63; ++rr) {
+      // 32 disjoint pairs; rotation J = [[c, s], [-s, c]] on (i, j), i < j
+      if (tid < 32) {
+        int i, j;
+        if (tid == 0) { i = rr % 63; j = 63; }
+        else { i = (rr + tid) % 63; j = (rr - tid + 63) % 63; }
+        if (i > j) { const int t = i; i = j; j = t; }
+        const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
+        double c = 1.0, s = 0.0;
+        if (gii > floor2 && gjj > floor2 && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
+          const double zeta = (gjj - gii) / (2.0 * gij);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = c * t;
+          L.rot_any = 1;
+        }
+        L.cs[tid] = c; L.sn[tid] = s; L.pi[tid] = i; L.pj[tid] = j;
+      }
+      __syncthreads();
+      // G <- J^T G J one 2 x 2 block (pair t rows, pair u columns) at a time, t <= u, and
+      // the mirror block written from the same values so G stays exactly symmetric.  Rows
+      // t and 31 - t of the block triangle are dealt together: 33 blocks per row pair.
+      for (int e = tid; e < 528; e += 256) {
+        const int rp = e / 33, off = e - 33 * rp;
+        int t, u;
+        if (off < 32 - rp) { t = rp; u = rp + off; }
+        else { t = 31 - rp; u = t + (off - (32 - rp)); }
+        const double st = L.sn[t], su = L.sn[u];
+        if (st == 0.0 && su == 0.0) continue;
+        const double ct = L.cs[t], cu = L.cs[u];
+        const int a0 = L.pi[t], a1 = L.pj[t], b0 = L.pi[u], b1 = L.pj[u];
+        const double x00 = L.G[a0][b0], x01 = L.G[a0][b1], x10 = L.G[a1][b0], x11 = L.G[a1][b1];
+        const double y00 = ct * x00 - st * x10, y01 = ct * x01 - st * x11;
+        const double y10 = st * x00 + ct * x10, y11 = st * x01 + ct * x11;
+        const double z00 = cu * y00 - su * y01, z01 = su * y00 + cu * y01;
+        const double z10 = cu * y10 - su * y11, z11 = su * y10 + cu * y11;
+        if (t == u) {
+          L.G[a0][a0] = z00; L.G[a1][a1] = z11; L.G[a0][a1] = 0.0; L.G[a1][a0] = 0.0;
+        } else {
+          L.G[a0][b0] = z00; L.G[a0][b1] = z01; L.G[a1][b0] = z10; L.G[a1][b1] = z11;
+          L.G[b0][a0] = z00; L.G[b1][a0] = z01; L.G[b0][a1] = z10; L.G[b1][a1] = z11;
+        }
+      }
+      // Q <- Q J (pair index uniform across a wave)
+      for (int e = tid; e < 32 * 64; e += 256) {
+        const int u = e >> 6, k = e & 63;
+        const double su = L.sn[u];
+        if (su != 0.0) {
+          const double cu = L.cs[u];
+          const int i = L.pi[u], j = L.pj[u];
+          const double qi_ = L.Q[k][i], qj_ = L.Q[k][j];
+          L.Q[k][i] = cu * qi_ - su * qj_;
+          L.Q[k][j] = su * qi_ + cu * qj_;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = L.rot_any;
+    if (!any) break;
+  }
+}
+
+// slot_of[so] = eigen-slot whose vector becomes output row so: eigenvalues descending
+// (ties: lower slot first), the np largest to block p, the rest to block q
+__device__ inline void eig_order(EigLds &L, int np, int nq) {
+  const int r = threadIdx.x;
+  if (r < 64) {
+    const bool vr = r < 32 ? (r < np) : (r - 32 < nq);
+    if (vr) {
+      const double lr_ = L.G[r][r];
+      int rank = 0;
+      for (int o = 0; o < 64; ++o) {
+        const bool vo = o < 32 ? (o < np) : (o - 32 < nq);
+        if (o == r || !vo) continue;
+        const double lo = L.G[o][o];
+        if (lo > lr_ || (lo == lr_ && o < r)) ++rank;
+      }
+      L.slot_of[rank < np ? rank : 32 + (rank - np)] = r;
+    }
+  }
+  __syncthreads();
+}
+
 // grid (pairs, matrices)
 __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step) {
-  __shared__ double Gs[64][65];
-  __shared__ double Qs[64][65];
-  __shared__ double cs_[32], sn_[32];
-  __shared__ int pi_[32], pj_[32];
-  __shared__ int rot_any, need;
-  __shared__ int slot_of[64];
+  __shared__ EigLds L;
   const SvdMat &a = mats[blockIdx.y];
   const int pair = blockIdx.x;
-  if (!a.active || step >= a.nb - 1 || pair >= a.nb / 2) return;
+  if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2) return;
   const int tid = threadIdx.x;
   int p, q;
   rr_pair(a.nb, step, pair, p, q);
@@ -169,137 +311,34 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     double v = 0.0;
     for (int ks = 0; ks < a.ksplit; ++ks) v += Gp[(int64_t)ks * 4096 + lo * 64 + hi];
-    Gs[i][j] = (valid(i) && valid(j)) ? v : 0.0;
-    Qs[i][j] = (i == j) ? 1.0 : 0.0;
+    L.G[i][j] = (valid(i) && valid(j)) ? v : 0.0;
+    L.Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  if (tid == 0) need = 0;
-  // Couplings below eps |A|_F^2 cannot move any singular value by more than
-  // about eps |A|_F; rows at the rounding floor never meet a relative test, so
-  // both the outer test and the inner rotations ignore them.
-  const double fro2 = *a.fro2;
-  const double floor_out = 4.0 * EPS53 * fro2, floor_in = EPS53 * fro2;
-  __syncthreads();
-  {
-    int loc = 0;
-    for (int e = tid; e < 4096; e += 256) {
-      const int i = e >> 6, j = e & 63;
-      if (i < j) {
-        const double gii = Gs[i][i], gjj = Gs[j][j], gij = Gs[i][j];
-        if (gii > 0.0 && gjj > 0.0 && fabs(gij) > a.tol * sqrt(gii * gjj) && fabs(gij) > floor_out) loc = 1;
-      }
-    }
-    if (__any(loc) && (tid & 63) == 0) atomicOr(&need, 1);
-  }
-  __syncthreads();
-  if (!need) {
+  const double floor2 = row_floor2(a, *a.fro2);
+  if (!eig_needs_rotation(L, a.tol, floor2)) {
     if (tid == 0) *skip = 1;
     return;
   }
   if (tid == 0) atomicAdd(a.ctr, 1);
-  const double tol_in = 4.0 * EPS53;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    __syncthreads();  // every thread has read rot_any of the previous sweep
-    if (tid == 0) rot_any = 0;
-    __syncthreads();
-    for (int rr = 0; rr < 63; ++rr) {
-      if (tid < 32) {
-        int i, j;
-        if (tid == 0) { i = rr % 63; j = 63; }
-        else { i = (rr + tid) % 63; j = (rr - tid + 63) % 63; }
-        if (i > j) { const int t = i; i = j; j = t; }
-        const double gii = Gs[i][i], gjj = Gs[j][j], gij = Gs[i][j];
-        double c = 1.0, s = 0.0;
-        if (fabs(gij) > floor_in && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
-          const double zeta = (gjj - gii) / (2.0 * gij);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = c * t;
-          rot_any = 1;
-        }
-        cs_[tid] = c; sn_[tid] = s; pi_[tid] = i; pj_[tid] = j;
-      }
-      __syncthreads();
-      for (int e = tid; e < 32 * 64; e += 256) {  // rows i, j of G
-        const int t = e >> 6, k = e & 63;
-        const double s = sn_[t];
-        if (s != 0.0) {
-          const double c = cs_[t];
-          const int i = pi_[t], j = pj_[t];
-          const double gi = Gs[i][k], gj = Gs[j][k];
-          Gs[i][k] = c * gi - s * gj;
-          Gs[j][k] = s * gi + c * gj;
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < 32 * 64; e += 256) {  // columns i, j of G and of Q
-        const int t = e >> 6, k = e & 63;
-        const double s = sn_[t];
-        if (s != 0.0) {
-          const double c = cs_[t];
-          const int i = pi_[t], j = pj_[t];
-          const double gi = Gs[k][i], gj = Gs[k][j];
-          double ni = c * gi - s * gj, nj = s * gi + c * gj;
-          if (k == i) nj = 0.0;
-          if (k == j) ni = 0.0;
-          Gs[k][i] = ni;
-          Gs[k][j] = nj;
-          const double qi_ = Qs[k][i], qj_ = Qs[k][j];
-          Qs[k][i] = c * qi_ - s * qj_;
-          Qs[k][j] = s * qi_ + c * qj_;
-        }
-      }
-      __syncthreads();
-    }
-    const int any = rot_any;
-    if (!any) break;
-  }
-  // eigenvalues descending (ties: lower slot first), larger ones to block p
-  if (tid < 64) {
-    const int r = tid;
-    if (valid(r)) {
-      const double lr_ = Gs[r][r];
-      int rank = 0;
-      for (int o = 0; o < 64; ++o) {
-        if (o == r || !valid(o)) continue;
-        const double lo = Gs[o][o];
-        if (lo > lr_ || (lo == lr_ && o < r)) ++rank;
-      }
-      slot_of[rank < np ? rank : 32 + (rank - np)] = r;
-    }
-  }
-  __syncthreads();
+  eig_inner(L, a.inner_max, floor2);
+  eig_order(L, np, nq);
   double *Qt = a.qt + (int64_t)pair * 4096;
   for (int e = tid; e < 4096; e += 256) {
     const int so = e >> 6, ri = e & 63;
-    Qt[e] = (valid(so) && valid(ri)) ? Qs[ri][slot_of[so]] : 0.0;
+    Qt[e] = (valid(so) && valid(ri)) ? L.Q[ri][L.slot_of[so]] : 0.0;
   }
   if (tid == 0) *skip = 0;
 }
 
 // -------------------------------------------------------------- apply
-// grid (pairs, column tiles of B then of Jt, matrices)
-__global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step) {
-  __shared__ double As[64][65];  // As[k][i] = Qt[i][k]
-  __shared__ double Xs[64][65];  // Xs[k][j] = X[row(k)][c0 + j]
-  const SvdMat &a = mats[blockIdx.z];
-  const int pair = blockIdx.x, tile = blockIdx.y;
-  const int ntile_b = (a.C + 63) / 64, ntile_j = (a.R + 63) / 64;
-  if (!a.active || step >= a.nb - 1 || pair >= a.nb / 2 || tile >= ntile_b + ntile_j) return;
-  if (a.skip[pair]) return;
-  int p, q;
-  rr_pair(a.nb, step, pair, p, q);
-  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
-  auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
-  auto grow = [&](int r) { return r < 32 ? p * BS + r : q * BS + (r - 32); };
-  double *X;
-  int ld, c0;
-  if (tile < ntile_b) { X = a.bw; ld = a.C; c0 = tile * 64; }
-  else { X = a.jt; ld = a.R; c0 = (tile - ntile_b) * 64; }
-  const double *Qt = a.qt + (int64_t)pair * 4096;
+// rows of X (valid slots, row grow(slot)) columns [c0, c0 + 64) <- Qt X, with
+// As[k][i] = Qt[i][k] in LDS; Xs is the staging tile
+template <class Valid, class Grow>
+__device__ inline void apply_tile(double *X, int ld, int c0, double (*As)[65], double (*Xs)[65], Valid valid,
+                                  Grow grow) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 4096; e += 256) {
     const int i = e >> 6, k = e & 63;
-    As[k][i] = Qt[e];
     Xs[i][k] = (valid(i) && c0 + k < ld) ? X[(int64_t)grow(i) * ld + c0 + k] : 0.0;
   }
   __syncthreads();
@@ -321,6 +360,87 @@ __global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step
       const int so = 16 * wave + 4 * r + lk, col = 16 * t + lr;  // f64 result layout
       if (valid(so) && c0 + col < ld) X[(int64_t)grow(so) * ld + c0 + col] = acc[t][r];
     }
+}
+
+// grid (pairs, column tiles of B then of Jt, matrices)
+__global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step) {
+  __shared__ double As[64][65];  // As[k][i] = Qt[i][k]
+  __shared__ double Xs[64][65];  // Xs[k][j] = X[row(k)][c0 + j]
+  const SvdMat &a = mats[blockIdx.z];
+  const int pair = blockIdx.x, tile = blockIdx.y;
+  const int ntile_b = (a.C + 63) / 64, ntile_j = (a.R + 63) / 64;
+  if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2 || tile >= ntile_b + ntile_j) return;
+  if (a.skip[pair]) return;
+  int p, q;
+  rr_pair(a.nb, step, pair, p, q);
+  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
+  auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
+  auto grow = [&](int r) { return r < 32 ? p * BS + r : q * BS + (r - 32); };
+  double *X;
+  int ld, c0;
+  if (tile < ntile_b) { X = a.bw; ld = a.C; c0 = tile * 64; }
+  else { X = a.jt; ld = a.R; c0 = (tile - ntile_b) * 64; }
+  const double *Qt = a.qt + (int64_t)pair * 4096;
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int i = e >> 6, k = e & 63;
+    As[k][i] = Qt[e];
+  }
+  apply_tile(X, ld, c0, As, Xs, valid, grow);
+}
+
+// -------------------------------------------------------------- whole Jacobi, one workgroup
+// Matrices with at most 64 rows to orthogonalise (one block pair) run every
+// sweep inside one workgroup: Gram on MFMA into LDS, the outer test, the inner
+// Jacobi, then the rotation of B and Jt, until a sweep needs no rotation.
+// ctr[0] = 0 when converged (1 otherwise), ctr[1] = sweeps.  grid (matrices)
+__global__ __launch_bounds__(256) void jacobi_fused_kernel(const SvdMat *mats, int max_sweeps) {
+  __shared__ EigLds L;
+  __shared__ double Xs[64][65];  // Gram staging, then apply tiles
+  const SvdMat &a = mats[blockIdx.x];
+  if (!a.active || !a.fused) return;
+  const int tid = threadIdx.x;
+  const int np = block_rows(a.R, 0), nq = block_rows(a.R, 1);
+  auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
+  auto grow = [](int r) { return r; };  // blocks 0 and 1: slot r is row r
+  const double floor2 = row_floor2(a, *a.fro2);
+  int sw = 0, conv = 0;
+  while (sw < max_sweeps) {
+    ++sw;
+    v4d acc[2][2];
+    gram_acc(a, 0, 1, np, nq, 0, a.C, reinterpret_cast<double (*)[65]>(&Xs[0][0]), acc);
+    gram_store(acc, &L.Q[0][0], 65);  // raw Gram, then the symmetric copy below
+    __syncthreads();
+    for (int e = tid; e < 4096; e += 256) {
+      const int i = e >> 6, j = e & 63;
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      L.G[i][j] = (valid(i) && valid(j)) ? L.Q[lo][hi] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 4096; e += 256) L.Q[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
+    if (!eig_needs_rotation(L, a.tol, floor2)) {
+      conv = 1;
+      break;
+    }
+    eig_inner(L, a.inner_max, floor2);
+    eig_order(L, np, nq);
+    // As[k][i] = Qt[i][k] = Q[k][slot_of[i]], written over G
+    for (int e = tid; e < 4096; e += 256) {
+      const int k = e >> 6, i = e & 63;
+      L.G[k][i] = (valid(i) && valid(k)) ? L.Q[k][L.slot_of[i]] : 0.0;
+    }
+    __syncthreads();
+    const int ntile_b = (a.C + 63) / 64;
+    for (int t = 0; t < ntile_b; ++t) {
+      apply_tile(a.bw, a.C, 64 * t, L.G, Xs, valid, grow);
+      __syncthreads();
+    }
+    apply_tile(a.jt, a.R, 0, L.G, Xs, valid, grow);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.ctr[0] = conv ? 0 : 1;
+    a.ctr[1] = sw;
+  }
 }
 
 // -------------------------------------------------------------- load / init
@@ -375,7 +495,162 @@ __global__ __launch_bounds__(256) void fro_kernel(const SvdMat *mats) {
 
 __global__ void zero_ctr_kernel(const SvdMat *mats, int nmat) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z < nmat && mats[z].active) *mats[z].ctr = 0;
+  if (z < nmat && mats[z].active && !mats[z].fused) *mats[z].ctr = 0;
+}
+
+// -------------------------------------------------------------- pivoted QR start
+// Householder QR with column pivoting of the loaded rows, B P = Q Rf, turns the
+// start state (B, Jt) = (A, I) into (Rf, Q^T): B = Jt A (up to the column
+// order, recorded in cperm) still holds, and the rows of Rf are graded, which
+// the one-sided Jacobi needs far fewer sweeps on than on A itself.  Step k:
+// one workgroup per matrix picks the trailing column of largest norm, swaps it
+// to k and forms the reflector; then every column of the trailing B and of Jt
+// is reflected (and the trailing norms recomputed) independently.
+constexpr int QR_MIN_ROWS_DEV = 256;
+
+// grid (column blocks, 1, matrices): column norms and the identity order
+__global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
+  const SvdMat &a = mats[blockIdx.z];
+  if (!a.active || !a.precond) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= a.C) return;
+  double s = 0.0;
+  for (int i = 0; i < a.R; ++i) {
+    const double v = a.bw[(int64_t)i * a.C + j];
+    s += v * v;
+  }
+  a.cn[j] = s;
+  a.cperm[j] = j;
+}
+
+// grid (matrices): pivot, column swap, reflector v = x - alpha e_0 of x = B[k:R, k]
+__global__ __launch_bounds__(256) void qr_pivot_kernel(const SvdMat *mats, int k) {
+  __shared__ double bv[4], red[4];
+  __shared__ int bi[4], piv;
+  __shared__ double xs0, nrm;
+  const SvdMat &a = mats[blockIdx.x];
+  if (!a.active || !a.precond || k >= a.R) return;
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bidx = 0x7fffffff;
+  for (int j = k + tid; j < a.C; j += 256) {
+    const double v = a.cn[j];
+    if (v > best) { best = v; bidx = j; }  // increasing j per thread: ties keep the lowest
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bidx, off, 64);
+    if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+  }
+  if ((tid & 63) == 0) { bv[tid >> 6] = best; bi[tid >> 6] = bidx; }
+  __syncthreads();
+  if (tid == 0) {
+    double b = bv[0];
+    int ii = bi[0];
+    for (int w = 1; w < 4; ++w)
+      if (bv[w] > b || (bv[w] == b && bi[w] < ii)) { b = bv[w]; ii = bi[w]; }
+    piv = (ii >= k && ii < a.C) ? ii : k;
+  }
+  __syncthreads();
+  const int p = piv;
+  if (p != k) {
+    for (int i = tid; i < a.R; i += 256) {
+      const int64_t r = (int64_t)i * a.C;
+      const double t = a.bw[r + k];
+      a.bw[r + k] = a.bw[r + p];
+      a.bw[r + p] = t;
+    }
+    if (tid == 0) {
+      const double tc = a.cn[k];
+      a.cn[k] = a.cn[p];
+      a.cn[p] = tc;
+      const int tp = a.cperm[k];
+      a.cperm[k] = a.cperm[p];
+      a.cperm[p] = tp;
+    }
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int i = k + tid; i < a.R; i += 256) {
+    const double v = a.bw[(int64_t)i * a.C + k];
+    s += v * v;
+  }
+  s = bsum256(s, red);
+  if (tid == 0) {
+    xs0 = a.bw[(int64_t)k * a.C + k];
+    nrm = sqrt(s);
+  }
+  __syncthreads();
+  const double x0 = xs0, nx = nrm;
+  // alpha = -sign(x0) |x|, v_0 = x0 - alpha, beta = 2 / v^T v = 1 / (|x| (|x| + |x0|))
+  const double alpha = x0 >= 0.0 ? -nx : nx;
+  const double beta = nx > 0.0 ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+  for (int i = k + tid; i < a.R; i += 256) {
+    const int64_t r = (int64_t)i * a.C + k;
+    const double v = (i == k) ? x0 - alpha : a.bw[r];
+    a.hv[i] = v;
+    a.bw[r] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
+  }
+  if (tid == 0) a.hv[a.R] = beta;
+}
+
+// grid (column blocks of B[:, k+1:] then of Jt, 1, matrices), 32 columns x 8 row groups:
+// X[k:, j] -= beta (v^T X[k:, j]) v; trailing norms of B recomputed from rows k+1..
+__global__ __launch_bounds__(256) void qr_update_kernel(const SvdMat *mats, int k) {
+  __shared__ double part[8][33];
+  const SvdMat &a = mats[blockIdx.z];
+  if (!a.active || !a.precond || k >= a.R) return;
+  const int nbB = (a.C - k - 1 + 31) / 32, nbJ = (a.R + 31) / 32;
+  const int blk = blockIdx.x;
+  if (blk >= nbB + nbJ) return;
+  const bool isB = blk < nbB;
+  double *X = isB ? a.bw : a.jt;
+  const int ld = isB ? a.C : a.R;
+  const int ncol = isB ? a.C : a.R;
+  const int j = isB ? k + 1 + blk * 32 + (threadIdx.x & 31) : (blk - nbB) * 32 + (threadIdx.x & 31);
+  const int rg = threadIdx.x >> 5;
+  const double beta = a.hv[a.R];
+  const bool colok = j < ncol;
+  double w = 0.0;
+  if (colok)
+    for (int i = k + rg; i < a.R; i += 8) w += a.hv[i] * X[(int64_t)i * ld + j];
+  part[rg][threadIdx.x & 31] = w;
+  __syncthreads();
+  double wt = 0.0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g) wt += part[g][threadIdx.x & 31];
+  const double f = beta * wt;
+  double nn = 0.0;
+  if (colok && beta != 0.0)
+    for (int i = k + rg; i < a.R; i += 8) {
+      const int64_t r = (int64_t)i * ld + j;
+      const double v = X[r] - f * a.hv[i];
+      X[r] = v;
+      if (i > k) nn += v * v;
+    }
+  else if (colok)
+    for (int i = k + 1 + rg; i < a.R; i += 8) {
+      const double v = X[(int64_t)i * ld + j];
+      nn += v * v;
+    }
+  if (!isB) return;
+  __syncthreads();
+  part[rg][threadIdx.x & 31] = nn;
+  __syncthreads();
+  if (rg == 0 && colok) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) t += part[g][threadIdx.x & 31];
+    a.cn[j] = t;
+  }
+}
+
+// grid (column blocks, 1, matrices)
+__global__ __launch_bounds__(256) void qr_pinv_kernel(const SvdMat *mats) {
+  const SvdMat &a = mats[blockIdx.z];
+  if (!a.active || !a.precond) return;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < a.C) a.pinv[a.cperm[c]] = c;
 }
 
 // -------------------------------------------------------------- finish
@@ -504,11 +779,21 @@ __global__ __launch_bounds__(256) void trunc_kernel(const SvdMat *mats) {
   }
 }
 
+// Kept values at or below this are null: at the rounding level of sigma_0 or under the
+// Jacobi row floor (whose rows were never orthogonalised against the others).  With the
+// pivoted-QR start every row with a nonzero norm was orthogonalised, so only rows whose
+// squares underflow count as null there.
+__device__ inline double null_threshold(const SvdMat &a) {
+  if (a.precond) return 1e-150 * a.S[0];
+  const double C = (double)(a.m > a.n ? a.m : a.n);
+  return EPS53 * C * fmax(a.S[0], 0.1 * sqrt(*a.fro2));
+}
+
 // U (m x k) and Vt (k x n), unscaled; null Bw-derived vectors are zeroed.
 // grid (chunks, 2, matrices): y = 0 writes U, y = 1 writes Vt
 template <typename T>
 __device__ inline void write_factors(const SvdMat &a, int which, int64_t e0, int64_t stride) {
-  const double thr = EPS53 * a.S[0] * (a.m > a.n ? a.m : a.n);
+  const double thr = null_threshold(a);
   if (which == 0) {
     T *U = static_cast<T *>(a.U);
     const int64_t total = (int64_t)a.m * a.k;
@@ -517,7 +802,7 @@ __device__ inline void write_factors(const SvdMat &a, int which, int64_t e0, int
       const int r = a.perm[j];
       double v;
       if (!a.trans) v = a.jt[(int64_t)r * a.R + i];
-      else v = (a.S[j] > thr && a.S[j] > 0.0) ? a.bw[(int64_t)r * a.C + i] / a.S[j] : 0.0;
+      else v = (a.S[j] > thr && a.S[j] > 0.0) ? a.bw[(int64_t)r * a.C + (a.pinv ? a.pinv[i] : i)] / a.S[j] : 0.0;
       U[e] = (T)v;
     }
   } else {
@@ -528,7 +813,7 @@ __device__ inline void write_factors(const SvdMat &a, int which, int64_t e0, int
       const int r = a.perm[j];
       double v;
       if (a.trans) v = a.jt[(int64_t)r * a.R + c];
-      else v = (a.S[j] > thr && a.S[j] > 0.0) ? a.bw[(int64_t)r * a.C + c] / a.S[j] : 0.0;
+      else v = (a.S[j] > thr && a.S[j] > 0.0) ? a.bw[(int64_t)r * a.C + (a.pinv ? a.pinv[c] : c)] / a.S[j] : 0.0;
       Vt[e] = (T)v;
     }
   }
@@ -546,7 +831,7 @@ __global__ __launch_bounds__(256) void write_kernel(const SvdMat *mats) {
 // (Vt rows when rows of A were orthogonalised, U columns otherwise); one block per matrix
 template <typename T>
 __device__ void complete_one(const SvdMat &a, double *vec, double *red, int *ok) {
-  const double thr = EPS53 * a.S[0] * (a.m > a.n ? a.m : a.n);
+  const double thr = null_threshold(a);
   const int L = a.trans ? a.m : a.n;
   T *base;
   int64_t es, vs;
@@ -593,7 +878,7 @@ __global__ __launch_bounds__(256) void complete_kernel(const SvdMat *mats) {
   const SvdMat &a = mats[blockIdx.x];
   if (a.k < 1) return;
   // only matrices with a kept null vector do any work
-  const double thr = EPS53 * a.S[0] * (a.m > a.n ? a.m : a.n);
+  const double thr = null_threshold(a);
   if (a.S[a.k - 1] > thr && a.S[a.k - 1] > 0.0) return;
   if (a.out_type == TNA_F64) complete_one<double>(a, vec, red, &ok);
   else complete_one<float>(a, vec, red, &ok);
@@ -650,6 +935,7 @@ __global__ __launch_bounds__(256) void gauge_kernel(const SvdMat *mats) {
 }
 
 int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+constexpr int QR_MIN_ROWS = QR_MIN_ROWS_DEV;
 
 }  // namespace
 
@@ -684,15 +970,24 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
   // 64-row block rotation and re-forming the Gram leave a rounding floor of about
   // (64 + C) ulps whatever C is, so the bound sits at twice that floor.
   a->tol = 2.0 * (64.0 + (double)a->C) * EPS53;
+  static const int inner_env = [] {
+    const char *e = std::getenv("TNA_SVD_INNER");
+    return e ? std::atoi(e) : 0;
+  }();
+  a->fused = (nb == 2 && a->C <= 1024) ? 1 : 0;
+  a->precond = (!a->fused && a->R >= QR_MIN_ROWS) ? 1 : 0;
+  // with the pivoted-QR start, two inner sweeps per block pair cost no extra outer sweeps
+  a->inner_max = inner_env > 0 ? inner_env : (a->fused ? 40 : 2);
   a->active = 1;
   return TNA_OK;
 }
 
 size_t svd_work_doubles(const SvdMat &a) {
   const size_t npairs = a.nb / 2;
-  return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R + 8;
+  return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R + 8 +
+         (a.precond ? (size_t)a.R + 8 + a.C : 0);
 }
-size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4; }
+size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4 + (a.precond ? 2 * (size_t)a.C : 0); }
 
 void svd_bind_work(SvdMat *a, double *dw, int *iw) {
   const size_t npairs = a->nb / 2;
@@ -707,11 +1002,24 @@ void svd_bind_work(SvdMat *a, double *dw, int *iw) {
   a->sig = dw;
   dw += a->R;
   a->fro2 = dw;
+  dw += 8;
   a->skip = iw;
   iw += npairs;
   a->perm = iw;
   iw += a->R;
   a->ctr = iw;
+  iw += 4;
+  if (a->precond) {
+    a->hv = dw;
+    dw += a->R + 8;
+    a->cn = dw;
+    a->cperm = iw;
+    iw += a->C;
+    a->pinv = iw;
+  } else {
+    a->hv = a->cn = nullptr;
+    a->cperm = a->pinv = nullptr;
+  }
 }
 
 static tna_status upload(const std::vector<SvdMat> &mats, SvdGroup &g, hipStream_t s) {
@@ -751,7 +1059,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
   hipLaunchKernelGGL(load_kernel, dim3(max_tiles_load, 1, nm), dim3(256), 0, s, d);
   hipLaunchKernelGGL(fro_kernel, dim3(nm), dim3(256), 0, s, d);
   TNA_LAUNCHED("svd.load");
-  if (!g.host_ctr) TNA_HIP(hipHostMalloc((void **)&g.host_ctr, sizeof(int) * 4096, hipHostMallocDefault));
+  if (!g.host_ctr) TNA_HIP(hipHostMalloc((void **)&g.host_ctr, sizeof(int) * 8192, hipHostMallocDefault));
   if (nm > 4096) {
     set_error("svd: at most 4096 matrices per group");
     return TNA_ERR_ARG;
@@ -764,7 +1072,45 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     apply_flops += 2.0 * b2 * (double)(a.C + a.R) * pairs;
     apply_bytes += 16.0 * ((double)a.R * a.C + (double)a.R * a.R);
   }
-  int active = nm;
+  // pivoted-QR start for the larger matrices
+  int qr_rows = 0, qr_cblk = 0, qr_ublk = 0;
+  for (auto &a : mats)
+    if (a.precond) {
+      qr_rows = std::max(qr_rows, a.R);
+      qr_cblk = std::max(qr_cblk, ceil_div(a.C, 256));
+      qr_ublk = std::max(qr_ublk, ceil_div(a.C, 32) + ceil_div(a.R, 32));
+    }
+  if (qr_rows > 0) {
+    hipLaunchKernelGGL(qr_init_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
+    double qr_bytes = 0.0;
+    for (auto &a : mats)
+      if (a.precond) qr_bytes += 16.0 * ((double)a.R * a.C / 3.0 + (double)a.R * a.R / 2.0);
+    timer_begin("svd.qr", s);
+    for (int k = 0; k < qr_rows; ++k) {
+      hipLaunchKernelGGL(qr_pivot_kernel, dim3(nm), dim3(256), 0, s, d, k);
+      hipLaunchKernelGGL(qr_update_kernel, dim3(qr_ublk, 1, nm), dim3(256), 0, s, d, k);
+    }
+    timer_end("svd.qr", 0.0, qr_bytes, s);
+    hipLaunchKernelGGL(qr_pinv_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
+    TNA_LAUNCHED("svd.qr");
+  }
+  // one block pair: every sweep inside one workgroup, no host round trip per sweep
+  int nfused = 0;
+  for (auto &a : mats) nfused += a.fused;
+  if (nfused > 0) {
+    timer_begin("svd.fused", s);
+    hipLaunchKernelGGL(jacobi_fused_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
+    timer_end("svd.fused", 0.0, 0.0, s);
+    TNA_LAUNCHED("svd.fused");
+  }
+  std::vector<int> live(nm);
+  int active = 0;
+  max_steps = 0;
+  for (int z = 0; z < nm; ++z) {
+    live[z] = !mats[z].fused;
+    active += live[z];
+    if (live[z]) max_steps = std::max(max_steps, mats[z].nb - 1);
+  }
   for (int sw = 1; sw <= max_sweeps && active > 0; ++sw) {
     hipLaunchKernelGGL(zero_ctr_kernel, dim3(ceil_div(nm, 64)), dim3(64), 0, s, d, nm);
     for (int step = 0; step < max_steps; ++step) {
@@ -780,8 +1126,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     }
     TNA_LAUNCHED("svd.sweep");
     for (int z = 0; z < nm; ++z)
-      if (mats[z].active)
-        TNA_HIP(hipMemcpyAsync(g.host_ctr + z, mats[z].ctr, sizeof(int), hipMemcpyDeviceToHost, s));
+      if (live[z]) TNA_HIP(hipMemcpyAsync(g.host_ctr + z, mats[z].ctr, sizeof(int), hipMemcpyDeviceToHost, s));
     TNA_HIP(hipStreamSynchronize(s));
     static const int dbg = [] {
       const char *e = std::getenv("TNA_DEBUG_SVD");
@@ -790,10 +1135,11 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     if (dbg) std::fprintf(stderr, "svd sweep %d: rotating pairs of matrix 0 = %d\n", sw, g.host_ctr[0]);
     bool changed = false;
     for (int z = 0; z < nm; ++z) {
-      if (!mats[z].active) continue;
+      if (!live[z]) continue;
       sweeps[z] = sw;
       if (g.host_ctr[z] == 0) {
         mats[z].active = 0;
+        live[z] = 0;
         --active;
         changed = true;
       }
@@ -801,9 +1147,20 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     if (changed && active > 0) {
       TNA_TRY(upload(mats, g, s));
       max_steps = 0;
-      for (auto &a : mats)
-        if (a.active) max_steps = std::max(max_steps, a.nb - 1);
+      for (int z = 0; z < nm; ++z)
+        if (live[z]) max_steps = std::max(max_steps, mats[z].nb - 1);
     }
+  }
+  if (nfused > 0) {
+    for (int z = 0; z < nm; ++z)
+      if (mats[z].fused)
+        TNA_HIP(hipMemcpyAsync(g.host_ctr + 2 * z, mats[z].ctr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    TNA_HIP(hipStreamSynchronize(s));
+    for (int z = 0; z < nm; ++z)
+      if (mats[z].fused) {
+        sweeps[z] = g.host_ctr[2 * z + 1];
+        if (g.host_ctr[2 * z] != 0) ++active;  // not converged within max_sweeps
+      }
   }
   for (auto &a : mats) a.active = 1;  // finishing kernels run on every matrix
   TNA_TRY(upload(mats, g, s));

@@ -18,8 +18,10 @@ def _svd(c, A, k):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (2, 8), (8, 2), (5, 7), (33, 33), (64, 100), (100, 64), (130, 70),
-                                 (97, 300), (256, 256)])
+                                 (97, 300), (256, 256), (300, 520), (600, 280)])
 def test_svd_matches_oracle(m, n):
+    """Shapes span the fused single-workgroup Jacobi (min(m, n) <= 64), the blocked path, and the
+    pivoted-QR start (min(m, n) >= 256), with the rows of A and of A^T."""
     A = synth.random_matrix(m, n, 100 + m + 7 * n)
     c = ctx()
     R = min(m, n)
@@ -75,13 +77,13 @@ def test_svd_rank_deficient_and_zero():
     assert np.abs(Vt @ Vt.T - np.eye(3)).max() <= 1e-14
 
 
-def test_svd_batched_equals_single():
-    import torch
+@pytest.mark.parametrize("m,n,k", [(70, 90, 20), (270, 300, 100)])
+def test_svd_batched_equals_single(m, n, k):
     c = ctx()
-    As = np.stack([synth.random_matrix(70, 90, 200 + i) for i in range(4)])
-    S, U, Vt, spec, sw, st = c.svd_truncate_batched(to_dev(As), 20)
+    As = np.stack([synth.random_matrix(m, n, 200 + i) for i in range(4)])
+    S, U, Vt, spec, sw, st = c.svd_truncate_batched(to_dev(As), k)
     for i in range(4):
-        S1, U1, Vt1, spec1, _, _, _ = _svd(c, As[i], 20)
+        S1, U1, Vt1, spec1, _, _, _ = _svd(c, As[i], k)
         assert np.abs(S[i].cpu().numpy() - S1).max() <= 1e-13 * S1[0]
         assert np.abs(U[i].cpu().numpy() - U1).max() <= 1e-10
 
