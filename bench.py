@@ -45,7 +45,20 @@ def parse():
     ap.add_argument("--svd-batch", type=int, default=1)
     ap.add_argument("--svd-dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--svd-tau", type=float, default=64.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with three 1 GiB device-to-device copies (a known-size reference for HBM counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """Three copies of 2^27 doubles (1 GiB read + 1 GiB written each) on the current stream."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each": 2 * a.numel() * 8, "copies": 3}), file=sys.stderr)
 
 
 def roofline_from(stats, dominant):
@@ -300,4 +313,7 @@ def main():
 
 
 if __name__ == "__main__":
+    args = parse()
     main()
+    if args.copy_probe:
+        copy_probe()

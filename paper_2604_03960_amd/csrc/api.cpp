@@ -107,6 +107,17 @@ void timer_end(const char *name, double flops, double bytes, hipStream_t s) {
   if (g_tm.pending.size() > 8192) drain_pending();
 }
 
+void timer_add_work(const char *name, double flops, double bytes) {
+  if (!timing_wanted(name)) return;
+  std::lock_guard<std::mutex> lk(g_tm.mu);
+  for (auto it = g_tm.pending.rbegin(); it != g_tm.pending.rend(); ++it)
+    if (it->name == name) {
+      it->flops += flops;
+      it->bytes += bytes;
+      return;
+    }
+}
+
 tna_status post_launch(const char *what) {
   static const int dbg = [] {
     const char *e = std::getenv("TNA_DEBUG_SYNC");

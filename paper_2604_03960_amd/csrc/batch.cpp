@@ -178,7 +178,7 @@ int parts_for(int64_t n) {
 }
 
 constexpr int LZ_SMALL_N = 4096;            // longest theta of the single-workgroup Lanczos path
-constexpr int NT_SMALL = 256;               // its workgroup size
+constexpr int NT_SMALL = 512;               // its workgroup size
 constexpr size_t LZ_SLOT = 128;             // per-chain h1/h2/y/nrm2 slots
 constexpr size_t LZ_PER = 3 * LZ_SLOT + 8;  // doubles per chain before the partials
 constexpr size_t LZ_PART = 128 * 512;       // partial-sum slots per chain and array
@@ -395,7 +395,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   std::vector<int> small(nc, 0), sm_ac(nc, 1);
   int nsmall = 0;
   size_t lds_small = 0;
-  if (d == 2 && (D == 3 || D == 5 || D == 8)) {
+  if (d == 2 && D * d * d <= 64) {
     for (int q = 0; q < nc; ++q) {
       const Visit &v = vs[q];
       if (v.nv > LZ_SMALL_N) continue;
@@ -549,7 +549,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       const Visit &v = vs[q];
       const int sl = slot[q];
       tna_dmrg dm = ch[q];
-      sp.push_back(LzSmall{v.chl, v.chr, v.kmax, sm_ac[q], dm->Le[v.b].as<double>(), dm->Re[v.b + 1].as<double>(),
+      sp.push_back(LzSmall{v.chl, v.chr, v.kmax, sm_ac[q], D, 0, dm->Le[v.b].as<double>(), dm->Re[v.b + 1].as<double>(),
                            dm->M12.as<double>() + (size_t)I2 * I2 * v.b, lp[q].V, j_dev + sl, act_dev + sl,
                            rec_small + (size_t)2 * LZ_HMAX * sl});
       sq.push_back(q);
@@ -557,7 +557,16 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     }
     const LzSmall *dsp = nullptr;
     TNA_TRY(arena_push(en->ar, sp.data(), sp.size(), s, &dsp));
-    std::vector<int> start(nc, 0);
+    std::vector<int> start(nc, 0), jdev(nc, 0);
+    // algorithmic work of one iteration at index t: H_eff products + CGS2 (two dot and two
+    // update passes over V_0..V_t) ; bytes: theta in, V_{t+1} out, the four passes over V
+    auto it_flops = [&](int q, int t) {
+      const Visit &v = vs[q];
+      const double cl = v.chl, cr = v.chr, dsq = (double)d * d;
+      return 2.0 * D * dsq * cl * cr * (cl + cr) + 2.0 * (D * dsq) * (D * dsq) * cl * cr +
+             8.0 * (t + 1) * (double)v.nv;
+    };
+    auto it_bytes = [&](int q, int t) { return 8.0 * (double)vs[q].nv * (2.0 + 4.0 * (t + 1)); };
     int chunk = 16;
     for (;;) {
       bool live = false;
@@ -571,6 +580,16 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       TNA_HIP(hipMemcpyAsync(en->h_rec, rec_small, sizeof(double) * 2 * LZ_HMAX * en->nslot, hipMemcpyDeviceToHost,
                              s));
       TNA_HIP(hipStreamSynchronize(s));
+      if (timing_wanted("lz.small")) {
+        double fl = 0.0, by = 0.0;
+        for (int q : sq)
+          for (int t = jdev[q]; t < en->h_j[slot[q]]; ++t) {
+            fl += it_flops(q, t);
+            by += it_bytes(q, t);
+          }
+        timer_add_work("lz.small", fl, by);
+      }
+      for (int q : sq) jdev[q] = en->h_j[slot[q]];
       for (int q : sq) {
         if (!act[q]) continue;
         start[q] = (int)al[q].size();
@@ -589,6 +608,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
         }
       }
       TNA_TRY(restart_stopped(small));
+      for (int q : sq)
+        if (act[q] && al[q].empty()) jdev[q] = 0;  // restarted: j reset on the device
       chunk = 8;
     }
   }

@@ -208,101 +208,160 @@ __global__ __launch_bounds__(NT) void lz_combine_kernel(const LzProb *probs) {
 
 // ------------------------------------------------------------------ single-workgroup Lanczos
 // Whole Lanczos iterations of one short theta inside one workgroup (grid x =
-// chain).  H_eff (Eq. 1's contraction in the order L, W_i W_{i+1}, R) reads
-// L, R^T and the two-site mixing matrix from LDS: the left and mixing stages
-// are fused per (a, c') with the DD = D d^2 channels in registers, the right
-// stage sums over (w'', c').  CGS2 against the basis in global memory follows;
-// alpha_j, beta_j^2 of every iteration go to rec[2j], rec[2j+1].  A workgroup
-// stops at kmax, after `iters` iterations, or when beta_j is negligible.
-template <int D, int DD>
-__global__ __launch_bounds__(NT) void lz_small_kernel(const LzSmall *probs, int iters) {
+// chain).  H_eff (Eq. 1's contraction in the order L, W_i W_{i+1}, R) runs as
+// three small FP64 MFMA products on LDS-resident operands, a chunk of `ac`
+// left indices at a time:
+//   X[(a,w)][(s',t',c')] = sum_a' L[(a,w)][a'] theta[a'][(s',t',c')]
+//   Z[o=(s,t,w'')][(a,c')] = sum_i M[o][i=(w,s',t')] X[a][i][c']
+//   out[(a,s,t)][c] = sum_{(w'',c')} Z[a][(s,t,w'')][c'] R[c][(w'',c')]
+// CGS2 against the basis in global memory follows (dot products eight at a
+// time); alpha_j, beta_j^2 of every iteration go to rec[2j], rec[2j+1].  A
+// workgroup stops at kmax, after `iters` iterations, or when beta_j is
+// negligible.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int NTS = 512;  // threads of the single-workgroup Lanczos (8 waves)
+
+// C(i, j) = sum_k A(i, k) B(k, j) on v_mfma_f64_16x16x4_f64, the waves of the block taking
+// 16 x 16 tiles in turn; the operands of step k + 4 are read before the MFMA of step k.
+// Operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; result D[i][j] in
+// lane j + 16 (i % 4), register i / 4.
+template <class FA, class FB, class FC>
+__device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_put) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = NTS / 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tn = (N + 15) >> 4, tiles = ((M + 15) >> 4) * tn;
+  for (int t = wave; t < tiles; t += nw) {
+    const int i0 = (t / tn) << 4, j0 = (t - (t / tn) * tn) << 4;
+    const int ia = i0 + lr, jb = j0 + lr;
+    const bool ra = ia < M, rb = jb < N;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    int k = lk;
+    double av = (ra && k < K) ? a_at(ia, k) : 0.0;
+    double bv = (rb && k < K) ? b_at(k, jb) : 0.0;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int kn = k + 4;
+      const double an = (ra && kn < K) ? a_at(ia, kn) : 0.0;
+      const double bn = (rb && kn < K) ? b_at(kn, jb) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      av = an;
+      bv = bn;
+      k = kn;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * r + lk;
+      if (i < M && rb) c_put(i, jb, acc[r]);
+    }
+  }
+}
+
+__device__ inline double block_sum_s(double v, double *sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NTS / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int iters) {
   extern __shared__ double lds[];
   const LzSmall &p = probs[blockIdx.x];
   if (!*p.active) return;
-  constexpr int dd = DD / D;
+  constexpr int dd = 4;  // d^2, d = 2
+  constexpr int NW = NTS / 64;
+  const int D = p.D, DD = D * dd;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int chl = p.chl, chr = p.chr, ac = p.ac;
-  const int n = chl * dd * chr;
+  const int n = chl * dd * chr, nr = dd * chr;
   double *th = lds;                                  // n: V_j
   double *wv = th + n;                               // n: H V_j, then orthogonalised
   double *Ls = wv + n;                               // L[a][w][a']
-  double *RT = Ls + (size_t)chl * D * chl;           // RT[(w'' chr + c') chr + c] = R[c][w''][c']
-  double *Ms = RT + (size_t)chr * D * chr;           // M[(s t w'')][(w s' t')]
-  double *Zc = Ms + DD * DD;                         // Zc[al][(s t w'')][c'] for a chunk of ac rows
+  double *Rs = Ls + (size_t)chl * D * chl;           // R[c][w''][c']
+  double *Ms = Rs + (size_t)chr * D * chr;           // M[o][i]
+  double *Xc = Ms + DD * DD;                         // X[al][i][c'] of a chunk
+  double *Zc = Xc + (size_t)ac * DD * chr;           // Z[al][o][c'] of a chunk
   double *hb = Zc + (size_t)ac * DD * chr;           // h of the two CGS passes
-  double *red = hb + 2 * LZ_HMAX;
-  for (int e = tid; e < chl * D * chl; e += NT) Ls[e] = p.L[e];
-  for (int e = tid; e < chr * D * chr; e += NT) {
-    const int c = e / (D * chr), r = e - c * (D * chr);
-    RT[(size_t)r * chr + c] = p.R[e];
-  }
-  for (int e = tid; e < DD * DD; e += NT) Ms[e] = p.M[e];
+  double *red = hb + 2 * LZ_HMAX;                    // 16 partials per wave
+  for (int e = tid; e < chl * D * chl; e += NTS) Ls[e] = p.L[e];
+  for (int e = tid; e < chr * D * chr; e += NTS) Rs[e] = p.R[e];
+  for (int e = tid; e < DD * DD; e += NTS) Ms[e] = p.M[e];
   int j = *p.j;
   for (int it = 0; it < iters && j < p.kmax; ++it) {
     const double *vj = p.V + (int64_t)j * n;
     double *vn = p.V + (int64_t)(j + 1) * n;
     __syncthreads();  // previous iteration done with th, wv and hb
-    for (int e = tid; e < n; e += NT) th[e] = vj[e];
+    for (int e = tid; e < n; e += NTS) th[e] = vj[e];
     __syncthreads();
     for (int a0 = 0; a0 < chl; a0 += ac) {
       const int na = chl - a0 < ac ? chl - a0 : ac;
-      for (int e = tid; e < na * chr; e += NT) {
-        const int al = e / chr, cp = e - al * chr;
-        const double *La = Ls + (size_t)(a0 + al) * D * chl;
-        double x[DD];
-#pragma unroll
-        for (int i = 0; i < DD; ++i) x[i] = 0.0;
-        for (int ap = 0; ap < chl; ++ap) {
-          double tv[dd];
-#pragma unroll
-          for (int st = 0; st < dd; ++st) tv[st] = th[(ap * dd + st) * chr + cp];
-#pragma unroll
-          for (int w = 0; w < D; ++w) {
-            const double l = La[w * chl + ap];
-#pragma unroll
-            for (int st = 0; st < dd; ++st) x[w * dd + st] += l * tv[st];
-          }
-        }
-        double *z = Zc + (size_t)al * DD * chr + cp;
-#pragma unroll
-        for (int o = 0; o < DD; ++o) {
-          double acc = 0.0;
-#pragma unroll
-          for (int i = 0; i < DD; ++i) acc += Ms[o * DD + i] * x[i];
-          z[(size_t)o * chr] = acc;
-        }
-      }
+      block_gemm(na * D, nr, chl, [&](int i, int k) { return Ls[(a0 * D + i) * chl + k]; },
+                 [&](int k, int c) { return th[k * nr + c]; },
+                 [&](int i, int c, double v) { Xc[i * nr + c] = v; });
       __syncthreads();
-      for (int e = tid; e < na * dd * chr; e += NT) {
-        const int al = e / (dd * chr), r = e - al * (dd * chr), st = r / chr, c = r - st * chr;
-        const double *z = Zc + ((size_t)al * DD + st * D) * chr;
-        double acc = 0.0;
-        for (int q = 0; q < D * chr; ++q) acc += z[q] * RT[(size_t)q * chr + c];
-        wv[((a0 + al) * dd + st) * chr + c] = acc;
-      }
+      block_gemm(DD, na * chr, DD, [&](int o, int i) { return Ms[o * DD + i]; },
+                 [&](int i, int c) {
+                   const int al = c / chr;
+                   return Xc[(al * DD + i) * chr + (c - al * chr)];
+                 },
+                 [&](int o, int c, double v) {
+                   const int al = c / chr;
+                   Zc[(al * DD + o) * chr + (c - al * chr)] = v;
+                 });
+      __syncthreads();
+      block_gemm(na * dd, chr, D * chr,
+                 [&](int i, int q) { return Zc[((i >> 2) * DD + (i & 3) * D) * chr + q]; },
+                 [&](int q, int c) { return Rs[c * (D * chr) + q]; },
+                 [&](int i, int c, double v) { wv[(a0 * dd + i) * chr + c] = v; });
       __syncthreads();
     }
-    // CGS2 against V_0..V_j
+    // CGS2 against V_0..V_j: dot products sixteen at a time, updates with batched loads
     double b2 = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       double *h = hb + pass * LZ_HMAX;
-      for (int i = wave; i <= j; i += NT / 64) {
-        const double *vi = p.V + (int64_t)i * n;
-        double acc = 0.0;
-        for (int e = lane; e < n; e += 64) acc += vi[e] * wv[e];
-        acc = wave_sum(acc);
-        if (lane == 0) h[i] = acc;
+      for (int i0 = 0; i0 <= j; i0 += 16) {
+        double acc[16];
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc[g] = 0.0;
+        for (int e = tid; e < n; e += NTS) {
+          const double w = wv[e];
+#pragma unroll
+          for (int g = 0; g < 16; ++g)
+            if (i0 + g <= j) acc[g] += p.V[(int64_t)(i0 + g) * n + e] * w;
+        }
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc[g] = wave_sum(acc[g]);
+        if (lane == 0)
+#pragma unroll
+          for (int g = 0; g < 16; ++g) red[wave * 16 + g] = acc[g];
+        __syncthreads();
+        if (tid < 16 && i0 + tid <= j) {
+          double sum = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) sum += red[w * 16 + tid];
+          h[i0 + tid] = sum;
+        }
+        __syncthreads();
       }
-      __syncthreads();
       double loc = 0.0;
-      for (int e = tid; e < n; e += NT) {
+      for (int e = tid; e < n; e += NTS) {
         double acc = 0.0;
-        for (int i = 0; i <= j; ++i) acc += h[i] * p.V[(int64_t)i * n + e];
+        int i = 0;
+        for (; i + 8 <= j + 1; i += 8) {
+          double v[8];
+#pragma unroll
+          for (int g = 0; g < 8; ++g) v[g] = p.V[(int64_t)(i + g) * n + e];
+#pragma unroll
+          for (int g = 0; g < 8; ++g) acc += h[i + g] * v[g];
+        }
+        for (; i <= j; ++i) acc += h[i] * p.V[(int64_t)i * n + e];
         const double v = wv[e] - acc;
         wv[e] = v;
         loc += v * v;
       }
-      if (pass == 1) b2 = block_sum(loc, red);
+      if (pass == 1) b2 = block_sum_s(loc, red);
       else __syncthreads();
     }
     if (tid == 0) {
@@ -313,7 +372,7 @@ __global__ __launch_bounds__(NT) void lz_small_kernel(const LzSmall *probs, int 
     const double beta = sqrt(b2);
     const bool stop = !(beta >= 1e-14);
     const double f = stop ? 1.0 : 1.0 / beta;
-    for (int e = tid; e < n; e += NT) vn[e] = wv[e] * f;
+    for (int e = tid; e < n; e += NTS) vn[e] = wv[e] * f;
     ++j;
     if (stop) break;
   }
@@ -384,8 +443,8 @@ tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s) {
 
 size_t lz_small_lds(int chl, int chr, int d, int D, int ac) {
   const size_t n = (size_t)chl * d * d * chr, DD = (size_t)D * d * d;
-  return sizeof(double) * (2 * n + (size_t)chl * D * chl + (size_t)chr * D * chr + DD * DD + (size_t)ac * DD * chr +
-                           2 * LZ_HMAX + 8);
+  return sizeof(double) * (2 * n + (size_t)chl * D * chl + (size_t)chr * D * chr + DD * DD +
+                           2 * (size_t)ac * DD * chr + 2 * LZ_HMAX + 16 * (NTS / 64));
 }
 
 tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, hipStream_t s) {
@@ -394,28 +453,22 @@ tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t
     set_error("lz_small: physical dimension 2 only");
     return TNA_ERR_UNSUPPORTED;
   }
-  void (*k)(const LzSmall *, int) = nullptr;
-  switch (D) {
-    case 3: k = lz_small_kernel<3, 12>; break;
-    case 5: k = lz_small_kernel<5, 20>; break;
-    case 8: k = lz_small_kernel<8, 32>; break;
-    default:
-      set_error("lz_small: MPO bond dimension must be 3, 5 or 8");
-      return TNA_ERR_UNSUPPORTED;
+  if (D * dsq > 64) {
+    set_error("lz_small: MPO bond dimension above 16");
+    return TNA_ERR_UNSUPPORTED;
   }
-  static bool attr_set[3] = {false, false, false};
-  const int slot = D == 3 ? 0 : (D == 5 ? 1 : 2);
-  if (!attr_set[slot]) {
-    TNA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)LZ_SMALL_LDS_MAX));
-    attr_set[slot] = true;
+  static bool attr_set = false;
+  if (!attr_set) {
+    TNA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(lz_small_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)LZ_SMALL_LDS_MAX));
+    attr_set = true;
   }
   if (lds > LZ_SMALL_LDS_MAX) {
     set_error("lz_small: LDS need above the limit");
     return TNA_ERR_ARG;
   }
   timer_begin("lz.small", s);
-  hipLaunchKernelGGL(k, dim3(nch), dim3(NT), lds, s, d, iters);
+  hipLaunchKernelGGL(lz_small_kernel, dim3(nch), dim3(NTS), lds, s, d, iters);
   timer_end("lz.small", 0.0, 0.0, s);
   TNA_LAUNCHED("lanczos.small");
   return TNA_OK;

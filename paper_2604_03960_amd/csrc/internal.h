@@ -48,6 +48,8 @@ bool timing_may_match(const char *name_prefix);
 bool timing_wanted(const char *name);
 void timer_begin(const char *name, hipStream_t s);
 void timer_end(const char *name, double flops, double bytes, hipStream_t s);
+// adds work known only after the launch (e.g. iterations run) to the last record of `name`
+void timer_add_work(const char *name, double flops, double bytes);
 
 // ------------------------------------------------------------------ device buffer
 // Grow-only device allocation; contents are not preserved across growth.
@@ -216,7 +218,8 @@ tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s);
 constexpr int LZ_HMAX = 128;                       // >= kmax + 1
 constexpr size_t LZ_SMALL_LDS_MAX = 160 * 1024;    // LDS of one gfx950 workgroup
 struct LzSmall {
-  int chl, chr, kmax, ac;  // ac: left indices per pass of the fused left/mixing stage
+  int chl, chr, kmax, ac;  // ac: left indices per chunk of the three H_eff products
+  int D, pad_;
   const double *L, *R, *M; // L[a][w][a'], R[c][w''][c'], mixing matrix (D d^2)^2
   double *V;               // Krylov basis, V_0 set
   int *j;

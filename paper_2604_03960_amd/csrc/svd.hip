@@ -72,6 +72,11 @@ __device__ inline int block_rows(int R, int blk) {
   return r < 0 ? 0 : (r > BS ? BS : r);
 }
 
+__device__ inline double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ inline double bsum256(double v, double *red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -164,6 +169,7 @@ struct EigLds {
   int pi[32], pj[32];
   int rot_any, need;
   int slot_of[64];
+  int vs[64];  // valid slots in order
 };
 
 // Rows whose squared norm is at or below row_floor2 = (0.1 eps C)^2 |A|_F^2 are at the
@@ -197,42 +203,60 @@ __device__ inline bool eig_needs_rotation(EigLds &L, double tol, double floor2) 
   return L.need != 0;
 }
 
-// Q <- Q J over sweeps of the round-robin ordering until a sweep rotates nothing
-// (or inner_max sweeps); the diagonal of G ends as the eigenvalues.
-__device__ inline void eig_inner(EigLds &L, int inner_max, double floor2) {
+// Q <- Q J over sweeps of a round-robin ordering of the nv valid slots (np of block p at
+// 0.., nq of block q at 32..) until a sweep rotates nothing (or inner_max sweeps); the
+// diagonal of G ends as the eigenvalues.  With nv odd a dummy index sits out each round.
+__device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np, int nq) {
   const int tid = threadIdx.x;
+  const int nv = np + nq, nvp = nv + (nv & 1), P = nvp / 2;
+  if (tid < 64) L.vs[tid] = tid < np ? tid : 32 + (tid - np);  // entries >= nv unused
   const double tol_in = 4.0 * EPS53;
   for (int sweep = 0; sweep < inner_max; ++sweep) {
-    __syncthreads();  // every thread has read rot_any of the previous sweep
+    __syncthreads();  // every thread has read rot_any of the previous sweep (and vs is set)
     if (tid == 0) L.rot_any = 0;
     __syncthreads();
-    for (int rr = 0; rr < 63; ++rr) {
-      // 32 disjoint pairs; rotation J = [[c, s], [-s, c]] on (i, j), i < j
-      if (tid < 32) {
-        int i, j;
-        if (tid == 0) { i = rr % 63; j = 63; }
-        else { i = (rr + tid) % 63; j = (rr - tid + 63) % 63; }
+    for (int rr = 0; rr < nvp - 1; ++rr) {
+      // P disjoint pairs; rotation J = [[c, s], [-s, c]] on (i, j), i < j; a pair with
+      // the dummy becomes (x, x) with the identity, so its rows still take the partner's
+      // column rotations below
+      if (tid < P) {
+        int ia, ib;
+        if (tid == 0) { ia = rr % (nvp - 1); ib = nvp - 1; }
+        else { ia = (rr + tid) % (nvp - 1); ib = (rr - tid + nvp - 1) % (nvp - 1); }
+        int i = ia < nv ? L.vs[ia] : -1, j = ib < nv ? L.vs[ib] : -1;
+        if (i < 0) i = j;
+        if (j < 0) j = i;
         if (i > j) { const int t = i; i = j; j = t; }
-        const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
         double c = 1.0, s = 0.0;
-        if (gii > floor2 && gjj > floor2 && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
-          const double zeta = (gjj - gii) / (2.0 * gij);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = c * t;
-          L.rot_any = 1;
+        if (i != j) {
+          const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
+          if (gii > floor2 && gjj > floor2 && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
+            const double zeta = (gjj - gii) / (2.0 * gij);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = c * t;
+            L.rot_any = 1;
+          }
         }
         L.cs[tid] = c; L.sn[tid] = s; L.pi[tid] = i; L.pj[tid] = j;
       }
       __syncthreads();
       // G <- J^T G J one 2 x 2 block (pair t rows, pair u columns) at a time, t <= u, and
-      // the mirror block written from the same values so G stays exactly symmetric.  Rows
-      // t and 31 - t of the block triangle are dealt together: 33 blocks per row pair.
-      for (int e = tid; e < 528; e += 256) {
-        const int rp = e / 33, off = e - 33 * rp;
+      // the mirror block written from the same values so G stays exactly symmetric.  For
+      // even P, rows t and P - 1 - t of the block triangle go together (P + 1 blocks per
+      // row pair); for odd P the square is walked and its lower half skipped.
+      const int nblk = (P & 1) ? P * P : (P / 2) * (P + 1);
+      for (int e = tid; e < nblk; e += 256) {
         int t, u;
-        if (off < 32 - rp) { t = rp; u = rp + off; }
-        else { t = 31 - rp; u = t + (off - (32 - rp)); }
+        if (P & 1) {
+          t = e / P;
+          u = e - t * P;
+          if (u < t) continue;
+        } else {
+          const int rp = e / (P + 1), off = e - rp * (P + 1);
+          if (off < P - rp) { t = rp; u = rp + off; }
+          else { t = P - 1 - rp; u = t + (off - (P - rp)); }
+        }
         const double st = L.sn[t], su = L.sn[u];
         if (st == 0.0 && su == 0.0) continue;
         const double ct = L.cs[t], cu = L.cs[u];
@@ -245,13 +269,14 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2) {
         if (t == u) {
           L.G[a0][a0] = z00; L.G[a1][a1] = z11; L.G[a0][a1] = 0.0; L.G[a1][a0] = 0.0;
         } else {
+          // a dummy pair has a0 == a1 (identity rotation): both writes carry the same value
           L.G[a0][b0] = z00; L.G[a0][b1] = z01; L.G[a1][b0] = z10; L.G[a1][b1] = z11;
           L.G[b0][a0] = z00; L.G[b1][a0] = z01; L.G[b0][a1] = z10; L.G[b1][a1] = z11;
         }
       }
-      // Q <- Q J (pair index uniform across a wave)
-      for (int e = tid; e < 32 * 64; e += 256) {
-        const int u = e >> 6, k = e & 63;
+      // Q <- Q J over the valid rows
+      for (int e = tid; e < P * nv; e += 256) {
+        const int u = e / nv, k = L.vs[e - u * nv];
         const double su = L.sn[u];
         if (su != 0.0) {
           const double cu = L.cs[u];
@@ -320,7 +345,7 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
     return;
   }
   if (tid == 0) atomicAdd(a.ctr, 1);
-  eig_inner(L, a.inner_max, floor2);
+  eig_inner(L, a.inner_max, floor2, np, nq);
   eig_order(L, np, nq);
   double *Qt = a.qt + (int64_t)pair * 4096;
   for (int e = tid; e < 4096; e += 256) {
@@ -421,7 +446,7 @@ __global__ __launch_bounds__(256) void jacobi_fused_kernel(const SvdMat *mats, i
       conv = 1;
       break;
     }
-    eig_inner(L, a.inner_max, floor2);
+    eig_inner(L, a.inner_max, floor2, np, nq);
     eig_order(L, np, nq);
     // As[k][i] = Qt[i][k] = Q[k][slot_of[i]], written over G
     for (int e = tid; e < 4096; e += 256) {
@@ -482,13 +507,24 @@ __global__ __launch_bounds__(256) void load_kernel(const SvdMat *mats) {
   }
 }
 
-// |A|_F^2 of the loaded rows; one block per matrix, fixed order
+// |A|_F^2 of the loaded rows in two fixed-order stages: block partials into the Gram
+// area (free until the first sweep), then one block per matrix sums them
+constexpr int FRO_BLOCKS = 256;
+__global__ __launch_bounds__(256) void fro_partial_kernel(const SvdMat *mats) {
+  __shared__ double red[4];
+  const SvdMat &a = mats[blockIdx.z];
+  const int64_t tot = (int64_t)a.R * a.C;
+  const int64_t chunk = (tot + FRO_BLOCKS - 1) / FRO_BLOCKS;
+  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < tot ? beg + chunk : tot;
+  double v = 0.0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += 256) v += a.bw[e] * a.bw[e];
+  v = bsum256(v, red);
+  if (threadIdx.x == 0) a.gram[blockIdx.x] = v;
+}
 __global__ __launch_bounds__(256) void fro_kernel(const SvdMat *mats) {
   __shared__ double red[4];
   const SvdMat &a = mats[blockIdx.x];
-  const int64_t tot = (int64_t)a.R * a.C;
-  double v = 0.0;
-  for (int64_t e = threadIdx.x; e < tot; e += 256) v += a.bw[e] * a.bw[e];
+  double v = threadIdx.x < FRO_BLOCKS ? a.gram[threadIdx.x] : 0.0;
   v = bsum256(v, red);
   if (threadIdx.x == 0) *a.fro2 = v;
 }
@@ -523,17 +559,20 @@ __global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
   a.cperm[j] = j;
 }
 
-// grid (matrices): pivot, column swap, reflector v = x - alpha e_0 of x = B[k:R, k]
-__global__ __launch_bounds__(256) void qr_pivot_kernel(const SvdMat *mats, int k) {
-  __shared__ double bv[4], red[4];
-  __shared__ int bi[4], piv;
+// grid (matrices), 1024 threads: pivot, column swap, reflector v = x - alpha e_0 of
+// x = B[k:R, k]; each thread keeps its (at most QR_ROWS_PER_THREAD) rows of the new
+// column k in registers, so column k and the pivot column are read once
+constexpr int QR_PIV_NT = 1024, QR_ROWS_PER_THREAD = 4;  // R <= 4096
+__global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats, int k) {
+  __shared__ double bv[16], red[16];
+  __shared__ int bi[16], piv;
   __shared__ double xs0, nrm;
   const SvdMat &a = mats[blockIdx.x];
   if (!a.active || !a.precond || k >= a.R) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double best = -1.0;
   int bidx = 0x7fffffff;
-  for (int j = k + tid; j < a.C; j += 256) {
+  for (int j = k + tid; j < a.C; j += QR_PIV_NT) {
     const double v = a.cn[j];
     if (v > best) { best = v; bidx = j; }  // increasing j per thread: ties keep the lowest
   }
@@ -542,54 +581,64 @@ __global__ __launch_bounds__(256) void qr_pivot_kernel(const SvdMat *mats, int k
     const int oi = __shfl_xor(bidx, off, 64);
     if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
   }
-  if ((tid & 63) == 0) { bv[tid >> 6] = best; bi[tid >> 6] = bidx; }
+  if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
   __syncthreads();
   if (tid == 0) {
     double b = bv[0];
     int ii = bi[0];
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < QR_PIV_NT / 64; ++w)
       if (bv[w] > b || (bv[w] == b && bi[w] < ii)) { b = bv[w]; ii = bi[w]; }
     piv = (ii >= k && ii < a.C) ? ii : k;
   }
   __syncthreads();
   const int p = piv;
-  if (p != k) {
-    for (int i = tid; i < a.R; i += 256) {
-      const int64_t r = (int64_t)i * a.C;
-      const double t = a.bw[r + k];
-      a.bw[r + k] = a.bw[r + p];
-      a.bw[r + p] = t;
-    }
-    if (tid == 0) {
-      const double tc = a.cn[k];
-      a.cn[k] = a.cn[p];
-      a.cn[p] = tc;
-      const int tp = a.cperm[k];
-      a.cperm[k] = a.cperm[p];
-      a.cperm[p] = tp;
-    }
-  }
-  __syncthreads();
+  double col[QR_ROWS_PER_THREAD];
   double s = 0.0;
-  for (int i = k + tid; i < a.R; i += 256) {
-    const double v = a.bw[(int64_t)i * a.C + k];
-    s += v * v;
+#pragma unroll
+  for (int u = 0; u < QR_ROWS_PER_THREAD; ++u) {
+    const int i = tid + u * QR_PIV_NT;
+    col[u] = 0.0;
+    if (i < a.R) {
+      const int64_t r = (int64_t)i * a.C;
+      const double xk = a.bw[r + k], xp = a.bw[r + p];
+      if (p != k) a.bw[r + p] = xk;
+      col[u] = xp;  // new column k
+      if (i >= k) s += xp * xp;
+    }
   }
-  s = bsum256(s, red);
+  if (tid == 0 && p != k) {
+    const double tc = a.cn[k];
+    a.cn[k] = a.cn[p];
+    a.cn[p] = tc;
+    const int tp = a.cperm[k];
+    a.cperm[k] = a.cperm[p];
+    a.cperm[p] = tp;
+  }
+  s = wave_sum_d(s);
+  if (lane == 0) red[wave] = s;
+  if (tid == (k % QR_PIV_NT)) xs0 = col[k / QR_PIV_NT];
+  __syncthreads();
   if (tid == 0) {
-    xs0 = a.bw[(int64_t)k * a.C + k];
-    nrm = sqrt(s);
+    double t = 0.0;
+    for (int w = 0; w < QR_PIV_NT / 64; ++w) t += red[w];
+    nrm = sqrt(t);
   }
   __syncthreads();
   const double x0 = xs0, nx = nrm;
   // alpha = -sign(x0) |x|, v_0 = x0 - alpha, beta = 2 / v^T v = 1 / (|x| (|x| + |x0|))
   const double alpha = x0 >= 0.0 ? -nx : nx;
   const double beta = nx > 0.0 ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
-  for (int i = k + tid; i < a.R; i += 256) {
+#pragma unroll
+  for (int u = 0; u < QR_ROWS_PER_THREAD; ++u) {
+    const int i = tid + u * QR_PIV_NT;
+    if (i >= a.R) continue;
     const int64_t r = (int64_t)i * a.C + k;
-    const double v = (i == k) ? x0 - alpha : a.bw[r];
-    a.hv[i] = v;
-    a.bw[r] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
+    if (i < k) {
+      a.bw[r] = col[u];
+    } else {
+      a.hv[i] = (i == k) ? x0 - alpha : col[u];
+      a.bw[r] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
+    }
   }
   if (tid == 0) a.hv[a.R] = beta;
 }
@@ -976,8 +1025,9 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
   }();
   a->fused = (nb == 2 && a->C <= 1024) ? 1 : 0;
   a->precond = (!a->fused && a->R >= QR_MIN_ROWS) ? 1 : 0;
-  // with the pivoted-QR start, two inner sweeps per block pair cost no extra outer sweeps
-  a->inner_max = inner_env > 0 ? inner_env : (a->fused ? 40 : 2);
+  // Two inner sweeps per block pair (one in the single-workgroup form, whose outer sweep
+  // is cheap) cost few extra outer sweeps and far less than diagonalising each pair
+  a->inner_max = inner_env > 0 ? inner_env : (a->fused ? 1 : 2);
   a->active = 1;
   return TNA_OK;
 }
@@ -1057,6 +1107,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
   TNA_TRY(upload(mats, g, s));
   const SvdMat *d = g.desc.as<SvdMat>();
   hipLaunchKernelGGL(load_kernel, dim3(max_tiles_load, 1, nm), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(fro_partial_kernel, dim3(FRO_BLOCKS, 1, nm), dim3(256), 0, s, d);
   hipLaunchKernelGGL(fro_kernel, dim3(nm), dim3(256), 0, s, d);
   TNA_LAUNCHED("svd.load");
   if (!g.host_ctr) TNA_HIP(hipHostMalloc((void **)&g.host_ctr, sizeof(int) * 8192, hipHostMallocDefault));
@@ -1087,7 +1138,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       if (a.precond) qr_bytes += 16.0 * ((double)a.R * a.C / 3.0 + (double)a.R * a.R / 2.0);
     timer_begin("svd.qr", s);
     for (int k = 0; k < qr_rows; ++k) {
-      hipLaunchKernelGGL(qr_pivot_kernel, dim3(nm), dim3(256), 0, s, d, k);
+      hipLaunchKernelGGL(qr_pivot_kernel, dim3(nm), dim3(QR_PIV_NT), 0, s, d, k);
       hipLaunchKernelGGL(qr_update_kernel, dim3(qr_ublk, 1, nm), dim3(256), 0, s, d, k);
     }
     timer_end("svd.qr", 0.0, qr_bytes, s);
@@ -1156,11 +1207,18 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       if (mats[z].fused)
         TNA_HIP(hipMemcpyAsync(g.host_ctr + 2 * z, mats[z].ctr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     TNA_HIP(hipStreamSynchronize(s));
+    double fl = 0.0, by = 0.0;
     for (int z = 0; z < nm; ++z)
       if (mats[z].fused) {
         sweeps[z] = g.host_ctr[2 * z + 1];
         if (g.host_ctr[2 * z] != 0) ++active;  // not converged within max_sweeps
+        // per sweep: Gram 2 R^2 C, rotation of B and Jt 2 R^2 (C + R); B read for the Gram,
+        // B and Jt read and written by the rotation
+        const double R = mats[z].R, C = mats[z].C, sw = sweeps[z];
+        fl += sw * (2.0 * R * R * C + 2.0 * R * R * (C + R));
+        by += sw * 8.0 * (R * C + 2.0 * (R * C + R * R));
       }
+    timer_add_work("svd.fused", fl, by);
   }
   for (auto &a : mats) a.active = 1;  // finishing kernels run on every matrix
   TNA_TRY(upload(mats, g, s));
