@@ -61,6 +61,33 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each": 2 * a.numel() * 8, "copies": 3}), file=sys.stderr)
 
 
+# HBM traffic per launch measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE, each scaled by
+# what the counter reads for a 1 GiB device copy); valid only while the kernel's source file
+# is unchanged since the counters were taken (sha256 recorded next to the figure)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCE = {"lz.small": "paper_2604_03960_amd/csrc/batch.hip", "svd.fused": "paper_2604_03960_amd/csrc/svd.hip",
+                 "svd.apply": "paper_2604_03960_amd/csrc/svd.hip", "svd.eigen": "paper_2604_03960_amd/csrc/svd.hip"}
+
+
+def traffic_for(kernel):
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            table = json.load(f)
+        ent = table[kernel]
+        with open(os.path.join(ROOT, KERNEL_SOURCE[kernel]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != ent["source_sha256"]:
+                return None
+        return ent["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def progress(msg):
+    if os.environ.get("TNA_BENCH_PROGRESS"):
+        print(msg, file=sys.stderr, flush=True)
+
+
 def roofline_from(stats, dominant):
     for r in stats:
         if r["name"] == dominant and r["count"] > 0:
@@ -75,7 +102,7 @@ def roofline_from(stats, dominant):
                 roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                         "frac": ach / PEAK["hbm_gbs"]}
             roof.update({"kernel": dominant, "launches": r["count"], "avg_us": 1e3 * avg_ms,
-                         "flops_per_launch": fl, "bytes_per_launch": by, "traffic": None})
+                         "flops_per_launch": fl, "bytes_per_launch": by, "traffic": traffic_for(dominant)})
             return roof
     return None
 
@@ -251,10 +278,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Es, logs = [], []
-    for _ in range(a.steps):
+    for i in range(a.steps):
         E, recs, st = dm.sweep()
         Es.append(E)
         logs += recs
+        progress(f"sweep {i + 1}/{a.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = ctx.kernel_stats(reset=True)

@@ -168,6 +168,7 @@ struct SvdMat {
   int precond, pad2_;                          // 1: rows start from the R factor of a pivoted QR
   double *hv, *cn;                             // work: Householder vector (R + 1, beta last), column norms (C)
   int *cperm, *pinv;                           // work: original column at position c, and its inverse (C each)
+  double *qv, *qws;                            // work: reflectors as rows (R x R), blocked-product scratch
 };
 struct SvdGroup {
   DevBuf desc, work_d, work_i;

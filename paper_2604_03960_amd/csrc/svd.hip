@@ -186,12 +186,13 @@ __device__ inline double row_floor2(const SvdMat &a, double fro2) {
 }
 
 // Outer test: does any pair of rows above the floor fail |g_ij| <= tol sqrt(g_ii g_jj)?
+template <int NTE>
 __device__ inline bool eig_needs_rotation(EigLds &L, double tol, double floor2) {
   const int tid = threadIdx.x;
   if (tid == 0) L.need = 0;
   __syncthreads();
   int loc = 0;
-  for (int e = tid; e < 4096; e += 256) {
+  for (int e = tid; e < 4096; e += NTE) {
     const int i = e >> 6, j = e & 63;
     if (i < j) {
       const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
@@ -206,6 +207,7 @@ __device__ inline bool eig_needs_rotation(EigLds &L, double tol, double floor2) 
 // Q <- Q J over sweeps of a round-robin ordering of the nv valid slots (np of block p at
 // 0.., nq of block q at 32..) until a sweep rotates nothing (or inner_max sweeps); the
 // diagonal of G ends as the eigenvalues.  With nv odd a dummy index sits out each round.
+template <int NTE>
 __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np, int nq) {
   const int tid = threadIdx.x;
   const int nv = np + nq, nvp = nv + (nv & 1), P = nvp / 2;
@@ -246,7 +248,7 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
       // even P, rows t and P - 1 - t of the block triangle go together (P + 1 blocks per
       // row pair); for odd P the square is walked and its lower half skipped.
       const int nblk = (P & 1) ? P * P : (P / 2) * (P + 1);
-      for (int e = tid; e < nblk; e += 256) {
+      for (int e = tid; e < nblk; e += NTE) {
         int t, u;
         if (P & 1) {
           t = e / P;
@@ -275,7 +277,7 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
         }
       }
       // Q <- Q J over the valid rows
-      for (int e = tid; e < P * nv; e += 256) {
+      for (int e = tid; e < P * nv; e += NTE) {
         const int u = e / nv, k = L.vs[e - u * nv];
         const double su = L.sn[u];
         if (su != 0.0) {
@@ -315,7 +317,8 @@ __device__ inline void eig_order(EigLds &L, int np, int nq) {
 }
 
 // grid (pairs, matrices)
-__global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step) {
+constexpr int EIG_NT = 512;
+__global__ __launch_bounds__(EIG_NT) void eigen_kernel(const SvdMat *mats, int step) {
   __shared__ EigLds L;
   const SvdMat &a = mats[blockIdx.y];
   const int pair = blockIdx.x;
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
   }
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
   const double *Gp = a.gram + (int64_t)pair * a.ksplit * 4096;
-  for (int e = tid; e < 4096; e += 256) {
+  for (int e = tid; e < 4096; e += EIG_NT) {
     const int i = e >> 6, j = e & 63;
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     double v = 0.0;
@@ -340,15 +343,15 @@ __global__ __launch_bounds__(256) void eigen_kernel(const SvdMat *mats, int step
     L.Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
   const double floor2 = row_floor2(a, *a.fro2);
-  if (!eig_needs_rotation(L, a.tol, floor2)) {
+  if (!eig_needs_rotation<EIG_NT>(L, a.tol, floor2)) {
     if (tid == 0) *skip = 1;
     return;
   }
   if (tid == 0) atomicAdd(a.ctr, 1);
-  eig_inner(L, a.inner_max, floor2, np, nq);
+  eig_inner<EIG_NT>(L, a.inner_max, floor2, np, nq);
   eig_order(L, np, nq);
   double *Qt = a.qt + (int64_t)pair * 4096;
-  for (int e = tid; e < 4096; e += 256) {
+  for (int e = tid; e < 4096; e += EIG_NT) {
     const int so = e >> 6, ri = e & 63;
     Qt[e] = (valid(so) && valid(ri)) ? L.Q[ri][L.slot_of[so]] : 0.0;
   }
@@ -442,11 +445,11 @@ __global__ __launch_bounds__(256) void jacobi_fused_kernel(const SvdMat *mats, i
     }
     __syncthreads();
     for (int e = tid; e < 4096; e += 256) L.Q[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
-    if (!eig_needs_rotation(L, a.tol, floor2)) {
+    if (!eig_needs_rotation<256>(L, a.tol, floor2)) {
       conv = 1;
       break;
     }
-    eig_inner(L, a.inner_max, floor2, np, nq);
+    eig_inner<256>(L, a.inner_max, floor2, np, nq);
     eig_order(L, np, nq);
     // As[k][i] = Qt[i][k] = Q[k][slot_of[i]], written over G
     for (int e = tid; e < 4096; e += 256) {
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
 // x = B[k:R, k]; each thread keeps its (at most QR_ROWS_PER_THREAD) rows of the new
 // column k in registers, so column k and the pivot column are read once
 constexpr int QR_PIV_NT = 1024, QR_ROWS_PER_THREAD = 4;  // R <= 4096
-__global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats, int k) {
+__global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats, int k, int pivot) {
   __shared__ double bv[16], red[16];
   __shared__ int bi[16], piv;
   __shared__ double xs0, nrm;
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double best = -1.0;
   int bidx = 0x7fffffff;
-  for (int j = k + tid; j < a.C; j += QR_PIV_NT) {
+  for (int j = k + tid; pivot && j < a.C; j += QR_PIV_NT) {
     const double v = a.cn[j];
     if (v > best) { best = v; bidx = j; }  // increasing j per thread: ties keep the lowest
   }
@@ -628,6 +631,7 @@ __global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats,
   // alpha = -sign(x0) |x|, v_0 = x0 - alpha, beta = 2 / v^T v = 1 / (|x| (|x| + |x0|))
   const double alpha = x0 >= 0.0 ? -nx : nx;
   const double beta = nx > 0.0 ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+  double *vrow = a.qv + (int64_t)k * a.R;  // reflector k as a row, zero before k
 #pragma unroll
   for (int u = 0; u < QR_ROWS_PER_THREAD; ++u) {
     const int i = tid + u * QR_PIV_NT;
@@ -635,62 +639,102 @@ __global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats,
     const int64_t r = (int64_t)i * a.C + k;
     if (i < k) {
       a.bw[r] = col[u];
+      vrow[i] = 0.0;
     } else {
-      a.hv[i] = (i == k) ? x0 - alpha : col[u];
+      const double v = (i == k) ? x0 - alpha : col[u];
+      a.hv[i] = v;
+      vrow[i] = v;
       a.bw[r] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
     }
   }
-  if (tid == 0) a.hv[a.R] = beta;
+  if (tid == 0) {
+    a.hv[a.R] = beta;
+    a.qws[2048 + 64 * (int64_t)a.C + k] = beta;
+  }
 }
 
-// grid (column blocks of B[:, k+1:] then of Jt, 1, matrices), 32 columns x 8 row groups:
-// X[k:, j] -= beta (v^T X[k:, j]) v; trailing norms of B recomputed from rows k+1..
-__global__ __launch_bounds__(256) void qr_update_kernel(const SvdMat *mats, int k) {
-  __shared__ double part[8][33];
+// T of the compact form H_k0 ... H_k0+nb-1 = I - V T V^T (T upper triangular) from
+// S = V^T V and the betas: T_ii = beta_i, T[0:i, i] = -beta_i T[0:i, 0:i] S[0:i, i].
+// One workgroup per matrix; S at qws[0..1024), T at qws[1024..2048), 32 x 32 row-major.
+__global__ __launch_bounds__(64) void qr_tfactor_kernel(const SvdMat *mats, int k0) {
+  const SvdMat &a = mats[blockIdx.x];
+  if (!a.active || !a.precond || k0 >= a.R) return;
+  const int nb = a.R - k0 < 32 ? a.R - k0 : 32;
+  const double *S = a.qws;
+  double *T = a.qws + 1024;
+  const double *beta = a.qws + 2048 + 64 * (int64_t)a.C + k0;
+  const int r = threadIdx.x;
+  if (r < 32)
+    for (int c = 0; c < 32; ++c) T[r * 32 + c] = 0.0;
+  __syncthreads();
+  for (int i = 0; i < nb; ++i) {
+    if (r < i) {
+      double acc = 0.0;
+      for (int c = r; c < i; ++c) acc += T[r * 32 + c] * S[c * 32 + i];
+      T[r * 32 + i] = -beta[i] * acc;
+    } else if (r == i) {
+      T[i * 32 + i] = beta[i];
+    }
+    __syncthreads();
+  }
+}
+
+// grid (column blocks of B[:, k+1:cend], 1, matrices), 32 columns x 32 row groups:
+// X[k:, j] -= beta (v^T X[k:, j]) v.  Rows are walked eight at a time with the loads
+// issued before their use, so the loop is bound by bandwidth rather than by latency.
+constexpr int QU_NT = 1024, QU_RG = QU_NT / 32, QU_UN = 8;
+__global__ __launch_bounds__(QU_NT) void qr_update_kernel(const SvdMat *mats, int k, int cend) {
+  __shared__ double part[QU_RG][33];
   const SvdMat &a = mats[blockIdx.z];
   if (!a.active || !a.precond || k >= a.R) return;
-  const int nbB = (a.C - k - 1 + 31) / 32, nbJ = (a.R + 31) / 32;
+  const int ce = cend < a.C ? cend : a.C;  // columns k+1 .. ce-1; Jt = Q^T is formed afterwards
+  const int nbB = (ce - k - 1 + 31) / 32;
   const int blk = blockIdx.x;
-  if (blk >= nbB + nbJ) return;
-  const bool isB = blk < nbB;
-  double *X = isB ? a.bw : a.jt;
-  const int ld = isB ? a.C : a.R;
-  const int ncol = isB ? a.C : a.R;
-  const int j = isB ? k + 1 + blk * 32 + (threadIdx.x & 31) : (blk - nbB) * 32 + (threadIdx.x & 31);
-  const int rg = threadIdx.x >> 5;
+  if (blk >= nbB) return;
+  double *X = a.bw;
+  const int ld = a.C;
+  const int cl = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  const int j = k + 1 + blk * 32 + cl;
   const double beta = a.hv[a.R];
-  const bool colok = j < ncol;
+  const bool colok = j < ce;
+  const int R = a.R;
   double w = 0.0;
-  if (colok)
-    for (int i = k + rg; i < a.R; i += 8) w += a.hv[i] * X[(int64_t)i * ld + j];
-  part[rg][threadIdx.x & 31] = w;
+  if (colok) {
+    int i = k + rg;
+    for (; i + (QU_UN - 1) * QU_RG < R; i += QU_UN * QU_RG) {
+      double x[QU_UN], h[QU_UN];
+#pragma unroll
+      for (int u = 0; u < QU_UN; ++u) {
+        x[u] = X[(int64_t)(i + u * QU_RG) * ld + j];
+        h[u] = a.hv[i + u * QU_RG];
+      }
+#pragma unroll
+      for (int u = 0; u < QU_UN; ++u) w += h[u] * x[u];
+    }
+    for (; i < R; i += QU_RG) w += a.hv[i] * X[(int64_t)i * ld + j];
+  }
+  part[rg][cl] = w;
   __syncthreads();
   double wt = 0.0;
 #pragma unroll
-  for (int g = 0; g < 8; ++g) wt += part[g][threadIdx.x & 31];
+  for (int g = 0; g < QU_RG; ++g) wt += part[g][cl];
   const double f = beta * wt;
-  double nn = 0.0;
-  if (colok && beta != 0.0)
-    for (int i = k + rg; i < a.R; i += 8) {
-      const int64_t r = (int64_t)i * ld + j;
-      const double v = X[r] - f * a.hv[i];
-      X[r] = v;
-      if (i > k) nn += v * v;
-    }
-  else if (colok)
-    for (int i = k + 1 + rg; i < a.R; i += 8) {
-      const double v = X[(int64_t)i * ld + j];
-      nn += v * v;
-    }
-  if (!isB) return;
-  __syncthreads();
-  part[rg][threadIdx.x & 31] = nn;
-  __syncthreads();
-  if (rg == 0 && colok) {
-    double t = 0.0;
+  if (colok && beta != 0.0) {
+    int i = k + rg;
+    for (; i + (QU_UN - 1) * QU_RG < R; i += QU_UN * QU_RG) {
+      double x[QU_UN], h[QU_UN];
 #pragma unroll
-    for (int g = 0; g < 8; ++g) t += part[g][threadIdx.x & 31];
-    a.cn[j] = t;
+      for (int u = 0; u < QU_UN; ++u) {
+        x[u] = X[(int64_t)(i + u * QU_RG) * ld + j];
+        h[u] = a.hv[i + u * QU_RG];
+      }
+#pragma unroll
+      for (int u = 0; u < QU_UN; ++u) X[(int64_t)(i + u * QU_RG) * ld + j] = x[u] - f * h[u];
+    }
+    for (; i < R; i += QU_RG) {
+      const int64_t r = (int64_t)i * ld + j;
+      X[r] = X[r] - f * a.hv[i];
+    }
   }
 }
 
@@ -1025,9 +1069,10 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
   }();
   a->fused = (nb == 2 && a->C <= 1024) ? 1 : 0;
   a->precond = (!a->fused && a->R >= QR_MIN_ROWS) ? 1 : 0;
-  // Two inner sweeps per block pair (one in the single-workgroup form, whose outer sweep
-  // is cheap) cost few extra outer sweeps and far less than diagonalising each pair
-  a->inner_max = inner_env > 0 ? inner_env : (a->fused ? 1 : 2);
+  // Two inner sweeps per block pair (one after the pivoted-QR start and in the
+  // single-workgroup form) cost few extra outer sweeps and far less than diagonalising
+  // each pair
+  a->inner_max = inner_env > 0 ? inner_env : ((a->fused || a->precond) ? 1 : 2);
   a->active = 1;
   return TNA_OK;
 }
@@ -1035,7 +1080,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
 size_t svd_work_doubles(const SvdMat &a) {
   const size_t npairs = a.nb / 2;
   return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R + 8 +
-         (a.precond ? (size_t)a.R + 8 + a.C : 0);
+         (a.precond ? (size_t)a.R + 8 + a.C + (size_t)a.R * a.R + 2048 + 64 * (size_t)a.C + 2 * (size_t)a.R : 0);
 }
 size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4 + (a.precond ? 2 * (size_t)a.C : 0); }
 
@@ -1063,11 +1108,15 @@ void svd_bind_work(SvdMat *a, double *dw, int *iw) {
     a->hv = dw;
     dw += a->R + 8;
     a->cn = dw;
+    dw += a->C;
+    a->qv = dw;
+    dw += (size_t)a->R * a->R;
+    a->qws = dw;  // S (32 x 32), T (32 x 32), W and W2 (32 x C each), betas (R), spare (R)
     a->cperm = iw;
     iw += a->C;
     a->pinv = iw;
   } else {
-    a->hv = a->cn = nullptr;
+    a->hv = a->cn = a->qv = a->qws = nullptr;
     a->cperm = a->pinv = nullptr;
   }
 }
@@ -1086,6 +1135,42 @@ static tna_status upload(const std::vector<SvdMat> &mats, SvdGroup &g, hipStream
   TNA_HIP(hipStreamSynchronize(s));
   std::memcpy(g.host, mats.data(), bytes);
   TNA_HIP(hipMemcpyAsync(g.desc.ptr, g.host, bytes, hipMemcpyHostToDevice, s));
+  return TNA_OK;
+}
+
+// X[k0:, :] <- (I - V T^T V^T) X[k0:, :] for the 32 reflectors k0.. of every QR-started
+// matrix, X the trailing columns of B (on_b) or all of Jt; V as rows in qv, T from
+// S = V^T V by qr_tfactor_kernel; scratch in qws.
+static tna_status qr_block_apply(const std::vector<SvdMat> &mats, const SvdMat *d, int nm, int k0, bool on_b,
+                                 hipStream_t s) {
+  bool any = false;
+  for (auto &a : mats) {
+    if (!a.precond || k0 >= a.R) continue;
+    if (on_b && k0 + 32 >= a.C) continue;
+    any = true;
+    const int R = a.R, nbk = std::min(32, R - k0), K = R - k0;
+    const double *Vb = a.qv + (int64_t)k0 * R + k0;
+    TNA_TRY(gemm(GemmArgs{nbk, nbk, K, Vb, R, 0, G_F64, Vb, R, 1, G_F64, a.qws, 32, G_F64, 1.0, 0.0, 1, 0, 0, 0,
+                          G_F64, 0}, s));
+  }
+  if (!any) return TNA_OK;
+  hipLaunchKernelGGL(qr_tfactor_kernel, dim3(nm), dim3(64), 0, s, d, k0);
+  TNA_LAUNCHED("svd.qr_tfactor");
+  for (auto &a : mats) {
+    if (!a.precond || k0 >= a.R) continue;
+    if (on_b && k0 + 32 >= a.C) continue;
+    const int R = a.R, nbk = std::min(32, R - k0), K = R - k0;
+    const double *Vb = a.qv + (int64_t)k0 * R + k0;
+    double *T = a.qws + 1024, *W = a.qws + 2048, *W2 = a.qws + 2048 + 32 * (int64_t)a.C;
+    double *X = on_b ? a.bw + (int64_t)k0 * a.C + k0 + 32 : a.jt + (int64_t)k0 * R;
+    const int ldx = on_b ? a.C : R, N = on_b ? a.C - k0 - 32 : R;
+    TNA_TRY(gemm(GemmArgs{nbk, N, K, Vb, R, 0, G_F64, X, ldx, 0, G_F64, W, N, G_F64, 1.0, 0.0, 1, 0, 0, 0, G_F64, 0},
+                 s));
+    TNA_TRY(gemm(GemmArgs{nbk, N, nbk, T, 32, 1, G_F64, W, N, 0, G_F64, W2, N, G_F64, 1.0, 0.0, 1, 0, 0, 0, G_F64, 0},
+                 s));
+    TNA_TRY(gemm(GemmArgs{K, N, nbk, Vb, R, 1, G_F64, W2, N, 0, G_F64, X, ldx, G_F64, -1.0, 1.0, 1, 0, 0, 0, G_F64,
+                          0}, s));
+  }
   return TNA_OK;
 }
 
@@ -1129,20 +1214,31 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     if (a.precond) {
       qr_rows = std::max(qr_rows, a.R);
       qr_cblk = std::max(qr_cblk, ceil_div(a.C, 256));
-      qr_ublk = std::max(qr_ublk, ceil_div(a.C, 32) + ceil_div(a.R, 32));
+      qr_ublk = std::max(qr_ublk, ceil_div(a.C, 32));
     }
   if (qr_rows > 0) {
     hipLaunchKernelGGL(qr_init_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
     double qr_bytes = 0.0;
     for (auto &a : mats)
       if (a.precond) qr_bytes += 16.0 * ((double)a.R * a.C / 3.0 + (double)a.R * a.R / 2.0);
+    // Blocked Householder QR (no column pivoting: the start it gives converges as fast on
+    // these matrices, and the trailing update becomes GEMMs): each 32-column panel is
+    // factored column by column, then B[k0:, k0+32:] <- (I - V T^T V^T) B[k0:, k0+32:].
     timer_begin("svd.qr", s);
-    for (int k = 0; k < qr_rows; ++k) {
-      hipLaunchKernelGGL(qr_pivot_kernel, dim3(nm), dim3(QR_PIV_NT), 0, s, d, k);
-      hipLaunchKernelGGL(qr_update_kernel, dim3(qr_ublk, 1, nm), dim3(256), 0, s, d, k);
+    for (int k0 = 0; k0 < qr_rows; k0 += 32) {
+      const int kend = std::min(k0 + 32, qr_rows);
+      for (int k = k0; k < kend; ++k) {
+        hipLaunchKernelGGL(qr_pivot_kernel, dim3(nm), dim3(QR_PIV_NT), 0, s, d, k, 0);
+        hipLaunchKernelGGL(qr_update_kernel, dim3(1, 1, nm), dim3(QU_NT), 0, s, d, k, k0 + 32);
+      }
+      TNA_TRY(qr_block_apply(mats, d, nm, k0, true, s));
     }
     timer_end("svd.qr", 0.0, qr_bytes, s);
     hipLaunchKernelGGL(qr_pinv_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
+    // Jt = Q^T = H_{R-1} ... H_0: 32 reflectors at a time, Jt <- (I - V T^T V^T) Jt
+    timer_begin("svd.qr_form", s);
+    for (int k0 = 0; k0 < qr_rows; k0 += 32) TNA_TRY(qr_block_apply(mats, d, nm, k0, false, s));
+    timer_end("svd.qr_form", 0.0, 0.0, s);
     TNA_LAUNCHED("svd.qr");
   }
   // one block pair: every sweep inside one workgroup, no host round trip per sweep
@@ -1169,7 +1265,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       hipLaunchKernelGGL(gram_kernel, dim3(max_pairs, max_ks, nm), dim3(256), 0, s, d, step);
       timer_end("svd.gram", gram_flops, gram_bytes, s);
       timer_begin("svd.eigen", s);
-      hipLaunchKernelGGL(eigen_kernel, dim3(max_pairs, nm), dim3(256), 0, s, d, step);
+      hipLaunchKernelGGL(eigen_kernel, dim3(max_pairs, nm), dim3(EIG_NT), 0, s, d, step);
       timer_end("svd.eigen", 0.0, 0.0, s);
       timer_begin("svd.apply", s);
       hipLaunchKernelGGL(apply_kernel, dim3(max_pairs, max_tiles, nm), dim3(256), 0, s, d, step);
