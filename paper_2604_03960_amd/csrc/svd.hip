@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void jacobi_fused_kernel(const SvdMat *mats, i
   __shared__ EigLds L;
   __shared__ double Xs[64][65];  // Gram staging, then apply tiles
   const SvdMat &a = mats[blockIdx.x];
-  if (!a.active || !a.fused) return;
+  if (!a.active || a.fused != 1) return;
   const int tid = threadIdx.x;
   const int np = block_rows(a.R, 0), nq = block_rows(a.R, 1);
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
@@ -465,6 +465,100 @@ __global__ __launch_bounds__(256) void jacobi_fused_kernel(const SvdMat *mats, i
     apply_tile(a.jt, a.R, 0, L.G, Xs, valid, grow);
     __syncthreads();
   }
+  if (tid == 0) {
+    a.ctr[0] = conv ? 0 : 1;
+    a.ctr[1] = sw;
+  }
+}
+
+// -------------------------------------------------------------- one-sided Jacobi, tiny matrices
+// At most 32 rows of at most 64 columns: the cyclic one-sided (Hestenes) method directly on
+// the rows, held in LDS with Jt.  Round-robin rounds of at most 16 disjoint row pairs; the 16
+// lanes of a pair's lane group each hold 4 columns of B and 2 of Jt, the three dot products
+// are reduced with shuffles inside the group, and every round ends with one barrier.
+// Rotation and tests as in the blocked method: J = [[c, s], [-s, c]] on rows (i, j), i < j,
+// outer tolerance a.tol, rows at the rounding floor left alone.  ctr[0] = 0 when converged,
+// ctr[1] = sweeps.  grid (matrices), 256 threads.
+__global__ __launch_bounds__(256) void jacobi_tiny_kernel(const SvdMat *mats, int max_sweeps) {
+  __shared__ double Bs[32][65];
+  __shared__ double Js[32][33];
+  __shared__ int vs_dummy;
+  const SvdMat &a = mats[blockIdx.x];
+  if (!a.active || a.fused != 2) return;
+  const int tid = threadIdx.x, t = tid >> 4, l = tid & 15;
+  const int R = a.R, C = a.C;
+  for (int e = tid; e < 32 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    Bs[r][c] = (r < R && c < C) ? a.bw[(int64_t)r * C + c] : 0.0;
+  }
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    Js[r][c] = (r < R && c < R) ? a.jt[(int64_t)r * R + c] : 0.0;
+  }
+  (void)vs_dummy;
+  const double floor2 = row_floor2(a, *a.fro2);
+  const int nvp = R + (R & 1), P = nvp / 2;
+  int sw = 0, conv = 0;
+  __syncthreads();
+  while (sw < max_sweeps) {
+    ++sw;
+    int rot = 0;
+    for (int rr = 0; rr < nvp - 1; ++rr) {
+      int i = -1, j = -1;
+      if (t < P) {
+        if (t == 0) { i = rr % (nvp - 1); j = nvp - 1; }
+        else { i = (rr + t) % (nvp - 1); j = (rr - t + nvp - 1) % (nvp - 1); }
+        if (i > j) { const int q = i; i = j; j = q; }
+        if (j >= R) i = -1;  // the dummy of an odd R
+      }
+      double xa[4], ya[4], xj[2], yj[2];
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (i >= 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xa[u] = Bs[i][l + 16 * u];
+          ya[u] = Bs[j][l + 16 * u];
+          al += xa[u] * xa[u];
+          be += ya[u] * ya[u];
+          ga += xa[u] * ya[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          xj[u] = Js[i][l + 16 * u];
+          yj[u] = Js[j][l + 16 * u];
+        }
+      }
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, 16);
+        be += __shfl_xor(be, off, 16);
+        ga += __shfl_xor(ga, off, 16);
+      }
+      if (i >= 0 && al > floor2 && be > floor2 && al > 0.0 && be > 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          Bs[i][l + 16 * u] = c * xa[u] - s * ya[u];
+          Bs[j][l + 16 * u] = s * xa[u] + c * ya[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          Js[i][l + 16 * u] = c * xj[u] - s * yj[u];
+          Js[j][l + 16 * u] = s * xj[u] + c * yj[u];
+        }
+        rot = 1;
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot)) {
+      conv = 1;
+      break;
+    }
+  }
+  for (int e = tid; e < R * C; e += 256) a.bw[e] = Bs[e / C][e % C];
+  for (int e = tid; e < R * R; e += 256) a.jt[e] = Js[e / R][e % R];
   if (tid == 0) {
     a.ctr[0] = conv ? 0 : 1;
     a.ctr[1] = sw;
@@ -1067,7 +1161,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
     const char *e = std::getenv("TNA_SVD_INNER");
     return e ? std::atoi(e) : 0;
   }();
-  a->fused = (nb == 2 && a->C <= 1024) ? 1 : 0;
+  a->fused = (a->R <= 32 && a->C <= 64) ? 2 : ((nb == 2 && a->C <= 1024) ? 1 : 0);
   a->precond = (!a->fused && a->R >= QR_MIN_ROWS) ? 1 : 0;
   // Two inner sweeps per block pair (one after the pivoted-QR start and in the
   // single-workgroup form) cost few extra outer sweeps and far less than diagonalising
@@ -1247,6 +1341,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
   if (nfused > 0) {
     timer_begin("svd.fused", s);
     hipLaunchKernelGGL(jacobi_fused_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
+    hipLaunchKernelGGL(jacobi_tiny_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
     timer_end("svd.fused", 0.0, 0.0, s);
     TNA_LAUNCHED("svd.fused");
   }
