@@ -165,8 +165,7 @@ struct SvdMat {
   int *skip, *perm, *ctr;                      // work
   void *U, *Vt;                                // m x k, k x n (out_type)
   double *fro2;                                // work: |A|_F^2 (device scalar)
-  int precond, pad2_;                          // 1: rows start from the R factor of a pivoted QR
-  double *hv, *cn;                             // work: Householder vector (R + 1, beta last), column norms (C)
+  int precond, pad2_;                          // 1: rows start from the R factor of a Householder QR
   int *cperm, *pinv;                           // work: original column at position c, and its inverse (C each)
   double *qv, *qws;                            // work: reflectors as rows (R x R), blocked-product scratch
 };

@@ -177,7 +177,7 @@ struct EigLds {
 // row are neither tested nor rotated (the relative test could never settle on them).
 // Skipping a coupling g_ij <= sigma_i sigma_floor moves sigma_i by at most
 // sigma_floor^2 / sigma_i; kept vectors below the floor are completed afterwards.
-// After the pivoted-QR start the rows are graded and even rows at the rounding level
+// After the QR start even rows at the rounding level
 // settle under the relative test, so no floor is used there.
 __device__ inline double row_floor2(const SvdMat &a, double fro2) {
   if (a.precond) return 0.0;
@@ -390,30 +390,37 @@ __device__ inline void apply_tile(double *X, int ld, int c0, double (*As)[65], d
     }
 }
 
-// grid (pairs, column tiles of B then of Jt, matrices)
+// grid (pairs, groups of APPLY_TPW column tiles of B then of Jt, matrices): the pair's
+// rotation is read into LDS once and applied to each tile of the group in turn
+constexpr int APPLY_TPW = 4;
 __global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step) {
   __shared__ double As[64][65];  // As[k][i] = Qt[i][k]
   __shared__ double Xs[64][65];  // Xs[k][j] = X[row(k)][c0 + j]
   const SvdMat &a = mats[blockIdx.z];
-  const int pair = blockIdx.x, tile = blockIdx.y;
+  const int pair = blockIdx.x;
   const int ntile_b = (a.C + 63) / 64, ntile_j = (a.R + 63) / 64;
-  if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2 || tile >= ntile_b + ntile_j) return;
+  const int t0 = blockIdx.y * APPLY_TPW;
+  if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2 || t0 >= ntile_b + ntile_j) return;
   if (a.skip[pair]) return;
   int p, q;
   rr_pair(a.nb, step, pair, p, q);
   const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
   auto grow = [&](int r) { return r < 32 ? p * BS + r : q * BS + (r - 32); };
-  double *X;
-  int ld, c0;
-  if (tile < ntile_b) { X = a.bw; ld = a.C; c0 = tile * 64; }
-  else { X = a.jt; ld = a.R; c0 = (tile - ntile_b) * 64; }
   const double *Qt = a.qt + (int64_t)pair * 4096;
   for (int e = threadIdx.x; e < 4096; e += 256) {
     const int i = e >> 6, k = e & 63;
     As[k][i] = Qt[e];
   }
-  apply_tile(X, ld, c0, As, Xs, valid, grow);
+  const int t1 = t0 + APPLY_TPW < ntile_b + ntile_j ? t0 + APPLY_TPW : ntile_b + ntile_j;
+  for (int tile = t0; tile < t1; ++tile) {
+    double *X;
+    int ld, c0;
+    if (tile < ntile_b) { X = a.bw; ld = a.C; c0 = tile * 64; }
+    else { X = a.jt; ld = a.R; c0 = (tile - ntile_b) * 64; }
+    apply_tile(X, ld, c0, As, Xs, valid, grow);
+    __syncthreads();  // Xs is refilled by the next tile
+  }
 }
 
 // -------------------------------------------------------------- whole Jacobi, one workgroup
@@ -631,119 +638,108 @@ __global__ void zero_ctr_kernel(const SvdMat *mats, int nmat) {
   if (z < nmat && mats[z].active && !mats[z].fused) *mats[z].ctr = 0;
 }
 
-// -------------------------------------------------------------- pivoted QR start
-// Householder QR with column pivoting of the loaded rows, B P = Q Rf, turns the
-// start state (B, Jt) = (A, I) into (Rf, Q^T): B = Jt A (up to the column
-// order, recorded in cperm) still holds, and the rows of Rf are graded, which
-// the one-sided Jacobi needs far fewer sweeps on than on A itself.  Step k:
-// one workgroup per matrix picks the trailing column of largest norm, swaps it
-// to k and forms the reflector; then every column of the trailing B and of Jt
-// is reflected (and the trailing norms recomputed) independently.
+// -------------------------------------------------------------- QR start
+// A Householder QR of the loaded rows, B = Q Rf, turns the start state (B, Jt) =
+// (A, I) into (Rf, Q^T): B = Jt A still holds, and the one-sided Jacobi needs far
+// fewer sweeps on the rows of Rf than on A itself.  Blocked: each panel of 32
+// columns is factored by one workgroup, the trailing columns take the panel's
+// block reflector as three GEMMs, and Q^T is formed from the stored reflectors the
+// same way.  No column pivoting: on the prescribed-spectrum matrices it did not
+// lower the sweep count; cperm / pinv keep the (identity) column order explicit.
 constexpr int QR_MIN_ROWS_DEV = 256;
 
-// grid (column blocks, 1, matrices): column norms and the identity order
+// grid (column blocks, 1, matrices): the identity column order (no pivoting is used)
 __global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
   const SvdMat &a = mats[blockIdx.z];
   if (!a.active || !a.precond) return;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= a.C) return;
-  double s = 0.0;
-  for (int i = 0; i < a.R; ++i) {
-    const double v = a.bw[(int64_t)i * a.C + j];
-    s += v * v;
-  }
-  a.cn[j] = s;
-  a.cperm[j] = j;
+  if (j < a.C) a.cperm[j] = j;
 }
 
-// grid (matrices), 1024 threads: pivot, column swap, reflector v = x - alpha e_0 of
-// x = B[k:R, k]; each thread keeps its (at most QR_ROWS_PER_THREAD) rows of the new
-// column k in registers, so column k and the pivot column are read once
-constexpr int QR_PIV_NT = 1024, QR_ROWS_PER_THREAD = 4;  // R <= 4096
-__global__ __launch_bounds__(QR_PIV_NT) void qr_pivot_kernel(const SvdMat *mats, int k, int pivot) {
-  __shared__ double bv[16], red[16];
-  __shared__ int bi[16], piv;
-  __shared__ double xs0, nrm;
+// grid (matrices), 1024 threads: Householder QR of the panel of columns k0 .. k0+31 of B
+// (rows k0..), one column after the other: x = B[k:R, k], alpha = -sign(x_0) |x|,
+// v = x - alpha e_0 (kept in LDS, stored as row k of qv), beta = 2 / v^T v =
+// 1 / (|x| (|x| + |x_0|)) (stored in qws); B[k:, k] <- (alpha, 0, ...); then every later
+// column c of the panel: B[k:, c] -= beta (v^T B[k:, c]) v, rows walked eight at a time
+// with the loads issued before their use.  The trailing columns are updated afterwards
+// with the block reflector (qr_block_apply).
+constexpr int QP_NT = 1024, QP_RG = QP_NT / 32, QP_UN = 8;
+__global__ __launch_bounds__(QP_NT) void qr_panel_kernel(const SvdMat *mats, int k0) {
+  __shared__ double vsh[4096];
+  __shared__ double red[QP_NT / 64];
+  __shared__ double part[QP_RG][33];
+  __shared__ double s_x0, s_nrm;
   const SvdMat &a = mats[blockIdx.x];
-  if (!a.active || !a.precond || k >= a.R) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double best = -1.0;
-  int bidx = 0x7fffffff;
-  for (int j = k + tid; pivot && j < a.C; j += QR_PIV_NT) {
-    const double v = a.cn[j];
-    if (v > best) { best = v; bidx = j; }  // increasing j per thread: ties keep the lowest
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(best, off, 64);
-    const int oi = __shfl_xor(bidx, off, 64);
-    if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-  }
-  if (lane == 0) { bv[wave] = best; bi[wave] = bidx; }
-  __syncthreads();
-  if (tid == 0) {
-    double b = bv[0];
-    int ii = bi[0];
-    for (int w = 1; w < QR_PIV_NT / 64; ++w)
-      if (bv[w] > b || (bv[w] == b && bi[w] < ii)) { b = bv[w]; ii = bi[w]; }
-    piv = (ii >= k && ii < a.C) ? ii : k;
-  }
-  __syncthreads();
-  const int p = piv;
-  double col[QR_ROWS_PER_THREAD];
-  double s = 0.0;
-#pragma unroll
-  for (int u = 0; u < QR_ROWS_PER_THREAD; ++u) {
-    const int i = tid + u * QR_PIV_NT;
-    col[u] = 0.0;
-    if (i < a.R) {
-      const int64_t r = (int64_t)i * a.C;
-      const double xk = a.bw[r + k], xp = a.bw[r + p];
-      if (p != k) a.bw[r + p] = xk;
-      col[u] = xp;  // new column k
-      if (i >= k) s += xp * xp;
+  if (!a.active || !a.precond || k0 >= a.R) return;
+  const int R = a.R, C = a.C, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kend = k0 + 32 < R ? k0 + 32 : R;
+  const int cend = k0 + 32 < C ? k0 + 32 : C;
+  double *B = a.bw;
+  for (int k = k0; k < kend; ++k) {
+    double ss = 0.0;
+    for (int i = k + tid; i < R; i += QP_NT) {
+      const double x = B[(int64_t)i * C + k];
+      vsh[i] = x;
+      ss += x * x;
     }
-  }
-  if (tid == 0 && p != k) {
-    const double tc = a.cn[k];
-    a.cn[k] = a.cn[p];
-    a.cn[p] = tc;
-    const int tp = a.cperm[k];
-    a.cperm[k] = a.cperm[p];
-    a.cperm[p] = tp;
-  }
-  s = wave_sum_d(s);
-  if (lane == 0) red[wave] = s;
-  if (tid == (k % QR_PIV_NT)) xs0 = col[k / QR_PIV_NT];
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < QR_PIV_NT / 64; ++w) t += red[w];
-    nrm = sqrt(t);
-  }
-  __syncthreads();
-  const double x0 = xs0, nx = nrm;
-  // alpha = -sign(x0) |x|, v_0 = x0 - alpha, beta = 2 / v^T v = 1 / (|x| (|x| + |x0|))
-  const double alpha = x0 >= 0.0 ? -nx : nx;
-  const double beta = nx > 0.0 ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
-  double *vrow = a.qv + (int64_t)k * a.R;  // reflector k as a row, zero before k
-#pragma unroll
-  for (int u = 0; u < QR_ROWS_PER_THREAD; ++u) {
-    const int i = tid + u * QR_PIV_NT;
-    if (i >= a.R) continue;
-    const int64_t r = (int64_t)i * a.C + k;
-    if (i < k) {
-      a.bw[r] = col[u];
-      vrow[i] = 0.0;
-    } else {
-      const double v = (i == k) ? x0 - alpha : col[u];
-      a.hv[i] = v;
-      vrow[i] = v;
-      a.bw[r] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
+    ss = wave_sum_d(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < QP_NT / 64; ++w) t += red[w];
+      s_nrm = sqrt(t);
+      s_x0 = vsh[k];
     }
-  }
-  if (tid == 0) {
-    a.hv[a.R] = beta;
-    a.qws[2048 + 64 * (int64_t)a.C + k] = beta;
+    __syncthreads();
+    const double x0 = s_x0, nx = s_nrm;
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    const double beta = nx > 0.0 ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+    if (tid == 0) {
+      vsh[k] = x0 - alpha;
+      a.qws[2048 + 64 * (int64_t)C + k] = beta;
+    }
+    __syncthreads();
+    double *vrow = a.qv + (int64_t)k * R;
+    for (int i = tid; i < R; i += QP_NT) {
+      vrow[i] = i < k ? 0.0 : vsh[i];
+      if (i >= k) B[(int64_t)i * C + k] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
+    }
+    const int cl = tid & 31, rg = tid >> 5, c = k + 1 + cl;
+    const bool colok = c < cend && beta != 0.0;
+    double w = 0.0;
+    if (colok) {
+      int i = k + rg;
+      for (; i + (QP_UN - 1) * QP_RG < R; i += QP_UN * QP_RG) {
+        double x[QP_UN];
+#pragma unroll
+        for (int u = 0; u < QP_UN; ++u) x[u] = B[(int64_t)(i + u * QP_RG) * C + c];
+#pragma unroll
+        for (int u = 0; u < QP_UN; ++u) w += vsh[i + u * QP_RG] * x[u];
+      }
+      for (; i < R; i += QP_RG) w += vsh[i] * B[(int64_t)i * C + c];
+    }
+    part[rg][cl] = w;
+    __syncthreads();
+    if (colok) {
+      double wt = 0.0;
+#pragma unroll
+      for (int g = 0; g < QP_RG; ++g) wt += part[g][cl];
+      const double f = beta * wt;
+      int i = k + rg;
+      for (; i + (QP_UN - 1) * QP_RG < R; i += QP_UN * QP_RG) {
+        double x[QP_UN];
+#pragma unroll
+        for (int u = 0; u < QP_UN; ++u) x[u] = B[(int64_t)(i + u * QP_RG) * C + c];
+#pragma unroll
+        for (int u = 0; u < QP_UN; ++u) B[(int64_t)(i + u * QP_RG) * C + c] = x[u] - f * vsh[i + u * QP_RG];
+      }
+      for (; i < R; i += QP_RG) {
+        const int64_t r = (int64_t)i * C + c;
+        B[r] = B[r] - f * vsh[i];
+      }
+    }
+    __syncthreads();  // panel column k+1 and vsh are rewritten next
   }
 }
 
@@ -770,65 +766,6 @@ __global__ __launch_bounds__(64) void qr_tfactor_kernel(const SvdMat *mats, int 
       T[i * 32 + i] = beta[i];
     }
     __syncthreads();
-  }
-}
-
-// grid (column blocks of B[:, k+1:cend], 1, matrices), 32 columns x 32 row groups:
-// X[k:, j] -= beta (v^T X[k:, j]) v.  Rows are walked eight at a time with the loads
-// issued before their use, so the loop is bound by bandwidth rather than by latency.
-constexpr int QU_NT = 1024, QU_RG = QU_NT / 32, QU_UN = 8;
-__global__ __launch_bounds__(QU_NT) void qr_update_kernel(const SvdMat *mats, int k, int cend) {
-  __shared__ double part[QU_RG][33];
-  const SvdMat &a = mats[blockIdx.z];
-  if (!a.active || !a.precond || k >= a.R) return;
-  const int ce = cend < a.C ? cend : a.C;  // columns k+1 .. ce-1; Jt = Q^T is formed afterwards
-  const int nbB = (ce - k - 1 + 31) / 32;
-  const int blk = blockIdx.x;
-  if (blk >= nbB) return;
-  double *X = a.bw;
-  const int ld = a.C;
-  const int cl = threadIdx.x & 31, rg = threadIdx.x >> 5;
-  const int j = k + 1 + blk * 32 + cl;
-  const double beta = a.hv[a.R];
-  const bool colok = j < ce;
-  const int R = a.R;
-  double w = 0.0;
-  if (colok) {
-    int i = k + rg;
-    for (; i + (QU_UN - 1) * QU_RG < R; i += QU_UN * QU_RG) {
-      double x[QU_UN], h[QU_UN];
-#pragma unroll
-      for (int u = 0; u < QU_UN; ++u) {
-        x[u] = X[(int64_t)(i + u * QU_RG) * ld + j];
-        h[u] = a.hv[i + u * QU_RG];
-      }
-#pragma unroll
-      for (int u = 0; u < QU_UN; ++u) w += h[u] * x[u];
-    }
-    for (; i < R; i += QU_RG) w += a.hv[i] * X[(int64_t)i * ld + j];
-  }
-  part[rg][cl] = w;
-  __syncthreads();
-  double wt = 0.0;
-#pragma unroll
-  for (int g = 0; g < QU_RG; ++g) wt += part[g][cl];
-  const double f = beta * wt;
-  if (colok && beta != 0.0) {
-    int i = k + rg;
-    for (; i + (QU_UN - 1) * QU_RG < R; i += QU_UN * QU_RG) {
-      double x[QU_UN], h[QU_UN];
-#pragma unroll
-      for (int u = 0; u < QU_UN; ++u) {
-        x[u] = X[(int64_t)(i + u * QU_RG) * ld + j];
-        h[u] = a.hv[i + u * QU_RG];
-      }
-#pragma unroll
-      for (int u = 0; u < QU_UN; ++u) X[(int64_t)(i + u * QU_RG) * ld + j] = x[u] - f * h[u];
-    }
-    for (; i < R; i += QU_RG) {
-      const int64_t r = (int64_t)i * ld + j;
-      X[r] = X[r] - f * a.hv[i];
-    }
   }
 }
 
@@ -968,7 +905,7 @@ __global__ __launch_bounds__(256) void trunc_kernel(const SvdMat *mats) {
 
 // Kept values at or below this are null: at the rounding level of sigma_0 or under the
 // Jacobi row floor (whose rows were never orthogonalised against the others).  With the
-// pivoted-QR start every row with a nonzero norm was orthogonalised, so only rows whose
+// QR start every row with a nonzero norm was orthogonalised, so only rows whose
 // squares underflow count as null there.
 __device__ inline double null_threshold(const SvdMat &a) {
   if (a.precond) return 1e-150 * a.S[0];
@@ -1163,7 +1100,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
   }();
   a->fused = (a->R <= 32 && a->C <= 64) ? 2 : ((nb == 2 && a->C <= 1024) ? 1 : 0);
   a->precond = (!a->fused && a->R >= QR_MIN_ROWS) ? 1 : 0;
-  // Two inner sweeps per block pair (one after the pivoted-QR start and in the
+  // Two inner sweeps per block pair (one after the QR start and in the
   // single-workgroup form) cost few extra outer sweeps and far less than diagonalising
   // each pair
   a->inner_max = inner_env > 0 ? inner_env : ((a->fused || a->precond) ? 1 : 2);
@@ -1174,7 +1111,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
 size_t svd_work_doubles(const SvdMat &a) {
   const size_t npairs = a.nb / 2;
   return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R + 8 +
-         (a.precond ? (size_t)a.R + 8 + a.C + (size_t)a.R * a.R + 2048 + 64 * (size_t)a.C + 2 * (size_t)a.R : 0);
+         (a.precond ? (size_t)a.R * a.R + 2048 + 64 * (size_t)a.C + 2 * (size_t)a.R : 0);
 }
 size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4 + (a.precond ? 2 * (size_t)a.C : 0); }
 
@@ -1199,10 +1136,6 @@ void svd_bind_work(SvdMat *a, double *dw, int *iw) {
   a->ctr = iw;
   iw += 4;
   if (a->precond) {
-    a->hv = dw;
-    dw += a->R + 8;
-    a->cn = dw;
-    dw += a->C;
     a->qv = dw;
     dw += (size_t)a->R * a->R;
     a->qws = dw;  // S (32 x 32), T (32 x 32), W and W2 (32 x C each), betas (R), spare (R)
@@ -1210,7 +1143,7 @@ void svd_bind_work(SvdMat *a, double *dw, int *iw) {
     iw += a->C;
     a->pinv = iw;
   } else {
-    a->hv = a->cn = a->qv = a->qws = nullptr;
+    a->qv = a->qws = nullptr;
     a->cperm = a->pinv = nullptr;
   }
 }
@@ -1302,13 +1235,12 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     apply_flops += 2.0 * b2 * (double)(a.C + a.R) * pairs;
     apply_bytes += 16.0 * ((double)a.R * a.C + (double)a.R * a.R);
   }
-  // pivoted-QR start for the larger matrices
-  int qr_rows = 0, qr_cblk = 0, qr_ublk = 0;
+  // QR start for the larger matrices
+  int qr_rows = 0, qr_cblk = 0;
   for (auto &a : mats)
     if (a.precond) {
       qr_rows = std::max(qr_rows, a.R);
       qr_cblk = std::max(qr_cblk, ceil_div(a.C, 256));
-      qr_ublk = std::max(qr_ublk, ceil_div(a.C, 32));
     }
   if (qr_rows > 0) {
     hipLaunchKernelGGL(qr_init_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
@@ -1320,11 +1252,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     // factored column by column, then B[k0:, k0+32:] <- (I - V T^T V^T) B[k0:, k0+32:].
     timer_begin("svd.qr", s);
     for (int k0 = 0; k0 < qr_rows; k0 += 32) {
-      const int kend = std::min(k0 + 32, qr_rows);
-      for (int k = k0; k < kend; ++k) {
-        hipLaunchKernelGGL(qr_pivot_kernel, dim3(nm), dim3(QR_PIV_NT), 0, s, d, k, 0);
-        hipLaunchKernelGGL(qr_update_kernel, dim3(1, 1, nm), dim3(QU_NT), 0, s, d, k, k0 + 32);
-      }
+      hipLaunchKernelGGL(qr_panel_kernel, dim3(nm), dim3(QP_NT), 0, s, d, k0);
       TNA_TRY(qr_block_apply(mats, d, nm, k0, true, s));
     }
     timer_end("svd.qr", 0.0, qr_bytes, s);
@@ -1363,7 +1291,8 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       hipLaunchKernelGGL(eigen_kernel, dim3(max_pairs, nm), dim3(EIG_NT), 0, s, d, step);
       timer_end("svd.eigen", 0.0, 0.0, s);
       timer_begin("svd.apply", s);
-      hipLaunchKernelGGL(apply_kernel, dim3(max_pairs, max_tiles, nm), dim3(256), 0, s, d, step);
+      hipLaunchKernelGGL(apply_kernel, dim3(max_pairs, ceil_div(max_tiles, APPLY_TPW), nm), dim3(256), 0, s, d,
+                         step);
       timer_end("svd.apply", apply_flops, apply_bytes, s);
     }
     TNA_LAUNCHED("svd.sweep");
