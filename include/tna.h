@@ -66,6 +66,17 @@ const char *tna_last_error(void);
  * {name, count, ms, flops, bytes} (flops and bytes: the algorithmic amounts
  * the launch sites declare, summed over launches) into out (cap bytes) and
  * clears the counters if reset != 0. */
+/* Caller-owned scratch.  tna_workspace_size: device bytes one call needs, for
+ * op "heff_apply" with dims {chi_l, chi_r, d, D, prec} or "svd_truncate" with dims
+ * {m, n, dtype, batch} (batch 1 for tna_svd_truncate).  tna_set_workspace: from
+ * then on tna_heff_apply and tna_svd_truncate(_batched) on ctx take their scratch
+ * from [dev_ptr, dev_ptr + bytes) (caller-owned device memory, e.g. a torch uint8
+ * tensor) instead of context-owned buffers; a call needing more returns
+ * TNA_ERR_NOMEM and launches nothing.  NULL (or 0 bytes) returns to context-owned
+ * scratch.  The workspace must stay valid while calls on ctx are in flight; calls on
+ * one ctx share it (they are ordered on the ctx stream).  Waits for the ctx stream. */
+tna_status tna_workspace_size(tna_ctx ctx, const char *op, const int64_t *dims, size_t *bytes);
+tna_status tna_set_workspace(tna_ctx ctx, void *dev_ptr, size_t bytes);
 tna_status tna_set_timing(tna_ctx ctx, int enable, const char *prefix);
 tna_status tna_kernel_stats(tna_ctx ctx, char *out, size_t cap, int reset);
 
@@ -181,6 +192,15 @@ tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid);
 /* Copies the MPS packed site after site into A_host (capacity given in
  * doubles); *count receives the number of doubles.  Synchronises. */
 tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t *count);
+/* Checkpoint / resume: writes the MPO, controller parameters and options, bond
+ * dimensions, site tensors, per-bond controller states (Alg. 2 state) and the
+ * scheduler history to `path` (binary, this library's own format); load recreates
+ * the run on ctx from them (right-canonicalisation and environments as in
+ * tna_dmrg_create) and restores the controller state, so the next sweep continues
+ * the saved run.  A learned scheduler is not saved (attach it again).  Errors:
+ * TNA_ERR_ARG on a file that cannot be opened, is not a checkpoint or is truncated. */
+tna_status tna_dmrg_save(tna_dmrg dm, const char *path);
+tna_status tna_dmrg_load(tna_ctx ctx, const char *path, tna_dmrg *out);
 void tna_dmrg_destroy(tna_dmrg dm);
 
 /* ---------------------------------------------------------------- many chains */

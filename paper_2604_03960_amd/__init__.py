@@ -96,6 +96,10 @@ _SIGS = {
     "tna_dmrg_get_state": ([_vp, _ip, C.POINTER(PidState)], C.c_int),
     "tna_dmrg_get_mps": ([_vp, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "tna_dmrg_destroy": ([_vp], None),
+    "tna_dmrg_save": ([_vp, C.c_char_p], C.c_int),
+    "tna_dmrg_load": ([_vp, C.c_char_p, C.POINTER(C.c_void_p)], C.c_int),
+    "tna_workspace_size": ([_vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)], C.c_int),
+    "tna_set_workspace": ([_vp, _vp, C.c_size_t], C.c_int),
     "tna_mlp_create": ([_vp, _vp, C.POINTER(C.c_void_p)], C.c_int),
     "tna_mlp_set_normalization": ([_vp, _vp, _vp], C.c_int),
     "tna_mlp_get_params": ([_vp, _vp], C.c_int),
@@ -188,6 +192,23 @@ class Context:
 
     def synchronize(self):
         _check(_lib.tna_synchronize(self.h))
+
+    def workspace_size(self, op: str, dims) -> int:
+        """Device bytes of scratch one call needs: op "heff_apply" with dims (chi_l, chi_r, d, D, prec) or
+        "svd_truncate" with dims (m, n, dtype, batch)."""
+        arr = (C.c_int64 * 5)(*[int(x) for x in dims] + [0] * (5 - len(dims)))
+        out = C.c_size_t(0)
+        _check(_lib.tna_workspace_size(self.h, op.encode(), arr, C.byref(out)))
+        return out.value
+
+    def set_workspace(self, buf=None):
+        """Caller-owned device scratch (e.g. a torch uint8 tensor, kept alive by this object); None returns to
+        context-owned scratch."""
+        self._ws = buf
+        if buf is None:
+            _check(_lib.tna_set_workspace(self.h, None, 0))
+        else:
+            _check(_lib.tna_set_workspace(self.h, _ptr(buf), buf.numel() * buf.element_size()))
 
     def set_timing(self, enable: bool, prefix: str = ""):
         """HIP-event timing of launches whose kernel name starts with prefix."""
@@ -286,6 +307,24 @@ class Dmrg:
             d["feat"] = np.array(r.feat[:], dtype=np.float32)
             recs.append(d)
         return E.value, recs, st
+
+    def save(self, path: str):
+        """Checkpoint (MPS, MPO, controller state) to a file; see tna_dmrg_save."""
+        _check(_lib.tna_dmrg_save(self.h, path.encode()))
+
+    @classmethod
+    def load(cls, ctx: "Context", path: str) -> "Dmrg":
+        """Resume a run saved with save()."""
+        h = C.c_void_p()
+        _check(_lib.tna_dmrg_load(ctx.h, path.encode(), C.byref(h)))
+        self = cls.__new__(cls)
+        self.h, self.ctx = h, ctx
+        # N, d, D from the file header (magic, then int32 N, d, D)
+        with open(path, "rb") as f:
+            f.read(8)
+            hdr = np.frombuffer(f.read(16), dtype=np.int32)
+        self.N, self.d, self.D = int(hdr[0]), int(hdr[1]), int(hdr[2])
+        return self
 
     def set_scheduler(self, net):
         """Attach a trained Mlp (None detaches); keeps a reference for the run's lifetime."""

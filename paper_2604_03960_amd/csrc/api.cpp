@@ -524,6 +524,60 @@ tna_status tna_mpo_build(int model, int N, const double *p, double *W, int *D_ou
   return TNA_OK;
 }
 
+// Scratch of one call: with a caller workspace set, each buffer becomes a view into it
+// (256-byte aligned, in list order); otherwise the context's own buffers grow as needed.
+typedef std::vector<std::pair<DevBuf *, size_t>> ScratchList;
+static size_t scratch_bytes(const ScratchList &l) {
+  size_t off = 0;
+  for (auto &e : l) off = ((off + 255) & ~(size_t)255) + e.second;
+  return off;
+}
+static tna_status bind_scratch(tna_ctx c, const ScratchList &l) {
+  if (c->ws) {
+    const size_t need = scratch_bytes(l);
+    if (need > c->ws_bytes) {
+      set_error("workspace too small: this call needs " + std::to_string(need) + " bytes");
+      return TNA_ERR_NOMEM;
+    }
+    size_t off = 0;
+    for (auto &e : l) {
+      off = (off + 255) & ~(size_t)255;
+      e.first->release();
+      e.first->ptr = static_cast<char *>(c->ws) + off;
+      e.first->bytes = e.second;
+      e.first->borrowed = true;
+      off += e.second;
+    }
+    return TNA_OK;
+  }
+  for (auto &e : l) {
+    if (e.first->borrowed) e.first->release();
+    TNA_TRY(e.first->ensure(e.second));
+  }
+  return TNA_OK;
+}
+
+static ScratchList heff_scratch(tna_ctx c, int chi_l, int chi_r, int d, int D, int prec) {
+  const int64_t nx = (int64_t)D * d * d * chi_l * chi_r;
+  const size_t el = prec == TNA_HEFF_F64 ? sizeof(double) : sizeof(float);
+  ScratchList l{{&c->x, el * nx}, {&c->z, el * nx}, {&c->m12, sizeof(double) * 32 * 32}};
+  if (prec != TNA_HEFF_F64) {
+    l.push_back({&c->lf, sizeof(float) * (size_t)chi_l * D * chi_l});
+    l.push_back({&c->rf, sizeof(float) * (size_t)chi_r * D * chi_r});
+  }
+  return l;
+}
+
+static tna_status svd_scratch(tna_ctx c, int batch, int m, int n, int dtype, ScratchList *out, SvdMat *proto) {
+  TNA_TRY(svd_plan_mat(m, n, dtype, batch, proto));
+  const size_t nd = svd_work_doubles(*proto), ni = svd_work_ints(*proto);
+  *out = ScratchList{{&c->svd.work_d, sizeof(double) * nd * batch},
+                     {&c->svd.work_i, sizeof(int) * ni * batch},
+                     {&c->spec, sizeof(double) * 24 * batch},
+                     {&c->svd.desc, sizeof(SvdMat) * batch}};
+  return TNA_OK;
+}
+
 tna_status tna_heff_apply(tna_ctx c, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
                           const double *W2, const double *R, const double *theta, double *out, int prec) {
   if (!c || !L || !W1 || !W2 || !R || !theta || !out) {
@@ -547,17 +601,11 @@ tna_status tna_heff_apply(tna_ctx c, int chi_l, int chi_r, int d, int D, const d
     return TNA_ERR_UNSUPPORTED;
   }
   hipStream_t s = c->stream;
-  const int64_t nx = (int64_t)D * d * d * chi_l * chi_r;
-  const size_t el = prec == TNA_HEFF_F64 ? sizeof(double) : sizeof(float);
-  TNA_TRY(c->x.ensure(el * nx));
-  TNA_TRY(c->z.ensure(el * nx));
-  TNA_TRY(c->m12.ensure(sizeof(double) * 32 * 32));
+  TNA_TRY(bind_scratch(c, heff_scratch(c, chi_l, chi_r, d, D, prec)));
   TNA_TRY(build_mix_matrix(0, d, D, W1, W2, c->m12.as<double>(), s));
   HeffOp op{chi_l, chi_r, d, D, L, R, c->m12.as<double>(), c->x.ptr, c->z.ptr, prec};
   if (prec != TNA_HEFF_F64) {
     const int64_t nl = (int64_t)chi_l * D * chi_l, nr = (int64_t)chi_r * D * chi_r;
-    TNA_TRY(c->lf.ensure(sizeof(float) * nl));
-    TNA_TRY(c->rf.ensure(sizeof(float) * nr));
     TNA_TRY(convert_f64_f32(L, c->lf.as<float>(), nl, s));
     TNA_TRY(convert_f64_f32(R, c->rf.as<float>(), nr, s));
     op.L = c->lf.ptr;
@@ -582,12 +630,11 @@ static tna_status svd_common(tna_ctx c, int batch, int m, int n, int dtype, cons
     return TNA_ERR_ARG;
   }
   SvdMat proto;
-  TNA_TRY(svd_plan_mat(m, n, dtype, batch, &proto));
+  ScratchList scr;
+  TNA_TRY(svd_scratch(c, batch, m, n, dtype, &scr, &proto));
+  TNA_TRY(bind_scratch(c, scr));
   const int k = std::min(chi_keep, proto.R);
   const size_t nd = svd_work_doubles(proto), ni = svd_work_ints(proto);
-  TNA_TRY(c->svd.work_d.ensure(sizeof(double) * nd * batch));
-  TNA_TRY(c->svd.work_i.ensure(sizeof(int) * ni * batch));
-  TNA_TRY(c->spec.ensure(sizeof(double) * 24 * batch));
   const size_t el = dtype == TNA_F64 ? sizeof(double) : sizeof(float);
   std::vector<SvdMat> mats(batch, proto);
   for (int z = 0; z < batch; ++z) {
@@ -627,6 +674,39 @@ tna_status tna_svd_truncate_batched(tna_ctx c, int batch, int m, int n, int dtyp
                                     int64_t strideVt, double *spec, int *sweeps_out) {
   return svd_common(c, batch, m, n, dtype, A, strideA, chi_keep, S, strideS, U, strideU, Vt, strideVt, spec,
                     nullptr, sweeps_out);
+}
+
+tna_status tna_workspace_size(tna_ctx c, const char *op, const int64_t *dims, size_t *bytes) {
+  if (!c || !op || !dims || !bytes) {
+    set_error("workspace_size: null argument");
+    return TNA_ERR_ARG;
+  }
+  if (std::strcmp(op, "heff_apply") == 0) {
+    *bytes = scratch_bytes(heff_scratch(c, (int)dims[0], (int)dims[1], (int)dims[2], (int)dims[3], (int)dims[4]));
+    return TNA_OK;
+  }
+  if (std::strcmp(op, "svd_truncate") == 0) {
+    ScratchList l;
+    SvdMat proto;
+    TNA_TRY(svd_scratch(c, dims[3] > 0 ? (int)dims[3] : 1, (int)dims[0], (int)dims[1], (int)dims[2], &l, &proto));
+    *bytes = scratch_bytes(l);
+    return TNA_OK;
+  }
+  set_error(std::string("workspace_size: unknown op ") + op);
+  return TNA_ERR_ARG;
+}
+
+tna_status tna_set_workspace(tna_ctx c, void *dev_ptr, size_t bytes) {
+  if (!c) {
+    set_error("set_workspace: null context");
+    return TNA_ERR_ARG;
+  }
+  TNA_HIP(hipStreamSynchronize(c->stream));  // calls in flight may still use the previous scratch
+  for (DevBuf *b : {&c->x, &c->z, &c->lf, &c->rf, &c->m12, &c->spec, &c->svd.work_d, &c->svd.work_i, &c->svd.desc})
+    if (b->borrowed) b->release();
+  c->ws = (dev_ptr && bytes) ? dev_ptr : nullptr;
+  c->ws_bytes = c->ws ? bytes : 0;
+  return TNA_OK;
 }
 
 tna_status tna_pid_chi_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next,

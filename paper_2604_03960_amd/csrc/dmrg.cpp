@@ -12,6 +12,9 @@
 #include <memory>
 #include <vector>
 
+#include <cstdint>
+#include <cstdio>
+#include <string>
 #include "internal.h"
 
 using namespace tna;
@@ -245,6 +248,108 @@ tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t
     TNA_HIP(hipMemcpy(A_host + off, dm->A[i].ptr, sizeof(double) * n, hipMemcpyDeviceToHost));
     off += n;
   }
+  return TNA_OK;
+}
+
+// Checkpoint: magic, sizes, MPO, controller parameters and options, bond dimensions,
+// site tensors, per-bond controller states and scheduler history, sweeps done.  Loading
+// recreates the run from the saved MPS (canonicalisation and environments as at create),
+// then restores the controller and scheduler state, so a resumed run continues the same
+// controller trajectory.
+static const char kMagic[8] = {'T', 'N', 'A', 'D', 'M', 'R', 'G', '1'};
+
+tna_status tna_dmrg_save(tna_dmrg dm, const char *path) {
+  if (!dm || !path) {
+    set_error("dmrg_save: null argument");
+    return TNA_ERR_ARG;
+  }
+  size_t count = 0;
+  TNA_TRY(tna_dmrg_get_mps(dm, nullptr, 0, &count));
+  std::vector<double> A(count);
+  TNA_TRY(tna_dmrg_get_mps(dm, A.data(), count, &count));
+  const int N = dm->N, d = dm->d, D = dm->D;
+  const size_t wsz = (size_t)D * D * d * d * N;
+  std::vector<double> W(wsz);
+  TNA_HIP(hipMemcpy(W.data(), dm->W.ptr, sizeof(double) * wsz, hipMemcpyDeviceToHost));
+  FILE *f = std::fopen(path, "wb");
+  if (!f) {
+    set_error(std::string("dmrg_save: cannot open ") + path);
+    return TNA_ERR_ARG;
+  }
+  const int32_t head[4] = {N, d, D, dm->sweeps_done};
+  const uint64_t na = count;
+  bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(head, sizeof(head), 1, f) == 1 &&
+            std::fwrite(&na, sizeof(na), 1, f) == 1 && std::fwrite(W.data(), sizeof(double), wsz, f) == wsz &&
+            std::fwrite(&dm->pid, sizeof(dm->pid), 1, f) == 1 && std::fwrite(&dm->opts, sizeof(dm->opts), 1, f) == 1 &&
+            std::fwrite(dm->chi.data(), sizeof(int), N - 1, f) == (size_t)(N - 1) &&
+            std::fwrite(A.data(), sizeof(double), count, f) == count &&
+            std::fwrite(dm->st.data(), sizeof(tna_pid_state), N - 1, f) == (size_t)(N - 1) &&
+            std::fwrite(dm->hist.data(), sizeof(double) * 8, N - 1, f) == (size_t)(N - 1) &&
+            std::fwrite(dm->nhist.data(), sizeof(int), N - 1, f) == (size_t)(N - 1) &&
+            std::fwrite(dm->pred.data(), sizeof(int), N - 1, f) == (size_t)(N - 1);
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) {
+    set_error(std::string("dmrg_save: write failed on ") + path);
+    return TNA_ERR_ARG;
+  }
+  return TNA_OK;
+}
+
+tna_status tna_dmrg_load(tna_ctx ctx, const char *path, tna_dmrg *out) {
+  if (!ctx || !path || !out) {
+    set_error("dmrg_load: null argument");
+    return TNA_ERR_ARG;
+  }
+  FILE *f = std::fopen(path, "rb");
+  if (!f) {
+    set_error(std::string("dmrg_load: cannot open ") + path);
+    return TNA_ERR_ARG;
+  }
+  auto fail = [&](const char *what) {
+    std::fclose(f);
+    set_error(std::string("dmrg_load: ") + what + " in " + path);
+    return TNA_ERR_ARG;
+  };
+  char magic[8];
+  int32_t head[4];
+  uint64_t na = 0;
+  if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, kMagic, 8) != 0) return fail("not a checkpoint");
+  if (std::fread(head, sizeof(head), 1, f) != 1 || std::fread(&na, sizeof(na), 1, f) != 1) return fail("short header");
+  const int N = head[0], d = head[1], D = head[2];
+  if (N < 2 || N > 100000 || d < 1 || d > 16 || D < 1 || D > 64 || na > ((uint64_t)1 << 40)) return fail("bad sizes");
+  const size_t wsz = (size_t)D * D * d * d * N;
+  std::vector<double> W(wsz), A(na);
+  tna_pid_params pid;
+  tna_dmrg_opts opts;
+  std::vector<int> chi(N - 1), nhist(N - 1), pred(N - 1);
+  std::vector<tna_pid_state> st(N - 1);
+  std::vector<std::array<double, 8>> hist(N - 1);
+  if (std::fread(W.data(), sizeof(double), wsz, f) != wsz || std::fread(&pid, sizeof(pid), 1, f) != 1 ||
+      std::fread(&opts, sizeof(opts), 1, f) != 1 || std::fread(chi.data(), sizeof(int), N - 1, f) != (size_t)(N - 1) ||
+      std::fread(A.data(), sizeof(double), na, f) != na ||
+      std::fread(st.data(), sizeof(tna_pid_state), N - 1, f) != (size_t)(N - 1) ||
+      std::fread(hist.data(), sizeof(double) * 8, N - 1, f) != (size_t)(N - 1) ||
+      std::fread(nhist.data(), sizeof(int), N - 1, f) != (size_t)(N - 1) ||
+      std::fread(pred.data(), sizeof(int), N - 1, f) != (size_t)(N - 1))
+    return fail("truncated file");
+  std::fclose(f);
+  size_t need = 0;
+  for (int i = 0; i < N; ++i) {
+    const size_t cl = i == 0 ? 1 : chi[i - 1], cr = i == N - 1 ? 1 : chi[i];
+    need += cl * d * cr;
+  }
+  if (need != na) {
+    set_error(std::string("dmrg_load: site tensors do not match the bond dimensions in ") + path);
+    return TNA_ERR_ARG;
+  }
+  tna_dmrg dm = nullptr;
+  TNA_TRY(tna_dmrg_create(ctx, N, d, D, W.data(), A.data(), chi.data(), &pid, &opts, &dm));
+  dm->st = st;
+  dm->hist = hist;
+  dm->nhist = nhist;
+  dm->pred = pred;
+  dm->sweeps_done = head[3];
+  *out = dm;
   return TNA_OK;
 }
 

@@ -56,6 +56,7 @@ void timer_add_work(const char *name, double flops, double bytes);
 struct DevBuf {
   void *ptr = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // a view into a caller-owned workspace: never freed or grown here
   tna_status ensure(size_t need);
   void release();
   template <class T> T *as() const { return static_cast<T *>(ptr); }
@@ -263,6 +264,8 @@ struct tna_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int timing = 0;
+  void *ws = nullptr;  // caller-owned device workspace (tna_set_workspace), or null
+  size_t ws_bytes = 0;
   tna::DevBuf x, z, lf, rf, m12, part, misc, spec;
   tna::SvdGroup svd;
   int *host_ctr = nullptr;     // pinned

@@ -27,6 +27,10 @@ namespace tna {
 
 tna_status DevBuf::ensure(size_t need) {
   if (need <= bytes) return TNA_OK;
+  if (borrowed) {
+    set_error("workspace too small for this call");
+    return TNA_ERR_NOMEM;
+  }
   release();
   size_t want = need + need / 4;
   if (hipMalloc(&ptr, want) != hipSuccess) {
@@ -40,9 +44,10 @@ tna_status DevBuf::ensure(size_t need) {
 }
 
 void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr && !borrowed) (void)hipFree(ptr);
   ptr = nullptr;
   bytes = 0;
+  borrowed = false;
 }
 
 namespace {
