@@ -198,7 +198,11 @@ def run_svd(a):
     ctx = tna.Context(0)
     n, B = a.svd_n, a.svd_batch
     dt = torch.float64 if a.svd_dtype == "f64" else torch.float32
-    A = torch.stack([torch.from_numpy(synth.svd_test_matrix(n, a.svd_tau, seed=0, index=i)) for i in range(B)])
+    mats = []
+    for i in range(B):
+        mats.append(torch.from_numpy(synth.svd_test_matrix(n, a.svd_tau, seed=0, index=i)))
+        progress(f"input matrix {i + 1}/{B} generated")
+    A = torch.stack(mats)
     A = A.to(dt).cuda().contiguous()
     sig = torch.from_numpy(synth.svd_test_spectrum(n, a.svd_tau)).cuda()
     run = (lambda: ctx.svd_truncate(A[0], n // 2)) if B == 1 else (lambda: ctx.svd_truncate_batched(A, n // 2))
