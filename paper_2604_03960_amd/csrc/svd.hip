@@ -174,7 +174,8 @@ struct EigLds {
   int pi[32], pj[32];
   int rot_any, need;
   int slot_of[64];
-  int vs[64];  // valid slots in order
+  int vs[64];                   // valid slots in order
+  unsigned short sched[63][32]; // round-robin pairs (i | j << 8) of one sweep
 };
 
 // Rows whose squared norm is at or below row_floor2 = (0.1 eps C)^2 |A|_F^2 are at the
@@ -212,34 +213,42 @@ __device__ inline bool eig_needs_rotation(EigLds &L, double tol, double floor2) 
 // Q <- Q J over sweeps of a round-robin ordering of the nv valid slots (np of block p at
 // 0.., nq of block q at 32..) until a sweep rotates nothing (or inner_max sweeps); the
 // diagonal of G ends as the eigenvalues.  With nv odd a dummy index sits out each round.
+// The slot pairs of every round are tabulated in LDS once per call.
 template <int NTE>
 __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np, int nq) {
   const int tid = threadIdx.x;
   const int nv = np + nq, nvp = nv + (nv & 1), P = nvp / 2;
   if (tid < 64) L.vs[tid] = tid < np ? tid : 32 + (tid - np);  // entries >= nv unused
+  __syncthreads();
+  // pair table: (i, j) with i <= j; a pair with the dummy becomes (x, x) and rotates nothing,
+  // but its row still takes the partner pairs' column rotations
+  for (int e = tid; e < (nvp - 1) * P; e += NTE) {
+    const int rr = e / P, t = e - rr * P;
+    int ia, ib;
+    if (t == 0) { ia = rr % (nvp - 1); ib = nvp - 1; }
+    else { ia = (rr + t) % (nvp - 1); ib = (rr - t + nvp - 1) % (nvp - 1); }
+    int i = ia < nv ? L.vs[ia] : -1, j = ib < nv ? L.vs[ib] : -1;
+    if (i < 0) i = j;
+    if (j < 0) j = i;
+    L.sched[rr][t] = (unsigned short)((i < j ? i : j) | ((i < j ? j : i) << 8));
+  }
   const double tol_in = 4.0 * EPS53;
   for (int sweep = 0; sweep < inner_max; ++sweep) {
-    __syncthreads();  // every thread has read rot_any of the previous sweep (and vs is set)
+    __syncthreads();  // every thread has read rot_any of the previous sweep (and the table is set)
     if (tid == 0) L.rot_any = 0;
     __syncthreads();
     for (int rr = 0; rr < nvp - 1; ++rr) {
-      // P disjoint pairs; rotation J = [[c, s], [-s, c]] on (i, j), i < j; a pair with
-      // the dummy becomes (x, x) with the identity, so its rows still take the partner's
-      // column rotations below
+      // rotation J = [[c, s], [-s, c]] on (i, j), i < j, zeroing g_ij:
+      // t = sign(d) 2 g_ij / (|d| + sqrt(d^2 + 4 g_ij^2)), d = g_jj - g_ii; c = 1 / sqrt(1 + t^2)
       if (tid < P) {
-        int ia, ib;
-        if (tid == 0) { ia = rr % (nvp - 1); ib = nvp - 1; }
-        else { ia = (rr + tid) % (nvp - 1); ib = (rr - tid + nvp - 1) % (nvp - 1); }
-        int i = ia < nv ? L.vs[ia] : -1, j = ib < nv ? L.vs[ib] : -1;
-        if (i < 0) i = j;
-        if (j < 0) j = i;
-        if (i > j) { const int t = i; i = j; j = t; }
+        const unsigned pr = L.sched[rr][tid];
+        const int i = pr & 0xff, j = pr >> 8;
         double c = 1.0, s = 0.0;
         if (i != j) {
           const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
           if (gii > floor2 && gjj > floor2 && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
-            const double zeta = (gjj - gii) / (2.0 * gij);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double dl = gjj - gii;
+            const double t = (dl >= 0.0 ? 2.0 : -2.0) * gij / (fabs(dl) + sqrt(dl * dl + 4.0 * gij * gij));
             c = 1.0 / sqrt(1.0 + t * t);
             s = c * t;
             L.rot_any = 1;
@@ -281,16 +290,23 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
           L.G[b0][a0] = z00; L.G[b1][a0] = z01; L.G[b0][a1] = z10; L.G[b1][a1] = z11;
         }
       }
-      // Q <- Q J over the valid rows
-      for (int e = tid; e < P * nv; e += NTE) {
-        const int u = e / nv, k = L.vs[e - u * nv];
-        const double su = L.sn[u];
-        if (su != 0.0) {
-          const double cu = L.cs[u];
-          const int i = L.pi[u], j = L.pj[u];
-          const double qi_ = L.Q[k][i], qj_ = L.Q[k][j];
-          L.Q[k][i] = cu * qi_ - su * qj_;
-          L.Q[k][j] = su * qi_ + cu * qj_;
+      // Q <- Q J over the valid rows: a pair's rotation read once per thread, NTE / 32 threads
+      // per pair walking the rows
+      {
+        constexpr int TPP = NTE / 32;
+        const int u = tid / TPP, r0 = tid - u * TPP;
+        if (u < P) {
+          const double su = L.sn[u];
+          if (su != 0.0) {
+            const double cu = L.cs[u];
+            const int i = L.pi[u], j = L.pj[u];
+            for (int kk = r0; kk < nv; kk += TPP) {
+              const int k = L.vs[kk];
+              const double qi_ = L.Q[k][i], qj_ = L.Q[k][j];
+              L.Q[k][i] = cu * qi_ - su * qj_;
+              L.Q[k][j] = su * qi_ + cu * qj_;
+            }
+          }
         }
       }
       __syncthreads();
