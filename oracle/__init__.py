@@ -70,6 +70,8 @@ def lib():
         _lib.or_spectrum.restype = None
         _lib.or_pid_update.argtypes = [C.POINTER(PidParams), C.POINTER(PidState), C.c_double, ip, dp]
         _lib.or_heff_apply.argtypes = [C.c_int] * 4 + [dp] * 6
+        _lib.or_heff_element.argtypes = [C.c_int] * 4 + [dp] * 5 + [C.c_int] * 4
+        _lib.or_heff_element.restype = C.c_double
         _lib.or_env_left.argtypes = [C.c_int] * 4 + [dp] * 4
         _lib.or_env_right.argtypes = [C.c_int] * 4 + [dp] * 4
         _lib.or_lanczos_heff.argtypes = [C.c_int] * 4 + [dp] * 5 + [C.c_double, C.c_int, C.c_int, C.c_int, dp, ip]
@@ -182,6 +184,16 @@ def heff_apply(L, W1, W2, R, theta):
     lib().or_heff_apply(chl, chr_, d, D, _p(_f64(L)), _p(_f64(W1)), _p(_f64(W2)), _p(_f64(R)),
                         _p(_f64(theta)), _p(out))
     return out
+
+
+def heff_element(L, W1, W2, R, theta, idx):
+    """One element (a, s, t, c) of H_eff theta from the definition (for large chi)."""
+    chl, D, _ = L.shape
+    chr_ = R.shape[0]
+    d = W1.shape[2]
+    a, s, t, c = (int(x) for x in idx)
+    return lib().or_heff_element(chl, chr_, d, D, _p(_f64(L)), _p(_f64(W1)), _p(_f64(W2)), _p(_f64(R)),
+                                 _p(_f64(theta)), a, s, t, c)
 
 
 def env_left(L, W, A):

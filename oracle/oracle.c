@@ -458,6 +458,46 @@ int or_pid_update(const or_pid_params *pp, or_pid_state *st, double s_raw, int *
 }
 
 /* ------------------------------------------------------------------------ */
+/* One element out[a][s][t][c] of H_eff theta (Eq. 18), straight from the     */
+/* definition: the left block first (sum over a'), then the right block       */
+/* (sum over c'), then the two MPO tensors.  For sizes whose full product is  */
+/* too slow here; the result must equal or_heff_apply's element.              */
+/* ------------------------------------------------------------------------ */
+double or_heff_element(int chl, int chr, int d, int D, const double *L, const double *W1, const double *W2,
+                       const double *R, const double *th, int a, int s, int t, int c) {
+  const size_t nq = (size_t)D * d * d * chr;
+  double *T1 = dalloc(nq);                 /* T1[w][s'][t'][c'] = sum_a' L[a][w][a'] th[a'][s'][t'][c'] */
+  for (int w = 0; w < D; ++w)
+    for (size_t q = 0; q < (size_t)d * d * chr; ++q) {
+      double acc = 0.0;
+      for (int ap = 0; ap < chl; ++ap)
+        acc += L[((size_t)a * D + w) * chl + ap] * th[(size_t)ap * d * d * chr + q];
+      T1[(size_t)w * d * d * chr + q] = acc;
+    }
+  double *T2 = dalloc((size_t)D * D * d * d); /* T2[w][w''][s'][t'] = sum_c' R[c][w''][c'] T1[w][s'][t'][c'] */
+  for (int w = 0; w < D; ++w)
+    for (int wq = 0; wq < D; ++wq)
+      for (int sp = 0; sp < d; ++sp)
+        for (int tp = 0; tp < d; ++tp) {
+          double acc = 0.0;
+          for (int cp = 0; cp < chr; ++cp)
+            acc += R[((size_t)c * D + wq) * chr + cp] * T1[(((size_t)w * d + sp) * d + tp) * chr + cp];
+          T2[(((size_t)w * D + wq) * d + sp) * d + tp] = acc;
+        }
+  double out = 0.0;                         /* sum W1[w][w'][s][s'] W2[w'][w''][t][t'] T2[w][w''][s'][t'] */
+  for (int w = 0; w < D; ++w)
+    for (int wp = 0; wp < D; ++wp)
+      for (int wq = 0; wq < D; ++wq)
+        for (int sp = 0; sp < d; ++sp)
+          for (int tp = 0; tp < d; ++tp)
+            out += W1[(((size_t)w * D + wp) * d + s) * d + sp] * W2[(((size_t)wp * D + wq) * d + t) * d + tp] *
+                   T2[(((size_t)w * D + wq) * d + sp) * d + tp];
+  free(T1);
+  free(T2);
+  return out;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Two-site effective Hamiltonian applied to theta (Eq. 18), contracted in   */
 /* the textbook order: L, then W_b, then W_{b+1}, then R.                     */
 /* out[a][s][t][c] = sum L[a][w][a'] W1[w][w'][s][s'] W2[w'][w''][t][t']      */

@@ -47,3 +47,27 @@ def test_heff_rejects_alias_and_bad_dims():
     with pytest.raises(tna.TnaError) as e:
         c.heff_apply(to_dev(L), to_dev(W[1]), to_dev(W[2]), to_dev(R), t, out=t)
     assert e.value.status == tna.TNA_ERR_ARG
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_heff_chi1024_sampled_against_oracle(prec, tol):
+    """chi_l = chi_r = 1024 (the c2 throughput shape): 24 sampled output elements against the oracle's
+    element-by-element definition; tolerance relative to the RMS of the output."""
+    import torch
+
+    import paper_2604_03960_amd as tna
+    rng = np.random.default_rng(1024)
+    chi, d, D = 1024, 2, 5
+    W = oracle.mpo(oracle.MODEL_XXZ, 8, [1.0, 1.0, 0.0])
+    L = rng.standard_normal((chi, D, chi)) / chi
+    R = rng.standard_normal((chi, D, chi)) / chi
+    th = rng.standard_normal((chi, d, d, chi))
+    c = tna.Context(0)
+    out = c.heff_apply(*(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (L, W[3], W[4], R, th)),
+                       prec=prec).cpu().numpy()
+    rms = np.sqrt(np.mean(out ** 2))
+    picks = [tuple(int(v) for v in (rng.integers(chi), rng.integers(d), rng.integers(d), rng.integers(chi)))
+             for _ in range(22)] + [(0, 0, 0, 0), (chi - 1, d - 1, d - 1, chi - 1)]
+    for idx in picks:
+        ref = oracle.heff_element(L, W[3], W[4], R, th, idx)
+        assert abs(out[idx] - ref) <= tol * rms, (idx, out[idx], ref)

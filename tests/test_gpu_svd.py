@@ -97,3 +97,23 @@ def test_svd_f32_input():
     So = oracle.svd(A32.astype(np.float64))[0]
     assert U.dtype == torch.float32
     assert np.abs(S.cpu().numpy() - So).max() <= 1e-12 * So[0]
+
+
+def test_prescribed_spectrum_chi1024_closed_form():
+    """2048 x 2048 (chi = 1024, the QR-started blocked path): sigma against the closed form exp(-k/64),
+    the kept factors orthonormal and reconstructing the kept part."""
+    import torch
+    n, tau, k = 2048, 64.0, 1024
+    A = synth.svd_test_matrix(n, tau, seed=0)
+    c = ctx()
+    S, U, Vt, spec, kk, sw, st = c.svd_truncate(torch.from_numpy(A).cuda(), k)
+    sig = synth.svd_test_spectrum(n, tau)
+    assert st == 0 and kk == k
+    assert np.abs(S.cpu().numpy() - sig).max() <= 64 * n * EPS
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    assert (U.T @ U - eye).abs().max().item() <= 64 * n * EPS
+    assert (Vt @ Vt.T - eye).abs().max().item() <= 64 * n * EPS
+    # (U S_k) Vt equals A minus its discarded part: project A onto the kept left vectors
+    Ad = torch.from_numpy(A).cuda()
+    rec = (U * S[:k]) @ Vt
+    assert (rec - U @ (U.T @ Ad)).abs().max().item() <= 64 * n * EPS

@@ -107,3 +107,17 @@ def test_sym_eig_jacobi_against_numpy():
     assert rc == 0
     assert np.abs(np.sort(w) - np.linalg.eigvalsh(A)).max() <= 1e-13 * np.abs(w).max()
     assert np.abs(V.T @ V - np.eye(30)).max() <= 1e-14
+
+
+def test_heff_element_equals_full_product():
+    """The one-element form used for large-chi spot checks agrees with the full contraction (itself pinned
+    against P^T H P above) on every element of a small random case."""
+    rng = np.random.default_rng(3)
+    chl, chr_, d, D = 7, 5, 2, 5
+    W = oracle.mpo(oracle.MODEL_XXZ, 6, [1.0, 0.8, 0.0])
+    L = rng.standard_normal((chl, D, chl))
+    R = rng.standard_normal((chr_, D, chr_))
+    th = rng.standard_normal((chl, d, d, chr_))
+    full = oracle.heff_apply(L, W[2], W[3], R, th)
+    for idx in np.ndindex(full.shape):
+        assert abs(oracle.heff_element(L, W[2], W[3], R, th, idx) - full[idx]) <= 1e-13 * np.abs(full).max()
