@@ -38,10 +38,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--roofline-kernel", default="", help="kernel-name prefix to time (default: auto)")
-    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd", "fixed_chi"], default="heisenberg100")
+    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd", "fixed_chi", "scheduler"],
+                    default="heisenberg100")
     ap.add_argument("--chi", type=int, default=256, help="fixed_chi: bond dimension")
     ap.add_argument("--matvecs", type=int, default=20, help="fixed_chi: H_eff applications per visit")
     ap.add_argument("--chains", type=int, default=64)
+    ap.add_argument("--sites", type=int, default=200, help="scheduler: chain length")
+    ap.add_argument("--chi-max", type=int, default=1024, help="scheduler: upper bond dimension")
+    ap.add_argument("--compare-serial", action="store_true", help="xxz_batch: also run the chains one by one")
     ap.add_argument("--svd-batch", type=int, default=1)
     ap.add_argument("--svd-dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--svd-tau", type=float, default=64.0)
@@ -135,13 +139,33 @@ def run_batch(a):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     Ns = np.array([N for _, N in chains])
+    serial = None
+    if a.compare_serial:
+        # the same chains, one at a time through the single-chain driver, same sweeps
+        t_ser, dE = 0.0, []
+        for i, (dlt, N) in enumerate(chains):
+            dm = tna.Dmrg(ctx, Ws[i], As[i], chis[i], pid, heff_prec=prec)
+            for _ in range(a.warmup):
+                dm.sweep()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(a.steps):
+                Es, _, _ = dm.sweep()
+            torch.cuda.synchronize()
+            t_ser += time.perf_counter() - ts
+            dE.append(abs(Es - E[i]) / N)
+            dm.close()
+            progress(f"serial chain {i + 1}/{len(chains)} done")
+        serial = {"chain_sweeps_per_s": a.chains * a.steps / t_ser, "speedup_batched": (t_ser / (t1 - t0)),
+                  "max_dE_per_site_vs_batched": float(max(dE)), "note": "Delta > 1 chains may settle on a "
+                  "different quasi-degenerate Neel state; compare energies"}
     out = {"metric": "chain-sweeps/s (64 XXZ chains swept together)", "value": a.chains * a.steps / (t1 - t0),
            "unit": "chain-sweeps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": 1e3 * (t1 - t0) / a.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32-heff+f64", "data": "synthetic",
            "config": {"workload": f"xxz_batch{a.chains}_N32-128_chi8-256", "chains": a.chains,
                       "N_total_sites": int(Ns.sum())},
-           "batch_stats": stats, "E_per_site": (E / Ns).tolist()[:8]}
+           "batch_stats": stats, "E_per_site": (E / Ns).tolist()[:8], "serial": serial}
     print(json.dumps(out))
 
 
@@ -185,6 +209,63 @@ def run_fixed_chi(a):
            "heff_gemm_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
            "roofline": roofline_from(stats, dom) if dom else None,
            "phase_ms": {"lanczos": sum(r["ms_lanczos"] for r in recs), "svd": sum(r["ms_svd"] for r in recs)}}
+    print(json.dumps(out))
+
+
+def run_scheduler(a):
+    """Learned bond-dimension scheduler vs the PID alone (J1-J2, J2 = 0.241, N = 200, D = 8, chi 16..1024,
+    target 1e-8, 10 sweeps).  The network is trained on the per-visit records of PID-only Heisenberg and XXZ
+    runs (the method's own sweeps), on the device."""
+    import numpy as np
+    import torch
+
+    import paper_2604_03960_amd as tna
+    from paper_2604_03960_amd import scheduler
+    import synth
+    ctx = tna.Context(0)
+    chi_min, chi_max, eps_t = 16, a.chi_max, 1e-8
+    pid = tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, chi_min, chi_max)
+
+    def run(model, params, N, sweeps, net=None):
+        W = tna.mpo_build(model, N, params)
+        A, chi, _ = synth.random_mps(N, 2, chi_min, seed=N + 7 * model)
+        dm = tna.Dmrg(ctx, W, A, chi, pid, eps_target=eps_t)
+        if net is not None:
+            dm.set_scheduler(net)
+        recs, E = [], None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(sweeps):
+            E, r, _ = dm.sweep()
+            recs += r
+            progress(f"model {model} N {N} sweep {i + 1}/{sweeps}")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dm.close()
+        return E, recs, dt
+
+    train_runs = []
+    for model, params, N in [(tna.MODEL_XXZ, [1.0, 1.0, 0.0], 40), (tna.MODEL_XXZ, [1.0, 0.5, 0.0], 40),
+                             (tna.MODEL_XXZ, [1.0, 1.5, 0.0], 40), (tna.MODEL_XXZ, [1.0, 0.8, 0.0], 60)]:
+        train_runs.append(run(model, params, N, 6)[1])
+    X, T = scheduler.build_dataset(train_runs, chi_min, chi_max)
+    t0 = time.perf_counter()
+    net, losses = scheduler.train(ctx, X, T, epochs=150, batch=128, lr=2e-3, seed=1)
+    t_train = time.perf_counter() - t0
+    N = a.sites
+    E_pid, r_pid, t_pid = run(tna.MODEL_J1J2, [1.0, 0.241], N, a.steps)
+    E_ml, r_ml, t_ml = run(tna.MODEL_J1J2, [1.0, 0.241], N, a.steps, net=net)
+    last = 2 * (N - 1)
+    s_pid, s_ml = scheduler.summarize(r_pid[-last:], eps_t), scheduler.summarize(r_ml[-last:], eps_t)
+    out = {"metric": f"sweeps/s, J1-J2 N={N} with the learned scheduler (PID fallback)", "value": a.steps / t_ml,
+           "unit": "sweeps/s", "n_gpus": 1, "steps": a.steps, "warmup": 0, "ms_per_step": 1e3 * t_ml / a.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32-mlp",
+           "data": "synthetic", "config": {"workload": f"j1j2_N{N}_J2_0.241_chi{chi_min}-{chi_max}_eps1e-8_learned_vs_pid",
+                                           "train_samples": int(X.shape[0]), "epochs": 150},
+           "pid_only": {"sweeps_per_s": a.steps / t_pid, "E_per_site": E_pid / N, **s_pid},
+           "learned": {"sweeps_per_s": a.steps / t_ml, "E_per_site": E_ml / N, **s_ml},
+           "dE_per_site_learned_minus_pid": (E_ml - E_pid) / N, "train_s": t_train,
+           "loss_first_last": [float(losses[0]), float(losses[-1])]}
     print(json.dumps(out))
 
 
@@ -251,6 +332,8 @@ def main():
         return run_svd(a)
     if a.workload == "fixed_chi":
         return run_fixed_chi(a)
+    if a.workload == "scheduler":
+        return run_scheduler(a)
     import numpy as np
     import torch
 

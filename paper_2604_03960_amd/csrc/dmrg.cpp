@@ -14,6 +14,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 #include "internal.h"
 
@@ -205,6 +206,9 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
   std::vector<int> slot{0}, bond{0}, half{0};
   std::vector<double> Es(1, 0.0);
   std::vector<tna_visit_log *> lg(log ? 1 : 0, nullptr);
+  // TNA_PROGRESS set: a line on stderr at most every 20 s, for long sweeps at large bond dimension
+  const bool progress = std::getenv("TNA_PROGRESS") != nullptr;
+  auto last = std::chrono::steady_clock::now();
   for (int h = 0; h < 2; ++h)
     for (int step = 0; step < N - 1; ++step) {
       bond[0] = h == 0 ? step : N - 2 - step;
@@ -212,6 +216,15 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
       if (log) lg[0] = log + h * (N - 1) + step;
       TNA_TRY(engine_step(dm->engine, cs, slot, bond, half, Es, lg, &worst));
       E = Es[0];
+      if (progress) {
+        const auto now = std::chrono::steady_clock::now();
+        if (std::chrono::duration<double>(now - last).count() > 20.0) {
+          std::fprintf(stderr, "[tna] sweep %d half %d bond %d chi %d E %.12f\n", dm->sweeps_done, h, bond[0],
+                       dm->chi[bond[0]], E);
+          std::fflush(stderr);
+          last = now;
+        }
+      }
     }
   dm->sweeps_done += 1;
   if (E_out) *E_out = E;
