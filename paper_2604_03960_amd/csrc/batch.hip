@@ -221,43 +221,123 @@ __global__ __launch_bounds__(NT) void lz_combine_kernel(const LzProb *probs) {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int NTS = 512;  // threads of the single-workgroup Lanczos (8 waves)
 
-// C(i, j) = sum_k A(i, k) B(k, j) on v_mfma_f64_16x16x4_f64, the waves of the block taking
-// 16 x 16 tiles in turn; the operands of step k + 4 are read before the MFMA of step k.
-// Operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; result D[i][j] in
-// lane j + 16 (i % 4), register i / 4.
+// One 16 x 16 output tile, C(i, j) = sum_{kb <= k < ke} A(i, k) B(k, j), on
+// v_mfma_f64_16x16x4_f64.  Operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+// result D[i][j] in lane j + 16 (i % 4), register i / 4.  Rows and columns past the matrix edge
+// read the last valid row/column (their results are discarded by the caller), so only a final
+// partial k-step needs a guard.  The operands of four k-steps are read together and fed to two
+// independent accumulator chains.
+template <class FA, class FB>
+__device__ inline v4d tile_mfma(int kb, int ke, int ia, int jb, int lk, FA a_at, FB b_at) {
+  v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+  const int k16 = kb + ((ke - kb) & ~15), k4 = kb + ((ke - kb) & ~3);
+  int k0 = kb;
+  for (; k0 < k16; k0 += 16) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = a_at(ia, k0 + 4 * u + lk);
+      bv[u] = b_at(k0 + 4 * u + lk, jb);
+    }
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], bv[2], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], bv[3], c1, 0, 0, 0);
+  }
+  for (; k0 < k4; k0 += 4) c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_at(ia, k0 + lk), b_at(k0 + lk, jb), c0, 0, 0, 0);
+  if (k0 < ke) {
+    const bool in = k0 + lk < ke;
+    const double av = in ? a_at(ia, k0 + lk) : 0.0, bv = in ? b_at(k0 + lk, jb) : 0.0;
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c1, 0, 0, 0);
+  }
+  return c0 + c1;
+}
+
+// C = A B over the whole workgroup, the waves taking 16 x 16 tiles in turn.  With no more than
+// half as many tiles as waves (and `part` holding tiles x 256 doubles within part_cap), each
+// tile's k range is split between two waves and the second half's partial sums pass through
+// `part` in LDS.
 template <class FA, class FB, class FC>
-__device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_put) {
+__device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_put, double *part = nullptr,
+                                  int part_cap = 0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = NTS / 64;
   const int lr = lane & 15, lk = lane >> 4;
   const int tn = (N + 15) >> 4, tiles = ((M + 15) >> 4) * tn;
+  if (part != nullptr && 2 * tiles <= nw && K >= 32 && tiles * 256 <= part_cap) {
+    const int kh = ((K >> 1) + 3) & ~3;
+    const bool have = wave < 2 * tiles, second = wave >= tiles;
+    const int t = second ? wave - tiles : wave;
+    const int i0 = (t / tn) << 4, j0 = (t - (t / tn) * tn) << 4;
+    const int ia = min(i0 + lr, M - 1), jb = j0 + lr, jc = min(jb, N - 1);
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    if (have) acc = tile_mfma(second ? kh : 0, second ? K : kh, ia, jc, lk, a_at, b_at);
+    if (have && second)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[(t * 64 + lane) * 4 + r] = acc[r];
+    __syncthreads();
+    if (have && !second)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 4 * r + lk;
+        if (i < M && jb < N) c_put(i, jb, acc[r] + part[(t * 64 + lane) * 4 + r]);
+      }
+    return;
+  }
   for (int t = wave; t < tiles; t += nw) {
     const int i0 = (t / tn) << 4, j0 = (t - (t / tn) * tn) << 4;
-    const int ia = i0 + lr, jb = j0 + lr;
-    const bool ra = ia < M, rb = jb < N;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    int k = lk;
-    double av = (ra && k < K) ? a_at(ia, k) : 0.0;
-    double bv = (rb && k < K) ? b_at(k, jb) : 0.0;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int kn = k + 4;
-      const double an = (ra && kn < K) ? a_at(ia, kn) : 0.0;
-      const double bn = (rb && kn < K) ? b_at(kn, jb) : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      av = an;
-      bv = bn;
-      k = kn;
-    }
+    const int ia = min(i0 + lr, M - 1), jb = j0 + lr, jc = min(jb, N - 1);
+    const v4d acc = tile_mfma(0, K, ia, jc, lk, a_at, b_at);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + 4 * r + lk;
-      if (i < M && rb) c_put(i, jb, acc[r]);
+      if (i < M && jb < N) c_put(i, jb, acc[r]);
     }
   }
 }
 
-__device__ inline double block_sum_s(double v, double *sh) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+// NB independent products C_b = A B_b (one shared A), the tiles of all products dealt to the
+// waves in turn.
+template <class FA, class FB, class FC>
+__device__ inline void block_gemm_nb(int NB, int M, int N, int K, FA a_at, FB b_at, FC c_put) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = NTS / 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tn = (N + 15) >> 4, tpb = ((M + 15) >> 4) * tn;
+  for (int t = wave; t < NB * tpb; t += nw) {
+    const int b = t / tpb, tt = t - b * tpb;
+    const int i0 = (tt / tn) << 4, j0 = (tt - (tt / tn) * tn) << 4;
+    const int ia = min(i0 + lr, M - 1), jb = j0 + lr, jc = min(jb, N - 1);
+    const v4d acc = tile_mfma(0, K, ia, jc, lk, a_at, [&](int k, int j) { return b_at(b, k, j); });
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * r + lk;
+      if (i < M && jb < N) c_put(b, i, jb, acc[r]);
+    }
+  }
+}
+
+// Wave-wide FP64 sum with DPP row operations (quad swaps, half-row and row mirrors, then the
+// row-15 and row-31 broadcasts); the total lands in lane 63.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_total(double v) {
+  v += dpp_d<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_d<0x140, 0xf>(v);  // row_mirror
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Workgroup sum (fixed order), returned to every thread.
+__device__ inline double block_total(double v, double *sh) {
+  v = wave_total(v);
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = 0.0;
 #pragma unroll
@@ -276,18 +356,21 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int chl = p.chl, chr = p.chr, ac = p.ac;
   const int n = chl * dd * chr, nr = dd * chr;
+  // Rows that the MFMA operand reads walk down (sixteen lanes, one row each) are stored with an
+  // odd stride in doubles, so those lanes fall on distinct LDS banks.
+  const int ldl = chl | 1, ldr = (D * chr) | 1, ldm = DD | 1, ldz = (D * chr) | 1;
   double *th = lds;                                  // n: V_j
   double *wv = th + n;                               // n: H V_j, then orthogonalised
-  double *Ls = wv + n;                               // L[a][w][a']
-  double *Rs = Ls + (size_t)chl * D * chl;           // R[c][w''][c']
-  double *Ms = Rs + (size_t)chr * D * chr;           // M[o][i]
-  double *Xc = Ms + DD * DD;                         // X[al][i][c'] of a chunk
-  double *Zc = Xc + (size_t)ac * DD * chr;           // Z[al][o][c'] of a chunk
-  double *hb = Zc + (size_t)ac * DD * chr;           // h of the two CGS passes
-  double *red = hb + 2 * LZ_HMAX;                    // 16 partials per wave
-  for (int e = tid; e < chl * D * chl; e += NTS) Ls[e] = p.L[e];
-  for (int e = tid; e < chr * D * chr; e += NTS) Rs[e] = p.R[e];
-  for (int e = tid; e < DD * DD; e += NTS) Ms[e] = p.M[e];
+  double *Ls = wv + n;                               // L[a][w][a'], rows (a, w) of stride ldl
+  double *Rs = Ls + (size_t)chl * D * ldl;           // R[c][w''][c'], rows c of stride ldr
+  double *Ms = Rs + (size_t)chr * ldr;               // M[o][i], rows o of stride ldm
+  double *Xc = Ms + DD * ldm;                        // X[al][i][c'] of a chunk
+  double *Zc = Xc + (size_t)ac * DD * chr;           // Z[al][s t][w''][c'], rows (al, s t) of stride ldz
+  double *hb = Zc + (size_t)ac * dd * ldz;           // h of the two CGS passes
+  double *red = hb + 2 * LZ_HMAX;                    // per-wave partial sums
+  for (int e = tid; e < chl * D * chl; e += NTS) Ls[(e / chl) * ldl + e % chl] = p.L[e];
+  for (int e = tid; e < chr * D * chr; e += NTS) Rs[(e / (D * chr)) * ldr + e % (D * chr)] = p.R[e];
+  for (int e = tid; e < DD * DD; e += NTS) Ms[(e / DD) * ldm + e % DD] = p.M[e];
   int j = *p.j;
   for (int it = 0; it < iters && j < p.kmax; ++it) {
     const double *vj = p.V + (int64_t)j * n;
@@ -297,71 +380,116 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
     __syncthreads();
     for (int a0 = 0; a0 < chl; a0 += ac) {
       const int na = chl - a0 < ac ? chl - a0 : ac;
-      block_gemm(na * D, nr, chl, [&](int i, int k) { return Ls[(a0 * D + i) * chl + k]; },
+      block_gemm(na * D, nr, chl, [&](int i, int k) { return Ls[(a0 * D + i) * ldl + k]; },
                  [&](int k, int c) { return th[k * nr + c]; },
                  [&](int i, int c, double v) { Xc[i * nr + c] = v; });
       __syncthreads();
-      block_gemm(DD, na * chr, DD, [&](int o, int i) { return Ms[o * DD + i]; },
-                 [&](int i, int c) {
-                   const int al = c / chr;
-                   return Xc[(al * DD + i) * chr + (c - al * chr)];
-                 },
-                 [&](int o, int c, double v) {
-                   const int al = c / chr;
-                   Zc[(al * DD + o) * chr + (c - al * chr)] = v;
-                 });
+      // output row o = (s t, w'') goes to Zc row (al, s t) at column w'' chr + c'
+      if (chr >= 16)  // one product per row index al: no division in the operand addressing
+        block_gemm_nb(na, DD, chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
+                      [&](int al, int i, int c) { return Xc[(al * DD + i) * chr + c]; },
+                      [&](int al, int o, int c, double v) {
+                        const int st = o / D;
+                        Zc[(al * dd + st) * ldz + (o - st * D) * chr + c] = v;
+                      });
+      else  // narrow right bond: the al blocks side by side in one product, so tiles stay full
+        block_gemm(DD, na * chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
+                   [&](int i, int c) {
+                     const int al = c / chr;
+                     return Xc[(al * DD + i) * chr + (c - al * chr)];
+                   },
+                   [&](int o, int c, double v) {
+                     const int al = c / chr, st = o / D;
+                     Zc[(al * dd + st) * ldz + (o - st * D) * chr + (c - al * chr)] = v;
+                   });
       __syncthreads();
-      block_gemm(na * dd, chr, D * chr,
-                 [&](int i, int q) { return Zc[((i >> 2) * DD + (i & 3) * D) * chr + q]; },
-                 [&](int q, int c) { return Rs[c * (D * chr) + q]; },
-                 [&](int i, int c, double v) { wv[(a0 * dd + i) * chr + c] = v; });
+      block_gemm(na * dd, chr, D * chr, [&](int i, int q) { return Zc[i * ldz + q]; },
+                 [&](int q, int c) { return Rs[c * ldr + q]; },
+                 [&](int i, int c, double v) { wv[(a0 * dd + i) * chr + c] = v; }, Xc, ac * DD * chr);
       __syncthreads();
     }
-    // CGS2 against V_0..V_j: dot products sixteen at a time, updates with batched loads
+    // CGS2 against V_0..V_j (n is a multiple of 4: element pairs, 16-byte accesses).  Dot
+    // products: one wave per basis vector (vectors wave, wave + 8, ..., two at a time), lanes over
+    // the element pairs, a DPP reduction; updates: one thread per element pair, sixteen vectors
+    // per batch of loads.
+    const int n2 = n >> 1;
+    const double2 *W2 = reinterpret_cast<const double2 *>(wv);
     double b2 = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       double *h = hb + pass * LZ_HMAX;
-      for (int i0 = 0; i0 <= j; i0 += 16) {
-        double acc[16];
+      for (int i = wave; i <= j; i += 2 * NW) {
+        const bool two = i + NW <= j;
+        const double2 *va = reinterpret_cast<const double2 *>(p.V + (int64_t)i * n);
+        const double2 *vb = reinterpret_cast<const double2 *>(p.V + (int64_t)(two ? i + NW : i) * n);
+        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+        int e = lane;
+        for (; e + 192 < n2; e += 256) {
+          double2 x[4], y[4], w[4];
 #pragma unroll
-        for (int g = 0; g < 16; ++g) acc[g] = 0.0;
-        for (int e = tid; e < n; e += NTS) {
-          const double w = wv[e];
+          for (int u = 0; u < 4; ++u) {
+            x[u] = va[e + 64 * u];
+            y[u] = vb[e + 64 * u];
+          }
 #pragma unroll
-          for (int g = 0; g < 16; ++g)
-            if (i0 + g <= j) acc[g] += p.V[(int64_t)(i0 + g) * n + e] * w;
+          for (int u = 0; u < 4; ++u) w[u] = W2[e + 64 * u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a0 += x[u].x * w[u].x;
+            a1 += x[u].y * w[u].y;
+            c0 += y[u].x * w[u].x;
+            c1 += y[u].y * w[u].y;
+          }
         }
-#pragma unroll
-        for (int g = 0; g < 16; ++g) acc[g] = wave_sum(acc[g]);
-        if (lane == 0)
-#pragma unroll
-          for (int g = 0; g < 16; ++g) red[wave * 16 + g] = acc[g];
-        __syncthreads();
-        if (tid < 16 && i0 + tid <= j) {
-          double sum = 0.0;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) sum += red[w * 16 + tid];
-          h[i0 + tid] = sum;
+        for (; e < n2; e += 64) {
+          const double2 x = va[e], y = vb[e], w = W2[e];
+          a0 += x.x * w.x;
+          a1 += x.y * w.y;
+          c0 += y.x * w.x;
+          c1 += y.y * w.y;
         }
-        __syncthreads();
+        const double sa = wave_total(a0 + a1), sc = wave_total(c0 + c1);
+        if (lane == 63) {
+          h[i] = sa;
+          if (two) h[i + NW] = sc;
+        }
       }
+      __syncthreads();
       double loc = 0.0;
-      for (int e = tid; e < n; e += NTS) {
-        double acc = 0.0;
+      for (int e = tid; e < n2; e += NTS) {
+        const double2 *ve = reinterpret_cast<const double2 *>(p.V) + e;
+        double2 acc = {0.0, 0.0};
         int i = 0;
-        for (; i + 8 <= j + 1; i += 8) {
-          double v[8];
+        for (; i + 16 <= j + 1; i += 16) {
+          double2 x[16];
 #pragma unroll
-          for (int g = 0; g < 8; ++g) v[g] = p.V[(int64_t)(i + g) * n + e];
+          for (int g = 0; g < 16; ++g) x[g] = ve[(int64_t)(i + g) * n2];
 #pragma unroll
-          for (int g = 0; g < 8; ++g) acc += h[i + g] * v[g];
+          for (int g = 0; g < 16; ++g) {
+            acc.x += h[i + g] * x[g].x;
+            acc.y += h[i + g] * x[g].y;
+          }
         }
-        for (; i <= j; ++i) acc += h[i] * p.V[(int64_t)i * n + e];
-        const double v = wv[e] - acc;
-        wv[e] = v;
-        loc += v * v;
+        for (; i + 4 <= j + 1; i += 4) {
+          double2 x[4];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) x[g] = ve[(int64_t)(i + g) * n2];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            acc.x += h[i + g] * x[g].x;
+            acc.y += h[i + g] * x[g].y;
+          }
+        }
+        for (; i <= j; ++i) {
+          const double2 x = ve[(int64_t)i * n2];
+          acc.x += h[i] * x.x;
+          acc.y += h[i] * x.y;
+        }
+        const double v0 = wv[2 * e] - acc.x, v1 = wv[2 * e + 1] - acc.y;
+        wv[2 * e] = v0;
+        wv[2 * e + 1] = v1;
+        loc += v0 * v0 + v1 * v1;
       }
-      if (pass == 1) b2 = block_sum_s(loc, red);
+      if (pass == 1) b2 = block_total(loc, red);
       else __syncthreads();
     }
     if (tid == 0) {
@@ -443,8 +571,9 @@ tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s) {
 
 size_t lz_small_lds(int chl, int chr, int d, int D, int ac) {
   const size_t n = (size_t)chl * d * d * chr, DD = (size_t)D * d * d;
-  return sizeof(double) * (2 * n + (size_t)chl * D * chl + (size_t)chr * D * chr + DD * DD +
-                           2 * (size_t)ac * DD * chr + 2 * LZ_HMAX + 16 * (NTS / 64));
+  const size_t ldl = chl | 1, ldr = (D * chr) | 1, ldm = DD | 1, ldz = ldr;
+  return sizeof(double) * (2 * n + (size_t)chl * D * ldl + (size_t)chr * ldr + DD * ldm + (size_t)ac * DD * chr +
+                           (size_t)ac * d * d * ldz + 2 * LZ_HMAX + 16 * (NTS / 64));
 }
 
 tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, hipStream_t s) {
