@@ -68,9 +68,8 @@ void arena_begin(Arena &a) {
   a.off = 0;
 }
 
-template <class T>
-tna_status arena_push(Arena &a, const T *src, size_t n, hipStream_t s, const T **dev_out) {
-  const size_t bytes = sizeof(T) * n;
+// reserves `bytes` (256-byte aligned) in the current block, or in a new one
+tna_status arena_reserve(Arena &a, size_t bytes, char **host, char **dev) {
   const size_t need = (bytes + 255) & ~(size_t)255;
   while (a.cur < a.blocks.size() && a.off + need > a.blocks[a.cur].cap) {
     ++a.cur;
@@ -89,22 +88,34 @@ tna_status arena_push(Arena &a, const T *src, size_t n, hipStream_t s, const T *
     a.off = 0;
   }
   ArenaBlock &b = a.blocks[a.cur];
-  char *h = b.host + a.off;
-  char *d = static_cast<char *>(b.dev) + a.off;
+  *host = b.host + a.off;
+  *dev = static_cast<char *>(b.dev) + a.off;
+  a.off += need;
+  return TNA_OK;
+}
+
+// host values -> the arena's device half (descriptors read by kernels)
+template <class T>
+tna_status arena_push(Arena &a, const T *src, size_t n, hipStream_t s, const T **dev_out) {
+  const size_t bytes = sizeof(T) * n;
+  char *h = nullptr, *d = nullptr;
+  TNA_TRY(arena_reserve(a, bytes, &h, &d));
   if (bytes) std::memcpy(h, src, bytes);
   if (bytes) TNA_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
-  a.off += need;
   *dev_out = reinterpret_cast<const T *>(d);
   return TNA_OK;
 }
 
-// host values -> device location, staged through the arena
+// host values -> a device location, uploaded in one transfer from the arena's pinned half (not
+// reused before the step's final synchronisation)
 template <class T>
 tna_status put_dev(Arena &a, const T *src, size_t n, T *dst, hipStream_t s) {
   if (n == 0) return TNA_OK;
-  const T *d = nullptr;
-  TNA_TRY(arena_push(a, src, n, s, &d));
-  TNA_HIP(hipMemcpyAsync(dst, d, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+  const size_t bytes = sizeof(T) * n;
+  char *h = nullptr, *d = nullptr;
+  TNA_TRY(arena_reserve(a, bytes, &h, &d));
+  std::memcpy(h, src, bytes);
+  TNA_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
   return TNA_OK;
 }
 
@@ -201,6 +212,7 @@ struct tna_engine_s {
   float *h_feat = nullptr;
   double *h_rec = nullptr;  // per slot 2 LZ_HMAX: alpha_j, beta_j^2 of the single-workgroup path
   int *h_j = nullptr;
+  std::vector<int> lz_last;  // per slot: Lanczos iterations of the previous visit (launch sizing)
   long small_launches = 0;
   long graph_launches = 0, lanczos_iters = 0;
   double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
@@ -226,6 +238,7 @@ tna_status engine_create(int nslot, tna_engine *out) {
   TNA_TRY(e->feat_d.ensure(sizeof(float) * 32 * nslot));
   TNA_TRY(e->y_d.ensure(sizeof(float) * 4 * nslot));
   e->hflags.assign(2 * (size_t)nslot, 0);
+  e->lz_last.assign(nslot, 0);
   TNA_HIP(hipHostMalloc((void **)&e->h_dbl, sizeof(double) * (24 * nslot + 2 * nslot + 16), hipHostMallocDefault));
   TNA_HIP(hipHostMalloc((void **)&e->h_feat, sizeof(float) * 32 * nslot, hipHostMallocDefault));
   TNA_TRY(e->recs.ensure(sizeof(double) * 2 * LZ_HMAX * nslot));
@@ -385,7 +398,13 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     en->hflags[slot[q]] = 0;
     en->hflags[en->nslot + slot[q]] = 1;
   }
-  auto push_act = [&]() { return put_dev(en->ar, en->hflags.data() + en->nslot, (size_t)en->nslot, act_dev, s); };
+  // active flags: uploaded only when they differ from what the device holds (no kernel writes them)
+  std::vector<int> act_up(en->hflags.begin() + en->nslot, en->hflags.end());
+  auto push_act = [&]() -> tna_status {
+    if (std::equal(act_up.begin(), act_up.end(), en->hflags.begin() + en->nslot)) return TNA_OK;
+    act_up.assign(en->hflags.begin() + en->nslot, en->hflags.end());
+    return put_dev(en->ar, en->hflags.data() + en->nslot, (size_t)en->nslot, act_dev, s);
+  };
   TNA_TRY(put_dev(en->ar, en->hflags.data(), 2 * (size_t)en->nslot, j_dev, s));
   const LzProb *dlp = nullptr;
   TNA_TRY(arena_push(en->ar, lp.data(), nc, s, &dlp));
@@ -567,7 +586,12 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
              8.0 * (t + 1) * (double)v.nv;
     };
     auto it_bytes = [&](int q, int t) { return 8.0 * (double)vs[q].nv * (2.0 + 4.0 * (t + 1)); };
-    int chunk = 16;
+    // the first launch runs about as many iterations as the chain's previous visit needed (the
+    // sweep's neighbouring bonds converge alike), later launches a few at a time: fewer host
+    // round trips and fewer iterations past convergence
+    int chunk = 0;
+    for (int q : sq) chunk = std::max(chunk, en->lz_last[slot[q]] - 2);
+    chunk = chunk > 0 ? std::min(std::max(chunk, 4), 64) : 16;
     for (;;) {
       bool live = false;
       for (int q : sq) live = live || act[q];
@@ -576,10 +600,10 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       TNA_TRY(push_act());
       TNA_TRY(lz_small(dsp, (int)sp.size(), D, d * d, chunk, lds_small, s));
       en->small_launches += 1;
-      TNA_HIP(hipMemcpyAsync(en->h_j, j_dev, sizeof(int) * en->nslot, hipMemcpyDeviceToHost, s));
       TNA_HIP(hipMemcpyAsync(en->h_rec, rec_small, sizeof(double) * 2 * LZ_HMAX * en->nslot, hipMemcpyDeviceToHost,
                              s));
       TNA_HIP(hipStreamSynchronize(s));
+      for (int q : sq) en->h_j[slot[q]] = (int)en->h_rec[(size_t)2 * LZ_HMAX * slot[q] + 2 * LZ_HMAX - 1];
       if (timing_wanted("lz.small")) {
         double fl = 0.0, by = 0.0;
         for (int q : sq)
@@ -610,8 +634,9 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       TNA_TRY(restart_stopped(small));
       for (int q : sq)
         if (act[q] && al[q].empty()) jdev[q] = 0;  // restarted: j reset on the device
-      chunk = 8;
+      chunk = 4;
     }
+    for (int q : sq) en->lz_last[slot[q]] = iters[q];
   }
   // ---- lockstep grouped path: replay, read every chain's (alpha_j, beta_j^2), decide on the host
   for (int q = 0; q < nc; ++q) act[q] = !small[q];

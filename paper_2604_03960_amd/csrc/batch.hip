@@ -5,6 +5,7 @@
 // once.  Each chain's Lanczos iteration index j lives in device memory, so the
 // launch sequence of one iteration does not change from one iteration to the
 // next and is captured once per sweep step as a HIP graph.
+#include "dev_reduce.h"
 #include "internal.h"
 
 namespace tna {
@@ -221,6 +222,15 @@ __global__ __launch_bounds__(NT) void lz_combine_kernel(const LzProb *probs) {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int NTS = 512;  // threads of the single-workgroup Lanczos (8 waves)
 
+// x / d for 0 <= x < 2^16 and 1 <= d < 2^16 with one multiply-high by ceil(2^32 / d) (exact in
+// that range: the rounding error of the reciprocal, times x, stays below 1 / d).
+struct FastDiv {
+  unsigned m;
+  int d;
+  __device__ explicit FastDiv(int d_) : m(d_ > 1 ? (unsigned)(((1ull << 32) + d_ - 1) / d_) : 0u), d(d_) {}
+  __device__ int div(int x) const { return d > 1 ? (int)__umulhi((unsigned)x, m) : x; }
+};
+
 // One 16 x 16 output tile, C(i, j) = sum_{kb <= k < ke} A(i, k) B(k, j), on
 // v_mfma_f64_16x16x4_f64.  Operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
 // result D[i][j] in lane j + 16 (i % 4), register i / 4.  Rows and columns past the matrix edge
@@ -260,7 +270,8 @@ __device__ inline v4d tile_mfma(int kb, int ke, int ia, int jb, int lk, FA a_at,
 template <class FA, class FB, class FC>
 __device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_put, double *part = nullptr,
                                   int part_cap = 0) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = NTS / 64;
+  const int lane = threadIdx.x & 63, nw = NTS / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int tn = (N + 15) >> 4, tiles = ((M + 15) >> 4) * tn;
   if (part != nullptr && 2 * tiles <= nw && K >= 32 && tiles * 256 <= part_cap) {
@@ -299,7 +310,8 @@ __device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_pu
 // waves in turn.
 template <class FA, class FB, class FC>
 __device__ inline void block_gemm_nb(int NB, int M, int N, int K, FA a_at, FB b_at, FC c_put) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = NTS / 64;
+  const int lane = threadIdx.x & 63, nw = NTS / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int tn = (N + 15) >> 4, tpb = ((M + 15) >> 4) * tn;
   for (int t = wave; t < NB * tpb; t += nw) {
@@ -313,25 +325,6 @@ __device__ inline void block_gemm_nb(int NB, int M, int N, int K, FA a_at, FB b_
       if (i < M && jb < N) c_put(b, i, jb, acc[r]);
     }
   }
-}
-
-// Wave-wide FP64 sum with DPP row operations (quad swaps, half-row and row mirrors, then the
-// row-15 and row-31 broadcasts); the total lands in lane 63.
-template <int CTRL, int ROWS>
-__device__ inline double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ inline double wave_total(double v) {
-  v += dpp_d<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
-  v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
-  v += dpp_d<0x140, 0xf>(v);  // row_mirror
-  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
 }
 
 // Workgroup sum (fixed order), returned to every thread.
@@ -359,6 +352,7 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
   // Rows that the MFMA operand reads walk down (sixteen lanes, one row each) are stored with an
   // odd stride in doubles, so those lanes fall on distinct LDS banks.
   const int ldl = chl | 1, ldr = (D * chr) | 1, ldm = DD | 1, ldz = (D * chr) | 1;
+  const FastDiv divD(D), divC(chr);
   double *th = lds;                                  // n: V_j
   double *wv = th + n;                               // n: H V_j, then orthogonalised
   double *Ls = wv + n;                               // L[a][w][a'], rows (a, w) of stride ldl
@@ -389,17 +383,17 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
         block_gemm_nb(na, DD, chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
                       [&](int al, int i, int c) { return Xc[(al * DD + i) * chr + c]; },
                       [&](int al, int o, int c, double v) {
-                        const int st = o / D;
+                        const int st = divD.div(o);
                         Zc[(al * dd + st) * ldz + (o - st * D) * chr + c] = v;
                       });
       else  // narrow right bond: the al blocks side by side in one product, so tiles stay full
         block_gemm(DD, na * chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
                    [&](int i, int c) {
-                     const int al = c / chr;
+                     const int al = divC.div(c);
                      return Xc[(al * DD + i) * chr + (c - al * chr)];
                    },
                    [&](int o, int c, double v) {
-                     const int al = c / chr, st = o / D;
+                     const int al = divC.div(c), st = divD.div(o);
                      Zc[(al * dd + st) * ldz + (o - st * D) * chr + (c - al * chr)] = v;
                    });
       __syncthreads();
@@ -504,7 +498,10 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
     ++j;
     if (stop) break;
   }
-  if (tid == 0) *p.j = j;
+  if (tid == 0) {
+    *p.j = j;
+    p.rec[2 * LZ_HMAX - 1] = (double)j;  // read back with the records (they end below 2 LZ_HMAX - 2)
+  }
 }
 
 __global__ __launch_bounds__(NT) void convert_grouped_kernel(const CvtProb *probs) {

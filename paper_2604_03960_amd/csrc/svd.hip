@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "dev_reduce.h"
 #include "internal.h"
 
 namespace tna {
@@ -51,6 +52,34 @@ void DevBuf::release() {
 }
 
 namespace {
+
+// Jacobi rotation zeroing the off-diagonal g of a symmetric 2 x 2 block [[a, g], [g, b]] (g != 0):
+// t = sign(b - a) 2 g / (|b - a| + sqrt((b - a)^2 + 4 g^2)), c = 1 / sqrt(1 + t^2), s = c t.  The
+// square roots and the quotient come from the hardware reciprocal and reciprocal-square-root
+// estimates refined by two Newton steps each (the relative error squares per step), which keeps
+// c^2 + s^2 = 1 to a few ulp while avoiding the long correctly rounded division and square-root
+// sequences.
+__device__ inline double rsqrt_nr(double x) {  // x > 0, finite
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ inline double rcp_nr(double x) {  // x > 0, finite
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline void jacobi_rot(double a, double b, double g, double &c, double &s) {
+  const double dl = b - a, q = fma(dl, dl, 4.0 * g * g);
+  const double t = (dl >= 0.0 ? 2.0 : -2.0) * g * rcp_nr(fabs(dl) + q * rsqrt_nr(q));
+  c = rsqrt_nr(fma(t, t, 1.0));
+  s = c * t;
+}
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr double EPS53 = 1.1102230246251565e-16;
@@ -246,11 +275,8 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
         double c = 1.0, s = 0.0;
         if (i != j) {
           const double gii = L.G[i][i], gjj = L.G[j][j], gij = L.G[i][j];
-          if (gii > floor2 && gjj > floor2 && fabs(gij) > tol_in * sqrt(fabs(gii * gjj))) {
-            const double dl = gjj - gii;
-            const double t = (dl >= 0.0 ? 2.0 : -2.0) * gij / (fabs(dl) + sqrt(dl * dl + 4.0 * gij * gij));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = c * t;
+          if (gii > floor2 && gjj > floor2 && gij * gij > tol_in * tol_in * fabs(gii * gjj)) {
+            jacobi_rot(gii, gjj, gij, c, s);
             L.rot_any = 1;
           }
         }
@@ -533,9 +559,13 @@ __global__ __launch_bounds__(256) void jacobi_tiny_kernel(const SvdMat *mats, in
     int rot = 0;
     for (int rr = 0; rr < nvp - 1; ++rr) {
       int i = -1, j = -1;
-      if (t < P) {
-        if (t == 0) { i = rr % (nvp - 1); j = nvp - 1; }
-        else { i = (rr + t) % (nvp - 1); j = (rr - t + nvp - 1) % (nvp - 1); }
+      if (t < P) {  // round rr of the round-robin: 0 <= rr + t, rr - t + nvp - 1 < 2 (nvp - 1)
+        const int m1 = nvp - 1;
+        if (t == 0) { i = rr; j = m1; }
+        else {
+          i = rr + t >= m1 ? rr + t - m1 : rr + t;
+          j = rr - t + m1 >= m1 ? rr - t : rr - t + m1;
+        }
         if (i > j) { const int q = i; i = j; j = q; }
         if (j >= R) i = -1;  // the dummy of an odd R
       }
@@ -556,16 +586,13 @@ __global__ __launch_bounds__(256) void jacobi_tiny_kernel(const SvdMat *mats, in
           yj[u] = Js[j][l + 16 * u];
         }
       }
-#pragma unroll
-      for (int off = 8; off > 0; off >>= 1) {
-        al += __shfl_xor(al, off, 16);
-        be += __shfl_xor(be, off, 16);
-        ga += __shfl_xor(ga, off, 16);
-      }
-      if (i >= 0 && al > floor2 && be > floor2 && al > 0.0 && be > 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+      // the 16 lanes of a pair are one DPP row
+      al = row16_sum(al);
+      be = row16_sum(be);
+      ga = row16_sum(ga);
+      if (i >= 0 && al > floor2 && be > floor2 && al > 0.0 && be > 0.0 && ga * ga > a.tol * a.tol * (al * be)) {
+        double c, s;
+        jacobi_rot(al, be, ga, c, s);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           Bs[i][l + 16 * u] = c * xa[u] - s * ya[u];
@@ -879,10 +906,17 @@ __global__ __launch_bounds__(1024) void sort_kernel(const SvdMat *mats) {
     const int beg = t * L, end = beg + L < R ? beg + L : R;
     double c = 0.0;
     for (int j = beg; j < end; ++j) c += key[j] * key[j];
-    csum[t] = c;
+    // sums over the chunks after this one: inclusive suffix scan in a fixed tree order
+    double v = c;
+    for (int off = 1; off < 1024; off <<= 1) {
+      csum[t] = v;
+      __syncthreads();
+      if (t + off < 1024) v += csum[t + off];
+      __syncthreads();
+    }
+    csum[t] = v;
     __syncthreads();
-    double after = 0.0;
-    for (int u = 1023; u > t; --u) after += csum[u];
+    const double after = t + 1 < 1024 ? csum[t + 1] : 0.0;
     int kmin = R;
     double tsum = after;
     for (int j = end - 1; j >= beg; --j) {
