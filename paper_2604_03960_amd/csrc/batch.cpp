@@ -527,6 +527,57 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     }
     return stop;
   };
+  // records t0 .. jn-1 of chain q at once, from the single-workgroup path.  The stopping rule is
+  // take()'s; the tridiagonal problem is solved for the newest record, and only when that one
+  // meets the residual test are the earlier new records solved, in order, to find the first that
+  // does (a record that met it and was followed by one that did not is not looked for).  Returns
+  // true when the chain stops.
+  auto take_batch = [&](int q, const double *r, int t0, int jn) -> bool {
+    const int base = (int)al[q].size();
+    const bool fixed = vs[q].fixed > 0;
+    int last = jn, cheap = 0;  // cheap: breakdown or kmax at record `last`
+    for (int t = t0; t < jn; ++t) {
+      al[q].push_back(r[2 * t]);
+      be[q].push_back(std::sqrt(r[2 * t + 1]));
+      if (be[q].back() < 1e-14 || t + 1 >= vs[q].kmax) {
+        last = t + 1;
+        cheap = 1;
+        break;
+      }
+    }
+    auto solve = [&](int nn) {
+      yv[q].assign(nn, 0.0);
+      Ec[q] = tridiag_lowest_host(nn, al[q].data(), be[q].data(), yv[q].data());
+      return std::fabs(be[q][nn - 1] * yv[q][nn - 1]) <= ch[q]->opts.lanczos_tol * std::max(1.0, std::fabs(Ec[q]));
+    };
+    int stop_at = 0;
+    bool converged = false;
+    if (fixed) {
+      solve(last);
+      if (cheap) stop_at = last, converged = true;
+    } else if (solve(last)) {
+      stop_at = last;
+      converged = true;
+      for (int nn = base + 1; nn < last; ++nn)
+        if (solve(nn)) {
+          stop_at = nn;
+          break;
+        }
+      if (stop_at == last) solve(last);  // the earlier trial solves overwrote Ec / yv
+    } else if (cheap) {
+      stop_at = last;
+      converged = be[q][last - 1] < 1e-14;
+    }
+    const int nn = stop_at > 0 ? stop_at : last;
+    al[q].resize(nn);
+    be[q].resize(nn);
+    iters[q] += nn - base;
+    if (stop_at == 0) return false;
+    conv[q] = converged;
+    nkeep[q] = nn;
+    act[q] = 0;
+    return true;
+  };
   // chains in `set` that stopped at kmax unconverged restart from their Ritz vector
   auto restart_stopped = [&](const std::vector<int> &set) -> tna_status {
     std::vector<int> rs(nc, 0);
@@ -619,12 +670,16 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
         start[q] = (int)al[q].size();
         const double *r = en->h_rec + (size_t)2 * LZ_HMAX * slot[q];
         const int jn = en->h_j[slot[q]];
-        for (int t = (int)al[q].size(); t < jn && act[q]; ++t) {
+        int jn_ok = jn;  // records past a non-finite one are not taken
+        for (int t = start[q]; t < jn; ++t)
           if (!std::isfinite(r[2 * t]) || !std::isfinite(r[2 * t + 1])) {
-            set_error("lanczos: non-finite coefficient");
-            return TNA_ERR_NONFINITE;
+            jn_ok = t;
+            break;
           }
-          take(q, r[2 * t], r[2 * t + 1]);
+        if (jn_ok > start[q]) take_batch(q, r, start[q], jn_ok);
+        if (act[q] && jn_ok < jn) {
+          set_error("lanczos: non-finite coefficient");
+          return TNA_ERR_NONFINITE;
         }
         if (act[q] && jn <= start[q]) {
           set_error("lanczos (single-workgroup path): no progress");
@@ -731,11 +786,17 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     }
   }
   std::vector<int> sweeps;
-  tna_status sst = svd_group_run(mats, en->svd, ch[0]->opts.svd_max_sweeps, sweeps, s);
+  tna_status sst = svd_group_run(mats, en->svd, ch[0]->opts.svd_max_sweeps, sweeps, s, true);
   if (sst != TNA_OK && sst != TNA_ERR_NOCONV) return sst;
   if (sst == TNA_ERR_NOCONV && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
   TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
   TNA_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < nc; ++q)  // single-workgroup Jacobi paths: sweeps and convergence from spec[7]
+    if (mats[q].fused) {
+      const double f = en->h_dbl[24 * q + 7];
+      sweeps[q] = (int)std::fabs(f);
+      if (f < 0.0 && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
+    }
   // ---- controllers, scheduler inputs, kept ranks
   std::vector<double> terms(6 * nc);
   std::vector<int> chi_next(nc), kk(nc), kneed(nc), chs(nc, 0), fb(nc, 0);

@@ -207,6 +207,42 @@ __global__ __launch_bounds__(NT) void lz_combine_kernel(const LzProb *probs) {
   }
 }
 
+// Start and Ritz steps of a chain whose vectors fit one partition (G == 1), one workgroup each:
+// V_0 = theta / |theta|, and theta = sum_i y_i V_i normalised in place.
+__global__ __launch_bounds__(NT) void lz_start1_kernel(const LzProb *probs) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.x];
+  if (!*p.active) return;
+  double loc = 0.0;
+  for (int64_t e = threadIdx.x; e < p.n; e += NT) loc += p.theta[e] * p.theta[e];
+  const double f = 1.0 / sqrt(block_sum(loc, sh));
+  for (int64_t e = threadIdx.x; e < p.n; e += NT) p.V[e] = p.theta[e] * f;
+}
+
+__global__ __launch_bounds__(NT) void lz_ritz1_kernel(const LzProb *probs) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.x];
+  if (!*p.active) return;
+  const int nv = p.nkeep;
+  double loc = 0.0;
+  for (int64_t e = threadIdx.x; e < p.n; e += NT) {
+    double acc = 0.0;
+    int i = 0;
+    for (; i + 8 <= nv; i += 8) {
+      double x[8];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) x[g] = p.V[(int64_t)(i + g) * p.n + e];
+#pragma unroll
+      for (int g = 0; g < 8; ++g) acc += p.y[i + g] * x[g];
+    }
+    for (; i < nv; ++i) acc += p.y[i] * p.V[(int64_t)i * p.n + e];
+    p.theta[e] = acc;
+    loc += acc * acc;
+  }
+  const double f = 1.0 / sqrt(block_sum(loc, sh));
+  for (int64_t e = threadIdx.x; e < p.n; e += NT) p.theta[e] *= f;
+}
+
 // ------------------------------------------------------------------ single-workgroup Lanczos
 // Whole Lanczos iterations of one short theta inside one workgroup (grid x =
 // chain).  H_eff (Eq. 1's contraction in the order L, W_i W_{i+1}, R) runs as
@@ -549,6 +585,11 @@ tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, double byt
 
 tna_status lz_start(const LzProb *d, int nch, int maxG, hipStream_t s) {
   // V_0 = theta / |theta|
+  if (maxG == 1) {
+    hipLaunchKernelGGL(lz_start1_kernel, dim3(nch), dim3(NT), 0, s, d);
+    TNA_LAUNCHED("lanczos.start");
+    return TNA_OK;
+  }
   hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 0, 1);
   hipLaunchKernelGGL(lz_norm_kernel, dim3(1, nch), dim3(NT), 0, s, d, 1, 1);
   hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 2, 1);
@@ -558,6 +599,11 @@ tna_status lz_start(const LzProb *d, int nch, int maxG, hipStream_t s) {
 
 tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s) {
   // theta = sum y_i V_i, then normalised in place
+  if (maxG == 1) {
+    hipLaunchKernelGGL(lz_ritz1_kernel, dim3(nch), dim3(NT), 0, s, d);
+    TNA_LAUNCHED("lanczos.ritz");
+    return TNA_OK;
+  }
   hipLaunchKernelGGL(lz_combine_kernel, dim3(maxG, nch), dim3(NT), 0, s, d);
   hipLaunchKernelGGL(lz_norm_kernel, dim3(maxG, nch), dim3(NT), 0, s, d, 0, 1);
   hipLaunchKernelGGL(lz_norm_kernel, dim3(1, nch), dim3(NT), 0, s, d, 1, 1);

@@ -182,10 +182,13 @@ size_t svd_work_doubles(const SvdMat &a);
 size_t svd_work_ints(const SvdMat &a);
 void svd_bind_work(SvdMat *a, double *dw, int *iw);
 // Loads every A, runs Jacobi sweeps until a matrix's sweep rotates nothing
-// (one host read per sweep), then sorts and writes S, spec[0,1,6,8..23].
-// Returns TNA_ERR_NOCONV if any matrix hit max_sweeps.
+// (one host read per sweep), then sorts and writes S, spec[0,1,6,7,8..23].
+// Returns TNA_ERR_NOCONV if any matrix hit max_sweeps.  With defer_fused, the
+// matrices on the single-workgroup Jacobi paths are not read back here: their
+// sweep counts (negative when not converged) are in spec[7].
 tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps, std::vector<int> &sweeps,
-                         hipStream_t s);
+                         hipStream_t s,
+                         bool defer_fused = false);
 // For each matrix's k: spec[2..5], U and Vt (completion of null vectors,
 // sign gauge, scaling).
 tna_status svd_group_outputs(std::vector<SvdMat> &mats, SvdGroup &g, hipStream_t s);

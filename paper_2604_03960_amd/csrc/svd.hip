@@ -896,6 +896,8 @@ __global__ __launch_bounds__(1024) void sort_kernel(const SvdMat *mats) {
     a.spec[1] = ent;
   }
   if (threadIdx.x < 16) a.spec[8 + threadIdx.x] = (int)threadIdx.x < a.R ? key[threadIdx.x] : 0.0;
+  // spec[7]: sweeps of the single-workgroup Jacobi paths, negative when not converged (0 otherwise)
+  if (threadIdx.x == 0) a.spec[7] = a.fused ? (a.ctr[0] ? -(double)a.ctr[1] : (double)a.ctr[1]) : 0.0;
   // spec[6]: smallest k >= 1 with sqrt(sum_{j>=k} S_j^2) <= eps_target (k = R always qualifies)
   if (a.eps_target > 0.0) {
     __shared__ double csum[1024];
@@ -1257,7 +1259,7 @@ static tna_status qr_block_apply(const std::vector<SvdMat> &mats, const SvdMat *
 }
 
 tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps, std::vector<int> &sweeps,
-                         hipStream_t s) {
+                         hipStream_t s, bool defer_fused) {
   const int nm = (int)mats.size();
   if (nm == 0) return TNA_OK;
   sweeps.assign(nm, 0);
@@ -1319,12 +1321,16 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     TNA_LAUNCHED("svd.qr");
   }
   // one block pair: every sweep inside one workgroup, no host round trip per sweep
-  int nfused = 0;
-  for (auto &a : mats) nfused += a.fused;
+  int nfused = 0, n_two = 0, n_tiny = 0;
+  for (auto &a : mats) {
+    nfused += a.fused != 0;
+    n_two += a.fused == 1;
+    n_tiny += a.fused == 2;
+  }
   if (nfused > 0) {
     timer_begin("svd.fused", s);
-    hipLaunchKernelGGL(jacobi_fused_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
-    hipLaunchKernelGGL(jacobi_tiny_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
+    if (n_two) hipLaunchKernelGGL(jacobi_fused_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
+    if (n_tiny) hipLaunchKernelGGL(jacobi_tiny_kernel, dim3(nm), dim3(256), 0, s, d, max_sweeps);
     timer_end("svd.fused", 0.0, 0.0, s);
     TNA_LAUNCHED("svd.fused");
   }
@@ -1377,7 +1383,9 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
         if (live[z]) max_steps = std::max(max_steps, mats[z].nb - 1);
     }
   }
-  if (nfused > 0) {
+  // with defer_fused the caller takes the sweep counts and convergence of the single-workgroup
+  // paths from spec[7] after its own read of the spectra (no synchronisation here)
+  if (nfused > 0 && !defer_fused) {
     for (int z = 0; z < nm; ++z)
       if (mats[z].fused)
         TNA_HIP(hipMemcpyAsync(g.host_ctr + 2 * z, mats[z].ctr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1395,8 +1403,12 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       }
     timer_add_work("svd.fused", fl, by);
   }
-  for (auto &a : mats) a.active = 1;  // finishing kernels run on every matrix
-  TNA_TRY(upload(mats, g, s));
+  bool reup = false;  // finishing kernels run on every matrix
+  for (auto &a : mats) {
+    reup = reup || !a.active;
+    a.active = 1;
+  }
+  if (reup) TNA_TRY(upload(mats, g, s));
   hipLaunchKernelGGL(norms_kernel, dim3(max_r4, 1, nm), dim3(256), 0, s, d);
   hipLaunchKernelGGL(sort_kernel, dim3(nm), dim3(1024), 0, s, d);
   TNA_LAUNCHED("svd.finish");
