@@ -144,6 +144,15 @@ typedef struct {
 tna_status tna_pid_chi_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next,
                               double *terms);
 
+/* Entropy-margin bond dimension (Sec. 4, Eq. 6-8 and Algorithm 1): the same EMA of the bond entropy
+ * as the PID (p->alpha; seeded with the first entropy unless p->ema_init_zero), then
+ * chi_next = clamp(ceil(gamma * exp(S_ema)), p->chi_min, p->chi_max).  gamma >= 1 is the margin.
+ * Updates st->s_ema, st->s_ema_prev, st->visits and st->chi (the PID fields stay untouched).
+ * Host arithmetic.  TNA_ERR_ARG on a null pointer, gamma < 1 or bad bounds; TNA_ERR_NONFINITE on a
+ * non-finite entropy. */
+tna_status tna_entropy_chi_update(const tna_pid_params *p, double gamma, tna_pid_state *st, double s_raw,
+                                  int *chi_next);
+
 /* ---------------------------------------------------------------- DMRG */
 typedef struct {
   double lanczos_tol;     /* residual |beta_j y_j| <= tol*max(1,|E|); default 1e-12 */
@@ -154,7 +163,16 @@ typedef struct {
   int fixed_chi;          /* >0: keep min(fixed_chi, m, n) regardless of the controller */
   int svd_max_sweeps;     /* default 60 */
   double eps_target;      /* truncation-error target that is reported (and used by schedulers) */
+  int chi_rule;           /* rank rule: TNA_CHI_PID (Algorithm 2, default), TNA_CHI_THRESHOLD,
+                             TNA_CHI_ENTROPY (Algorithm 1); fixed_chi > 0 overrides all three */
+  int pad_;
+  double rule_param;      /* TNA_CHI_THRESHOLD: eps_trunc (keep the singular values above it, at most
+                             pid.chi_max and at least one); TNA_CHI_ENTROPY: the margin gamma >= 1 */
 } tna_dmrg_opts;
+
+/* chi_rule values.  The PID runs and is logged under every rule; under TNA_CHI_ENTROPY the per-bond
+ * state is advanced by tna_entropy_chi_update instead. */
+enum { TNA_CHI_PID = 0, TNA_CHI_THRESHOLD = 1, TNA_CHI_ENTROPY = 2 };
 
 /* One record per bond visit (host).  k_needed: smallest rank whose
  * truncation error meets opts.eps_target on this visit's spectrum;

@@ -49,7 +49,8 @@ class PidState(C.Structure):
 
 class DmrgOpts(C.Structure):
     _fields_ = [("n_sweeps", C.c_int), ("lanczos_kmax", C.c_int), ("lanczos_restarts", C.c_int),
-                ("fixed_iters", C.c_int), ("lanczos_tol", C.c_double), ("fixed_chi", C.c_int), ("pad", C.c_int)]
+                ("fixed_iters", C.c_int), ("lanczos_tol", C.c_double), ("fixed_chi", C.c_int), ("pad", C.c_int),
+                ("chi_rule", C.c_int), ("pad2", C.c_int), ("rule_param", C.c_double)]
 
 
 _lib = None
@@ -69,6 +70,8 @@ def lib():
         _lib.or_spectrum.argtypes = [C.c_int, dp, C.c_int, dp]
         _lib.or_spectrum.restype = None
         _lib.or_pid_update.argtypes = [C.POINTER(PidParams), C.POINTER(PidState), C.c_double, ip, dp]
+        _lib.or_entropy_chi_update.argtypes = [C.POINTER(PidParams), C.c_double, C.POINTER(PidState), C.c_double,
+                                               ip, dp]
         _lib.or_heff_apply.argtypes = [C.c_int] * 4 + [dp] * 6
         _lib.or_heff_element.argtypes = [C.c_int] * 4 + [dp] * 5 + [C.c_int] * 4
         _lib.or_heff_element.restype = C.c_double
@@ -176,6 +179,17 @@ def pid_update(pp: PidParams, st: PidState, s_raw: float):
     return chi.value, dict(P=terms[0], I=terms[1], D=terms[2], u=terms[3], sbar=terms[4], e=terms[5])
 
 
+def entropy_chi_update(pp: PidParams, gamma: float, st: PidState, s_raw: float):
+    """Algorithm 1 (Sec. 4, Eq. 6-8): EMA of the entropy, chi = clamp(ceil(gamma exp(S_ema)))."""
+    chi = C.c_int(0)
+    terms = np.zeros(6)
+    rc = lib().or_entropy_chi_update(C.byref(pp), C.c_double(gamma), C.byref(st), C.c_double(s_raw), C.byref(chi),
+                                     _p(terms))
+    if rc != 0:
+        raise ValueError("entropy rule: bad arguments")
+    return chi.value, float(terms[4])
+
+
 def heff_apply(L, W1, W2, R, theta):
     chl, D, _ = L.shape
     chr_ = R.shape[0]
@@ -233,11 +247,11 @@ def right_canonical(N, d, A_packed, chi):
 
 
 def dmrg_run(W, A_packed, chi_init, pp: PidParams, n_sweeps, lanczos_tol=1e-12, kmax=100, restarts=5,
-             fixed_iters=0, fixed_chi=0):
+             fixed_iters=0, fixed_chi=0, chi_rule=0, rule_param=0.0):
     """Runs the two-site DMRG; returns dict(log=[records], E=[per sweep], chi=[final], pid=[states], rc)."""
     W = _f64(W)
     N, D, _, d, _ = W.shape
-    opts = DmrgOpts(n_sweeps, kmax, restarts, fixed_iters, lanczos_tol, fixed_chi, 0)
+    opts = DmrgOpts(n_sweeps, kmax, restarts, fixed_iters, lanczos_tol, fixed_chi, 0, chi_rule, 0, rule_param)
     nrec = n_sweeps * 2 * (N - 1)
     log = np.zeros((nrec, LOG_FIELDS))
     E = np.zeros(n_sweeps)

@@ -457,6 +457,37 @@ int or_pid_update(const or_pid_params *pp, or_pid_state *st, double s_raw, int *
   return OR_OK;
 }
 
+/* Algorithm 1 (Sec. 4): entropy -> EMA (Eq. 8, seeded with the first entropy unless
+ * ema_init_zero) -> chi_target = ceil(gamma exp(S_ema)) (Eq. 7) -> clamp to
+ * [chi_min, chi_max].  Shares the per-bond state with the PID (EMA fields,
+ * chi, visits); terms[4] = S_ema, the PID terms are zero. */
+int or_entropy_chi_update(const or_pid_params *pp, double gamma, or_pid_state *st, double s_raw, int *chi_next,
+                          double *terms) {
+  if (pp->chi_min < 1 || pp->chi_max < pp->chi_min || !(gamma >= 1.0)) return OR_ERR_ARG;
+  int first = st->visits == 0;
+  double sbar_prev = first ? (pp->ema_init_zero ? 0.0 : s_raw) : st->s_ema;
+  double sbar;
+  if (first && !pp->ema_init_zero) {
+    sbar = s_raw;
+  } else {
+    double t1 = pp->alpha * s_raw;
+    double t2 = (1.0 - pp->alpha) * sbar_prev;
+    sbar = t1 + t2;
+  }
+  double target = ceil(gamma * exp(sbar));
+  long c;
+  if (target < pp->chi_min) c = pp->chi_min;
+  else if (target > pp->chi_max) c = pp->chi_max;
+  else c = (long)target;
+  st->s_ema_prev = first ? sbar : st->s_ema;
+  st->s_ema = sbar;
+  st->chi = (int)c;
+  st->visits += 1;
+  if (chi_next) *chi_next = (int)c;
+  if (terms) { terms[0] = terms[1] = terms[2] = terms[3] = terms[5] = 0.0; terms[4] = sbar; }
+  return OR_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One element out[a][s][t][c] of H_eff theta (Eq. 18), straight from the     */
 /* definition: the left block first (sum over a'), then the right block       */
@@ -750,6 +781,10 @@ typedef struct {
   double lanczos_tol;
   int fixed_chi; /* >0: keep min(fixed_chi, m, n), controller still logged */
   int pad;
+  int chi_rule;  /* 0: PID (Algorithm 2); 1: standard threshold rule, keep min(chi_max, r) with
+                    r = #{sigma > rule_param} (at least 1; Sec. 10); 2: Algorithm 1, gamma = rule_param */
+  int pad2;
+  double rule_param;
 } or_dmrg_opts;
 
 #define OR_LOG_FIELDS 22
@@ -843,8 +878,15 @@ int or_dmrg_run(int N, int d, int D, const double *W, const double *A_init, cons
         or_spectrum(Rk, S, Rk, sp);
         double terms[6] = {0};
         int chi_next = 0;
-        or_pid_update(pp, &ps[b], sp[1], &chi_next, terms);
+        if (op->chi_rule == 2) or_entropy_chi_update(pp, op->rule_param, &ps[b], sp[1], &chi_next, terms);
+        else or_pid_update(pp, &ps[b], sp[1], &chi_next, terms);
         int keep = op->fixed_chi > 0 ? op->fixed_chi : chi_next;
+        if (op->fixed_chi <= 0 && op->chi_rule == 1) {
+          int r = 0;
+          for (int j = 0; j < Rk; ++j) r += S[j] > op->rule_param;
+          if (r < 1) r = 1;
+          keep = r < pp->chi_max ? r : pp->chi_max;
+        }
         int k = keep < Rk ? keep : Rk;
         or_spectrum(Rk, S, k, sp);
         double nk = 0.0;

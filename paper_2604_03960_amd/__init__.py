@@ -20,6 +20,7 @@ TNA_OK, TNA_ERR_ARG, TNA_ERR_NOMEM, TNA_ERR_DEVICE, TNA_ERR_NOCONV, TNA_ERR_NONF
 F64, F32 = 0, 1
 HEFF_F64, HEFF_F32, HEFF_BF16X3 = 0, 1, 2
 MODEL_XXZ, MODEL_J1J2, MODEL_TFIM = 0, 1, 2
+CHI_PID, CHI_THRESHOLD, CHI_ENTROPY = 0, 1, 2  # rank rules: Algorithm 2, singular values above eps_trunc, Algorithm 1
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_DEVICE", 4: "ERR_NOCONV", 5: "ERR_NONFINITE",
                 6: "ERR_UNSUPPORTED"}
@@ -57,7 +58,8 @@ class PidState(C.Structure):
 class DmrgOpts(C.Structure):
     _fields_ = [("lanczos_tol", C.c_double), ("lanczos_kmax", C.c_int), ("lanczos_restarts", C.c_int),
                 ("lanczos_fixed_iters", C.c_int), ("heff_prec", C.c_int), ("fixed_chi", C.c_int),
-                ("svd_max_sweeps", C.c_int), ("eps_target", C.c_double)]
+                ("svd_max_sweeps", C.c_int), ("eps_target", C.c_double), ("chi_rule", C.c_int), ("pad_", C.c_int),
+                ("rule_param", C.c_double)]
 
 
 class VisitLog(C.Structure):
@@ -90,6 +92,7 @@ _SIGS = {
     "tna_svd_truncate_batched": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int, _vp, C.c_int64,
                                   _vp, C.c_int64, _vp, C.c_int64, _vp, _ip], C.c_int),
     "tna_pid_chi_update": ([C.POINTER(PidParams), C.POINTER(PidState), C.c_double, _ip, _dp], C.c_int),
+    "tna_entropy_chi_update": ([C.POINTER(PidParams), C.c_double, C.POINTER(PidState), C.c_double, _ip], C.c_int),
     "tna_dmrg_create": ([_vp, C.c_int, C.c_int, C.c_int, _dp, _dp, _ip, C.POINTER(PidParams), C.POINTER(DmrgOpts),
                          C.POINTER(C.c_void_p)], C.c_int),
     "tna_dmrg_sweep": ([_vp, _dp, C.POINTER(VisitLog)], C.c_int),
@@ -156,6 +159,13 @@ def mpo_build(model: int, N: int, params) -> np.ndarray:
 
 def pid_params(kp, ki, kd, s_target, alpha, chi_min, chi_max, beta=0.0, ema_init_zero=False) -> PidParams:
     return PidParams(kp, ki, kd, s_target, alpha, beta, chi_min, chi_max, int(ema_init_zero), 0)
+
+
+def entropy_chi_update(pp: PidParams, gamma: float, st: PidState, s_raw: float) -> int:
+    """Algorithm 1: EMA of the entropy, then clamp(ceil(gamma exp(S_ema)), chi_min, chi_max)."""
+    chi = C.c_int(0)
+    _check(_lib.tna_entropy_chi_update(C.byref(pp), float(gamma), C.byref(st), float(s_raw), C.byref(chi)))
+    return chi.value
 
 
 def pid_chi_update(pp: PidParams, st: PidState, s_raw: float):
@@ -280,7 +290,7 @@ class Dmrg:
 
     def __init__(self, ctx: Context, W: np.ndarray, A_packed: np.ndarray, chi_init, pid: PidParams,
                  lanczos_tol=1e-12, lanczos_kmax=100, lanczos_restarts=5, fixed_iters=0, heff_prec=HEFF_F64,
-                 fixed_chi=0, svd_max_sweeps=60, eps_target=1e-8):
+                 fixed_chi=0, svd_max_sweeps=60, eps_target=1e-8, chi_rule=CHI_PID, rule_param=0.0):
         W = np.ascontiguousarray(W, dtype=np.float64)
         N, D, _, d, _ = W.shape
         self.N, self.d, self.D = N, d, D
@@ -288,7 +298,7 @@ class Dmrg:
         A = np.ascontiguousarray(A_packed, dtype=np.float64)
         chi = np.ascontiguousarray(chi_init, dtype=np.int32)
         self.opts = DmrgOpts(lanczos_tol, lanczos_kmax, lanczos_restarts, fixed_iters, heff_prec, fixed_chi,
-                             svd_max_sweeps, eps_target)
+                             svd_max_sweeps, eps_target, chi_rule, 0, rule_param)
         self.pid = pid
         h = C.c_void_p()
         _check(_lib.tna_dmrg_create(ctx.h, N, d, D, W.ctypes.data_as(_dp), A.ctypes.data_as(_dp),
@@ -424,7 +434,8 @@ class DmrgBatch:
     """Independent chains swept together through grouped launches."""
 
     def __init__(self, ctx: Context, Ws, As, chis, pid: PidParams, lanczos_tol=1e-12, lanczos_kmax=100,
-                 lanczos_restarts=5, heff_prec=HEFF_F64, fixed_chi=0, svd_max_sweeps=60, eps_target=1e-8):
+                 lanczos_restarts=5, heff_prec=HEFF_F64, fixed_chi=0, svd_max_sweeps=60, eps_target=1e-8,
+                 chi_rule=CHI_PID, rule_param=0.0):
         n = len(Ws)
         self.Ws = [np.ascontiguousarray(w, dtype=np.float64) for w in Ws]
         self.As = [np.ascontiguousarray(a, dtype=np.float64) for a in As]
@@ -435,7 +446,7 @@ class DmrgBatch:
         Ap = (_dp * n)(*[a.ctypes.data_as(_dp) for a in self.As])
         Cp = (_ip * n)(*[c.ctypes.data_as(_ip) for c in self.chis])
         self.opts = DmrgOpts(lanczos_tol, lanczos_kmax, lanczos_restarts, 0, heff_prec, fixed_chi, svd_max_sweeps,
-                             eps_target)
+                             eps_target, chi_rule, 0, rule_param)
         self.pid = pid
         h = C.c_void_p()
         _check(_lib.tna_dmrg_batch_create(ctx.h, n, self.N.ctypes.data_as(_ip), d, D, Wp, Ap, Cp, C.byref(pid),

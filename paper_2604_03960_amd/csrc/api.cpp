@@ -376,6 +376,44 @@ tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, 
   }
   return TNA_OK;
 }
+
+// Algorithm 1 (Eq. 6-8): the EMA as in pid_update, then clamp(ceil(gamma exp(S_ema)), chi_min, chi_max)
+tna_status entropy_update(const tna_pid_params *p, double gamma, tna_pid_state *st, double s_raw, int *chi_next,
+                          double *terms) {
+  if (!p || !st) {
+    set_error("entropy rule: null argument");
+    return TNA_ERR_ARG;
+  }
+  if (p->chi_min < 1 || p->chi_max < p->chi_min || !(gamma >= 1.0) || !std::isfinite(gamma)) {
+    set_error("entropy rule: need 1 <= chi_min <= chi_max and a finite gamma >= 1");
+    return TNA_ERR_ARG;
+  }
+  if (!std::isfinite(s_raw)) {
+    set_error("entropy rule: non-finite entropy");
+    return TNA_ERR_NONFINITE;
+  }
+  const bool first = st->visits == 0;
+  const double prev = first ? (p->ema_init_zero ? 0.0 : s_raw) : st->s_ema;
+  double sbar;
+  if (first && !p->ema_init_zero) sbar = s_raw;
+  else {
+    const double fresh = p->alpha * s_raw;
+    const double old = (1.0 - p->alpha) * prev;
+    sbar = fresh + old;
+  }
+  const double target = std::ceil(gamma * std::exp(sbar));
+  long chi = target < (double)p->chi_min ? p->chi_min : target > (double)p->chi_max ? p->chi_max : (long)target;
+  st->s_ema_prev = first ? sbar : st->s_ema;
+  st->s_ema = sbar;
+  st->chi = (int)chi;
+  st->visits += 1;
+  if (chi_next) *chi_next = (int)chi;
+  if (terms) {
+    terms[0] = terms[1] = terms[2] = terms[3] = terms[5] = 0.0;
+    terms[4] = sbar;
+  }
+  return TNA_OK;
+}
 #pragma clang fp contract(on)
 
 }  // namespace tna
@@ -712,6 +750,11 @@ tna_status tna_set_workspace(tna_ctx c, void *dev_ptr, size_t bytes) {
 tna_status tna_pid_chi_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next,
                               double *terms) {
   return pid_update(p, st, s_raw, chi_next, terms);
+}
+
+tna_status tna_entropy_chi_update(const tna_pid_params *p, double gamma, tna_pid_state *st, double s_raw,
+                                  int *chi_next) {
+  return entropy_update(p, gamma, st, s_raw, chi_next, nullptr);
 }
 
 }  // extern "C"

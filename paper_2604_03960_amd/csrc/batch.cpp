@@ -188,6 +188,7 @@ int parts_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 512));
 }
 
+constexpr int SPEC = 32;                    // doubles per spectrum record (the SVD writes 0..24)
 constexpr int LZ_SMALL_N = 4096;            // longest theta of the single-workgroup Lanczos path
 constexpr int NT_SMALL = 512;               // its workgroup size
 constexpr size_t LZ_SLOT = 128;             // per-chain h1/h2/y/nrm2 slots
@@ -234,12 +235,12 @@ tna_status engine_create(int nslot, tna_engine *out) {
   TNA_TRY(e->ints.ensure(sizeof(int) * 2 * nslot));
   TNA_TRY(e->dbl.ensure(sizeof(double) * 2 * nslot));
   TNA_TRY(e->lzst.ensure(sizeof(double) * (LZ_PER + 2 * LZ_PART) * nslot));
-  TNA_TRY(e->spec.ensure(sizeof(double) * 24 * nslot));
+  TNA_TRY(e->spec.ensure(sizeof(double) * SPEC * nslot));
   TNA_TRY(e->feat_d.ensure(sizeof(float) * 32 * nslot));
   TNA_TRY(e->y_d.ensure(sizeof(float) * 4 * nslot));
   e->hflags.assign(2 * (size_t)nslot, 0);
   e->lz_last.assign(nslot, 0);
-  TNA_HIP(hipHostMalloc((void **)&e->h_dbl, sizeof(double) * (24 * nslot + 2 * nslot + 16), hipHostMallocDefault));
+  TNA_HIP(hipHostMalloc((void **)&e->h_dbl, sizeof(double) * (SPEC * nslot + 2 * nslot + 16), hipHostMallocDefault));
   TNA_HIP(hipHostMalloc((void **)&e->h_feat, sizeof(float) * 32 * nslot, hipHostMallocDefault));
   TNA_TRY(e->recs.ensure(sizeof(double) * 2 * LZ_HMAX * nslot));
   TNA_HIP(hipHostMalloc((void **)&e->h_rec, sizeof(double) * 2 * LZ_HMAX * nslot, hipHostMallocDefault));
@@ -780,8 +781,9 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       a.S = sp;
       Sq[q] = sp;
       sp += a.R;
-      a.spec = en->spec.as<double>() + 24 * q;
+      a.spec = en->spec.as<double>() + SPEC * q;
       a.eps_target = ch[q]->opts.eps_target > 0 ? ch[q]->opts.eps_target : 1e-8;
+      a.thr = ch[q]->opts.chi_rule == TNA_CHI_THRESHOLD ? ch[q]->opts.rule_param : 0.0;
       a.out_type = TNA_F64;
     }
   }
@@ -789,11 +791,11 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   tna_status sst = svd_group_run(mats, en->svd, ch[0]->opts.svd_max_sweeps, sweeps, s, true);
   if (sst != TNA_OK && sst != TNA_ERR_NOCONV) return sst;
   if (sst == TNA_ERR_NOCONV && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
-  TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
+  TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * SPEC * nc, hipMemcpyDeviceToHost, s));
   TNA_HIP(hipStreamSynchronize(s));
   for (int q = 0; q < nc; ++q)  // single-workgroup Jacobi paths: sweeps and convergence from spec[7]
     if (mats[q].fused) {
-      const double f = en->h_dbl[24 * q + 7];
+      const double f = en->h_dbl[SPEC * q + 7];
       sweeps[q] = (int)std::fabs(f);
       if (f < 0.0 && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
     }
@@ -804,10 +806,14 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   for (int q = 0; q < nc; ++q) {
     tna_dmrg dm = ch[q];
     const Visit &v = vs[q];
-    const double *h = en->h_dbl + 24 * q;
+    const double *h = en->h_dbl + SPEC * q;
     const double Sent = h[1];
     kneed[q] = (int)h[6];
-    TNA_TRY(pid_update(&dm->pid, &dm->st[v.b], Sent, &chi_next[q], &terms[6 * q]));
+    // rank rule: Algorithm 2 (PID, also run and logged under the threshold rule) or Algorithm 1
+    if (dm->opts.chi_rule == TNA_CHI_ENTROPY)
+      TNA_TRY(entropy_update(&dm->pid, dm->opts.rule_param, &dm->st[v.b], Sent, &chi_next[q], &terms[6 * q]));
+    else
+      TNA_TRY(pid_update(&dm->pid, &dm->st[v.b], Sent, &chi_next[q], &terms[6 * q]));
     // scheduler inputs: EMA history (oldest first, padded with the oldest),
     // 16 largest log sigma (floored at ln 1e-16), relative bond position
     auto &hb = dm->hist[v.b];
@@ -826,7 +832,9 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     }
     f[24] = (float)((v.b + 1.0) / dm->N);
     int keep = dm->opts.fixed_chi > 0 ? dm->opts.fixed_chi : chi_next[q];
-    if (dm->sched && dm->opts.fixed_chi <= 0 && dm->pred[v.b] > 0) {
+    if (dm->opts.fixed_chi <= 0 && dm->opts.chi_rule == TNA_CHI_THRESHOLD)  // min(chi_max, r), r >= 1
+      keep = std::min(dm->pid.chi_max, std::max(1, (int)h[24]));
+    if (dm->sched && dm->opts.fixed_chi <= 0 && dm->opts.chi_rule == TNA_CHI_PID && dm->pred[v.b] > 0) {
       chs[q] = dm->pred[v.b];
       if (std::min(chs[q], mats[q].R) < std::min(kneed[q], mats[q].R)) fb[q] = 1;  // would miss eps_target
       else keep = chs[q];
@@ -920,10 +928,10 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     }
   }
   // per-visit records: truncation sums of the outputs pass and the last kept value
-  TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * 24 * nc, hipMemcpyDeviceToHost, s));
+  TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * SPEC * nc, hipMemcpyDeviceToHost, s));
   std::vector<double> slast(nc, 0.0);
   for (int q = 0; q < nc; ++q)
-    TNA_HIP(hipMemcpyAsync(en->h_dbl + 24 * nc + q, Sq[q] + (kk[q] - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+    TNA_HIP(hipMemcpyAsync(en->h_dbl + SPEC * nc + q, Sq[q] + (kk[q] - 1), sizeof(double), hipMemcpyDeviceToHost, s));
   TNA_HIP(hipStreamSynchronize(s));
   auto t3 = std::chrono::steady_clock::now();
   const double mL = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -937,14 +945,14 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     tna_visit_log *rp = logs.empty() ? nullptr : logs[q];
     if (!rp) continue;
     tna_visit_log &r = *rp;
-    const double *h = en->h_dbl + 24 * q;
+    const double *h = en->h_dbl + SPEC * q;
     const double *tm = &terms[6 * q];
     std::memset(&r, 0, sizeof r);
     r.sweep = ch[q]->sweeps_done; r.dir = vs[q].half; r.bond = vs[q].b; r.m = vs[q].m; r.n = vs[q].n;
     r.k = kk[q]; r.chi_ctrl = chi_next[q]; r.lanczos_iters = iters[q]; r.svd_sweeps = sweeps[q];
     r.lanczos_ok = conv[q]; r.E = Ec[q]; r.S = h[1]; r.S_ema = tm[4]; r.eps = h[2]; r.wdisc = h[3];
     r.gap = h[5]; r.P = tm[0]; r.I = tm[1]; r.D = tm[2]; r.u = tm[3]; r.sigma0 = h[8];
-    r.sigma_last = en->h_dbl[24 * nc + q];
+    r.sigma_last = en->h_dbl[SPEC * nc + q];
     r.ms_lanczos = mL; r.ms_svd = mS; r.ms_other = mE;
     r.k_needed = kneed[q]; r.chi_sched = chs[q]; r.fallback = fb[q];
     for (int i = 0; i < 25; ++i) r.feat[i] = en->h_feat[32 * q + i];

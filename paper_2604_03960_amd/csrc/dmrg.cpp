@@ -101,6 +101,12 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
     set_error("dmrg_create: heff_prec must be F64 or F32");
     return TNA_ERR_ARG;
   }
+  if (o.chi_rule < TNA_CHI_PID || o.chi_rule > TNA_CHI_ENTROPY ||
+      (o.chi_rule == TNA_CHI_THRESHOLD && !(o.rule_param > 0.0)) ||
+      (o.chi_rule == TNA_CHI_ENTROPY && !(o.rule_param >= 1.0))) {
+    set_error("dmrg_create: chi_rule needs eps_trunc > 0 (threshold) or gamma >= 1 (entropy)");
+    return TNA_ERR_ARG;
+  }
   dm->opts = o;
   dm->chi.assign(chi_init, chi_init + N - 1);
   dm->st.assign(N - 1, tna_pid_state{0, 0, 0, 0, pid->chi_min, 0});

@@ -159,10 +159,11 @@ struct SvdMat {
   int k, dtype, out_type, scale_mode;         // kept rank; scale 0 none, 1 Vt rows, 2 U columns by S_j/|S_k|
   int inner_max, fused;                        // cap on inner Jacobi sweeps; whole Jacobi in one workgroup
   double tol, eps_target;
+  double thr;                                  // > 0: spec[24] = number of values above thr (spec holds 32)
   const void *A;                               // m x n (dtype)
   double *bw, *jt, *gram, *qt, *sig;           // work
   double *S;                                   // R sorted values (output)
-  double *spec;                                // 24 doubles: Z, S_vN, eps, eps^2/Z, |S_k|, gap, k_needed, -, S_0..S_15
+  double *spec;                                // 24 doubles: Z, S_vN, eps, eps^2/Z, |S_k|, gap, k_needed, sweeps, S_0..S_15
   int *skip, *perm, *ctr;                      // work
   void *U, *Vt;                                // m x k, k x n (out_type)
   double *fro2;                                // work: |A|_F^2 (device scalar)
@@ -258,6 +259,8 @@ tna_status env_left(int chl, int k, int d, int D, const double *L, const double 
 tna_status env_right(int k, int chr, int d, int D, const double *R, const double *Mr, const double *B, double *T1,
                      double *T2, double *Rn, hipStream_t s);
 tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next, double *terms);
+tna_status entropy_update(const tna_pid_params *p, double gamma, tna_pid_state *st, double s_raw, int *chi_next,
+                          double *terms);
 tna_status mlp_forward_dev(tna_mlp n, int B, const float *X, float *y);
 
 }  // namespace tna

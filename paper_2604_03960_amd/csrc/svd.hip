@@ -898,6 +898,20 @@ __global__ __launch_bounds__(1024) void sort_kernel(const SvdMat *mats) {
   if (threadIdx.x < 16) a.spec[8 + threadIdx.x] = (int)threadIdx.x < a.R ? key[threadIdx.x] : 0.0;
   // spec[7]: sweeps of the single-workgroup Jacobi paths, negative when not converged (0 otherwise)
   if (threadIdx.x == 0) a.spec[7] = a.fused ? (a.ctr[0] ? -(double)a.ctr[1] : (double)a.ctr[1]) : 0.0;
+  // spec[24] (thr > 0 only): how many values exceed thr, for threshold truncation
+  if (a.thr > 0.0) {
+    __shared__ int cnt_w[16];
+    int cnt = 0;
+    for (int i = threadIdx.x; i < a.R; i += 1024) cnt += key[i] > a.thr;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) cnt_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int c = 0;
+      for (int w = 0; w < 16; ++w) c += cnt_w[w];
+      a.spec[24] = (double)c;
+    }
+  }
   // spec[6]: smallest k >= 1 with sqrt(sum_{j>=k} S_j^2) <= eps_target (k = R always qualifies)
   if (a.eps_target > 0.0) {
     __shared__ double csum[1024];

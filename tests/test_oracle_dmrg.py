@@ -78,3 +78,38 @@ def test_critical_ising_paper_value():
     closed = (1 - 1 / math.sin(math.pi / (2 * (2 * 20 + 1)))) / 20
     assert abs(e - closed) <= 1e-8
     assert round(e, 5) == -1.25539
+
+
+def _run_rule(N, chi_min, chi_max, sweeps, chi_rule, rule_param):
+    W = oracle.mpo(0, N, HEIS)
+    A, chi, _ = synth.random_mps(N, 2, chi_min, 0)
+    pp = oracle.pid_params(0.5, 0.05, 0.1, 0.5, 0.3, chi_min, chi_max)
+    return pp, oracle.dmrg_run(W, A, chi, pp, sweeps, chi_rule=chi_rule, rule_param=rule_param)
+
+
+def test_threshold_rule_tiny_eps_is_exact():
+    # standard rule chi_k = min(chi_max, r), r = #{sigma > eps_trunc} (Sec. 10): with eps_trunc far
+    # below every nonzero value nothing is truncated, so the sweep reaches the exact ground state
+    _, r = _run_rule(12, 8, 64, 3, 1, 1e-300)
+    assert abs(r["E"][-1] - E12) <= 1e-10 * abs(E12)
+
+
+def test_threshold_rule_keeps_values_above_eps():
+    eps = 1e-3
+    _, r = _run_rule(12, 8, 64, 3, 1, eps)
+    for rec in r["log"]:
+        if rec["k"] < min(rec["m"], rec["n"]) and rec["k"] < 64:
+            assert rec["sigma_kept_last"] > eps  # every kept value exceeds eps_trunc
+    assert r["E"][-1] >= E12 - 1e-12 and r["E"][-1] - E12 < 1e-4 * abs(E12)
+
+
+def test_entropy_rule_large_margin_is_exact_and_decisions_replay():
+    # gamma large enough that ceil(gamma e^S) >= chi_max = 64 >= every rank of N = 12: exact
+    _, r = _run_rule(12, 8, 64, 3, 2, 64.0)
+    assert abs(r["E"][-1] - E12) <= 1e-10 * abs(E12)
+    # gamma = 2: every logged decision is Algorithm 1 replayed on the logged entropies
+    pp, r = _run_rule(12, 4, 32, 3, 2, 2.0)
+    states = [oracle.PidState() for _ in range(11)]
+    for rec in r["log"]:
+        c, _ = oracle.entropy_chi_update(pp, 2.0, states[int(rec["bond"])], rec["S"])
+        assert c == rec["chi_ctrl"] and rec["k"] == min(c, rec["m"], rec["n"])

@@ -84,3 +84,33 @@ def test_bethe_trend():
     M = np.array([[n, 1.0, 1.0 / n] for n in Ns])
     a, b, c = np.linalg.lstsq(M, np.array(Es), rcond=None)[0]
     assert abs(a - g["value"]) <= 1e-3
+
+
+def tfim_free_fermion_energy(N, J, h):
+    """Ground energy of the open chain H = -J sum sz sz - h sum sx (Pauli) from its free-fermion form
+    (Jordan-Wigner; Lieb, Schultz and Mattis 1961): quadratic form with A_ii = 2h, A_{i,i+1} = -J,
+    B_{i,i+1} = -B_{i+1,i} = -J; E0 = -(1/2) sum_k Lambda_k with Lambda_k^2 the eigenvalues of
+    (A - B)(A + B)."""
+    A = np.zeros((N, N))
+    B = np.zeros((N, N))
+    for i in range(N):
+        A[i, i] = 2.0 * h
+    for i in range(N - 1):
+        A[i, i + 1] = A[i + 1, i] = -J
+        B[i, i + 1], B[i + 1, i] = -J, J
+    lam2 = np.linalg.eigvalsh((A - B) @ (A + B))
+    return -0.5 * float(np.sum(np.sqrt(np.abs(lam2))))
+
+
+@pytest.mark.parametrize("N,J,h", [(6, 1.0, 0.7), (9, 0.6, 0.25), (10, 1.0, 1.3)])
+def test_tfim_ed_equals_free_fermions(N, J, h):
+    E = oracle.ed_ground(2, N, [J, h])[0]
+    assert abs(E - tfim_free_fermion_energy(N, J, h)) <= 1e-10 * abs(E)
+
+
+def test_tfim_critical_free_fermions_closed_form():
+    # at J = h the single-particle energies are 4 sin((2k-1) pi / (2(2N+1))), k = 1..N, so
+    # E0 = 1 - 1 / sin(pi / (2(2N+1))): checks the numerical free-fermion form itself
+    import math
+    for N in (5, 20, 40):
+        assert abs(tfim_free_fermion_energy(N, 1.0, 1.0) - (1 - 1 / math.sin(math.pi / (2 * (2 * N + 1))))) < 1e-11

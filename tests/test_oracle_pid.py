@@ -64,3 +64,30 @@ def test_predictor_beta():
     assert out[0][1]["u"] == pytest.approx(1.0)
     assert out[1][1]["e"] == pytest.approx(2.8)
     assert out[1][0] == 51 + 3
+
+
+# ---- Algorithm 1 (Sec. 4, Eq. 6-8): chi = clamp(ceil(gamma exp(S_ema)), chi_min, chi_max)
+def test_entropy_rule_hand_values():
+    import math
+    pp = oracle.pid_params(0.0, 0.0, 0.0, 0.0, 0.3, 4, 64)
+    st = oracle.PidState()
+    st.chi = 4
+    chi, sbar = oracle.entropy_chi_update(pp, 1.5, st, 1.0)  # first visit seeds the EMA: 1.5 e = 4.08 -> 5
+    assert sbar == 1.0 and chi == 5
+    chi, sbar = oracle.entropy_chi_update(pp, 1.5, st, 2.0)  # 0.3*2 + 0.7*1 = 1.3; 1.5 e^1.3 = 5.50 -> 6
+    assert abs(sbar - 1.3) < 1e-15 and chi == 6
+    chi, sbar = oracle.entropy_chi_update(pp, 1.5, st, 12.0)  # 3.6 + 0.91 = 4.51; 1.5 e^4.51 = 136 -> 64
+    assert abs(sbar - 4.51) < 1e-14 and chi == 64
+    chi, _ = oracle.entropy_chi_update(pp, 2.5, oracle.PidState(), 0.0)  # product state: ceil(2.5) = 3 -> 4
+    assert chi == 4
+    # ten equal Schmidt weights: S = ln 10, so chi >= e^S = 10 (Eq. 6); margin 1.05 -> ceil(10.5) = 11
+    chi, _ = oracle.entropy_chi_update(pp, 1.05, oracle.PidState(), math.log(10.0))
+    assert chi == 11
+
+
+def test_entropy_rule_ema_zero_seed_and_bad_margin():
+    pp = oracle.pid_params(0.0, 0.0, 0.0, 0.0, 0.5, 1, 100, ema_init_zero=True)
+    chi, sbar = oracle.entropy_chi_update(pp, 1.0, oracle.PidState(), 2.0)  # 0.5*2 + 0.5*0 = 1; ceil(e) = 3
+    assert sbar == 1.0 and chi == 3
+    with pytest.raises(ValueError):
+        oracle.entropy_chi_update(pp, 0.9, oracle.PidState(), 1.0)  # the margin must be >= 1
