@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--roofline-kernel", default="", help="kernel-name prefix to time (default: auto)")
-    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd", "fixed_chi", "scheduler"],
+    ap.add_argument("--workload", choices=["heisenberg100", "xxz_batch", "svd", "fixed_chi", "scheduler", "rules"],
                     default="heisenberg100")
     ap.add_argument("--chi", type=int, default=256, help="fixed_chi: bond dimension")
     ap.add_argument("--matvecs", type=int, default=20, help="fixed_chi: H_eff applications per visit")
@@ -269,6 +269,47 @@ def run_scheduler(a):
     print(json.dumps(out))
 
 
+def run_rules(a):
+    """The rank rules side by side (the paper's ablation, Sec. 13): Heisenberg chain, chi_max = 64,
+    5 sweeps from the same initial MPS under fixed chi, the PID (Algorithm 2), the threshold rule
+    (eps_trunc = 1e-10) and Algorithm 1 (gamma = 1.5).  Wall time per run, E/N, mean and max kept chi."""
+    import numpy as np
+    import torch
+
+    import paper_2604_03960_amd as tna
+    import synth
+    ctx = tna.Context(0)
+    out_runs = {}
+    for N in (20, a.N):
+        W = tna.mpo_build(tna.MODEL_XXZ, N, [1.0, 1.0, 0.0])
+        A, chi, _ = synth.random_mps(N, 2, 4, seed=1)
+        pid = tna.pid_params(2.0, 0.1, 0.5, 0.5, 0.3, 4, 64)
+        rules = {"fixed_chi64": dict(fixed_chi=64), "pid": dict(),
+                 "threshold_1e-10": dict(chi_rule=tna.CHI_THRESHOLD, rule_param=1e-10),
+                 "alg1_gamma1.5": dict(chi_rule=tna.CHI_ENTROPY, rule_param=1.5)}
+        for name, kw in rules.items():
+            dm = tna.Dmrg(ctx, W, A, chi, pid, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(5):
+                E, recs, st = dm.sweep()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ks = np.array([r["k"] for r in recs[-(N - 1):]])
+            out_runs[f"N{N}_{name}"] = {"s": dt, "E_per_site": E / N, "chi_mean": float(ks.mean()),
+                                        "chi_max": int(ks.max())}
+            dm.close()
+            progress(f"N {N} {name} done")
+    base = {N: out_runs[f"N{N}_fixed_chi64"]["s"] for N in (20, a.N)}
+    for k, v in out_runs.items():
+        v["speedup_vs_fixed"] = base[int(k.split("_")[0][1:])] / v["s"]
+    out = {"metric": "5-sweep wall time per rank rule (fixed chi 64 = 1.0x)", "value": out_runs["N20_pid"]["speedup_vs_fixed"],
+           "unit": "x vs fixed chi (N=20 PID)", "n_gpus": 1, "steps": 5, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"heisenberg_rules_N20_N{a.N}_chimax64"}, "runs": out_runs}
+    print(json.dumps(out))
+
+
 def run_svd(a):
     """Isolated truncated SVDs of n x n matrices with spectrum exp(-k/tau), keep n/2."""
     import numpy as np
@@ -334,6 +375,8 @@ def main():
         return run_fixed_chi(a)
     if a.workload == "scheduler":
         return run_scheduler(a)
+    if a.workload == "rules":
+        return run_rules(a)
     import numpy as np
     import torch
 
