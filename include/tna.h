@@ -124,7 +124,8 @@ tna_status tna_svd_truncate_batched(tna_ctx ctx, int batch, int m, int n, int dt
                                     int64_t strideVt, double *spec, int *sweeps_out);
 
 /* ---------------------------------------------------------------- controller */
-/* EMA (Eq. 8), optional linear predictor (Eq. 16, beta > 0) and PID with
+/* EMA (Eq. 8), optional linear predictor (Eq. 16, beta > 0) and its second-order
+ * extension (Sec. 7, beta2 > 0), then PID with
  * anti-windup (Eq. 9-11, Algorithm 2), one call per bond visit.
  * First visit: the EMA starts at S (or at 0 with ema_init_zero) and the
  * previous error equals the current one.  Rounding is to nearest, ties to
@@ -134,6 +135,8 @@ tna_status tna_svd_truncate_batched(tna_ctx ctx, int batch, int m, int n, int dt
 typedef struct {
   double kp, ki, kd, s_target, alpha, beta;
   int chi_min, chi_max, ema_init_zero, pad;
+  double beta2; /* second-order predictor (Sec. 7): adds beta2 (S(t) - 2 S(t-1) + S(t-2)) of the EMA
+                   to the predicted entropy from a bond's third visit on; 0 = off */
 } tna_pid_params;
 
 typedef struct {

@@ -405,6 +405,7 @@ void or_spectrum(int R, const double *S, int k, double *out) {
 typedef struct {
   double kp, ki, kd, s_target, alpha, beta;
   int chi_min, chi_max, ema_init_zero, pad;
+  double beta2; /* weight of the curvature term of the second-order predictor (Sec. 7) */
 } or_pid_params;
 
 typedef struct {
@@ -430,6 +431,13 @@ int or_pid_update(const or_pid_params *pp, or_pid_state *st, double s_raw, int *
     double trend = sbar - sbar_prev;
     double ext = pp->beta * trend;
     sig = sbar + ext;
+  }
+  /* second-order predictor (Sec. 7): + beta2 (Sbar(t) - 2 Sbar(t-1) + Sbar(t-2)), from the
+   * third visit on (s_ema_prev holds Sbar(t-2) before this update) */
+  if (pp->beta2 > 0.0 && st->visits >= 2) {
+    double curv = (sbar - 2.0 * sbar_prev) + st->s_ema_prev;
+    double ext2 = pp->beta2 * curv;
+    sig = sig + ext2;
   }
   double e = sig - pp->s_target;
   double e_prev = first ? e : st->e_prev;

@@ -47,7 +47,7 @@ _lib = C.CDLL(LIB_PATH)
 class PidParams(C.Structure):
     _fields_ = [("kp", C.c_double), ("ki", C.c_double), ("kd", C.c_double), ("s_target", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("chi_min", C.c_int), ("chi_max", C.c_int),
-                ("ema_init_zero", C.c_int), ("pad", C.c_int)]
+                ("ema_init_zero", C.c_int), ("pad", C.c_int), ("beta2", C.c_double)]
 
 
 class PidState(C.Structure):
@@ -157,8 +157,9 @@ def mpo_build(model: int, N: int, params) -> np.ndarray:
     return W
 
 
-def pid_params(kp, ki, kd, s_target, alpha, chi_min, chi_max, beta=0.0, ema_init_zero=False) -> PidParams:
-    return PidParams(kp, ki, kd, s_target, alpha, beta, chi_min, chi_max, int(ema_init_zero), 0)
+def pid_params(kp, ki, kd, s_target, alpha, chi_min, chi_max, beta=0.0, ema_init_zero=False,
+               beta2=0.0) -> PidParams:
+    return PidParams(kp, ki, kd, s_target, alpha, beta, chi_min, chi_max, int(ema_init_zero), 0, beta2)
 
 
 def entropy_chi_update(pp: PidParams, gamma: float, st: PidState, s_raw: float) -> int:

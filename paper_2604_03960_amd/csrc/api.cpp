@@ -349,6 +349,13 @@ tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, 
     const double ahead = p->beta * slope;
     signal = sbar + ahead;
   }
+  // second-order predictor (Sec. 7): the EMA's curvature, from the third visit on (s_ema_prev
+  // holds the EMA two visits back until this update)
+  if (p->beta2 > 0.0 && st->visits >= 2) {
+    const double curv = (sbar - 2.0 * prev) + st->s_ema_prev;
+    const double extra = p->beta2 * curv;
+    signal = signal + extra;
+  }
   const double e = signal - p->s_target;
   const double e_last = first ? e : st->e_prev;
   // Algorithm 2

@@ -98,3 +98,27 @@ def test_tfim_n60_critical_closed_form():
     dm.close()
     closed = 1 - 1 / math.sin(math.pi / (2 * (2 * N + 1)))
     assert E >= closed - 1e-9 and (E - closed) / N < 1e-7, (E, closed)
+
+
+def test_second_order_predictor_matches_oracle():
+    # PID with the linear and second-order predictors (beta 0.4, beta2 0.3): visit-by-visit parity
+    import paper_2604_03960_amd as tna
+    N, gains = 16, (2.0, 0.1, 0.5)
+    W = oracle.mpo(0, N, [1.0, 1.0, 0.0])
+    A, chi, _ = synth.random_mps(N, 2, 4, 0)
+    ro = oracle.dmrg_run(W, A, chi, oracle.pid_params(*gains, 0.5, 0.3, 4, 48, beta=0.4, beta2=0.3), 3)
+    dm = tna.Dmrg(ctx(), W, A, chi, tna.pid_params(*gains, 0.5, 0.3, 4, 48, beta=0.4, beta2=0.3))
+    logs, Es = [], []
+    for _ in range(3):
+        E, recs, st = dm.sweep()
+        Es.append(E)
+        logs += recs
+    dm.close()
+    _compare(ro, np.array(Es), logs, 1e-10)
+    rng = np.random.default_rng(11)
+    pg, po = tna.pid_params(*gains, 1.0, 0.3, 4, 256, beta=0.4, beta2=0.3), \
+        oracle.pid_params(*gains, 1.0, 0.3, 4, 256, beta=0.4, beta2=0.3)
+    sg, so = tna.PidState(), oracle.PidState()
+    sg.chi = so.chi = 4
+    for s in rng.uniform(0.0, 4.0, 200):
+        assert tna.pid_chi_update(pg, sg, float(s))[0] == oracle.pid_update(po, so, float(s))[0]

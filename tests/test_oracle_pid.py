@@ -91,3 +91,23 @@ def test_entropy_rule_ema_zero_seed_and_bad_margin():
     assert sbar == 1.0 and chi == 3
     with pytest.raises(ValueError):
         oracle.entropy_chi_update(pp, 0.9, oracle.PidState(), 1.0)  # the margin must be >= 1
+
+
+def test_second_order_predictor():
+    # Sec. 7: S_hat = Sbar + beta (Sbar - Sbar(t-1)) + beta2 (Sbar - 2 Sbar(t-1) + Sbar(t-2)), the
+    # curvature from the third visit on.  alpha = 1 makes Sbar = S; S = t^2 is then extrapolated
+    # exactly one visit ahead with beta = beta2 = 1 (Newton's backward form of the parabola).
+    pp = oracle.pid_params(1.0, 0.0, 0.0, 0.0, 1.0, 1, 1000, beta=1.0, beta2=1.0)
+    _, out = _run(pp, [0.0, 1.0, 4.0, 9.0], chi0=500)
+    # visits: no trend (0); 1 + 1 (no curvature yet); 4 + 3 + 2 = 9; 9 + 5 + 2 = 16
+    assert [o[1]["e"] for o in out] == pytest.approx([0.0, 2.0, 9.0, 16.0])
+
+
+def test_second_order_off_is_linear():
+    seq = [0.3, 0.9, 1.4, 1.6, 1.65]
+    lin = _run(oracle.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 4, 64, beta=0.5), seq)[1]
+    off = _run(oracle.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 4, 64, beta=0.5, beta2=0.0), seq)[1]
+    on = _run(oracle.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 4, 64, beta=0.5, beta2=0.7), seq)[1]
+    assert [o[1]["e"] for o in lin] == [o[1]["e"] for o in off]
+    assert [o[1]["e"] for o in on][:2] == [o[1]["e"] for o in lin][:2]  # no curvature before visit 3
+    assert [o[1]["e"] for o in on][2:] != [o[1]["e"] for o in lin][2:]
