@@ -283,21 +283,25 @@ def run_rules(a):
     for N in (20, a.N):
         W = tna.mpo_build(tna.MODEL_XXZ, N, [1.0, 1.0, 0.0])
         A, chi, _ = synth.random_mps(N, 2, 4, seed=1)
-        pid = tna.pid_params(2.0, 0.1, 0.5, 0.5, 0.3, 4, 64)
         rules = {"fixed_chi64": dict(fixed_chi=64), "pid": dict(),
                  "threshold_1e-10": dict(chi_rule=tna.CHI_THRESHOLD, rule_param=1e-10),
-                 "alg1_gamma1.5": dict(chi_rule=tna.CHI_ENTROPY, rule_param=1.5)}
+                 "alg1_gamma1.5": dict(chi_rule=tna.CHI_ENTROPY, rule_param=1.5),
+                 "pid_gains_x0.5": dict(gain_scale=0.5), "pid_gains_x1.5": dict(gain_scale=1.5)}
         for name, kw in rules.items():
-            dm = tna.Dmrg(ctx, W, A, chi, pid, **kw)
+            g = kw.pop("gain_scale", 1.0)  # the paper's +-50% robustness check scales all three gains
+            pp = tna.pid_params(2.0 * g, 0.1 * g, 0.5 * g, 0.5, 0.3, 4, 64)
+            dm = tna.Dmrg(ctx, W, A, chi, pp, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            Es = []
             for i in range(5):
                 E, recs, st = dm.sweep()
+                Es.append(E / N)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ks = np.array([r["k"] for r in recs[-(N - 1):]])
             out_runs[f"N{N}_{name}"] = {"s": dt, "E_per_site": E / N, "chi_mean": float(ks.mean()),
-                                        "chi_max": int(ks.max())}
+                                        "chi_max": int(ks.max()), "E_per_site_by_sweep": Es}
             dm.close()
             progress(f"N {N} {name} done")
     base = {N: out_runs[f"N{N}_fixed_chi64"]["s"] for N in (20, a.N)}
