@@ -383,7 +383,11 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
   constexpr int NW = NTS / 64;
   const int D = p.D, DD = D * dd;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int chl = p.chl, chr = p.chr, ac = p.ac;
+  const int chl = p.chl, chr = p.chr, ac = p.ac, kmax = p.kmax;
+  // descriptor fields in registers: the stores into the basis below could alias the descriptor for
+  // the compiler, which would otherwise reload them from memory inside the iteration loop
+  double *const V = p.V;
+  double *const rec = p.rec;
   const int n = chl * dd * chr, nr = dd * chr;
   // Rows that the MFMA operand reads walk down (sixteen lanes, one row each) are stored with an
   // odd stride in doubles, so those lanes fall on distinct LDS banks.
@@ -402,9 +406,9 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
   for (int e = tid; e < chr * D * chr; e += NTS) Rs[(e / (D * chr)) * ldr + e % (D * chr)] = p.R[e];
   for (int e = tid; e < DD * DD; e += NTS) Ms[(e / DD) * ldm + e % DD] = p.M[e];
   int j = *p.j;
-  for (int it = 0; it < iters && j < p.kmax; ++it) {
-    const double *vj = p.V + (int64_t)j * n;
-    double *vn = p.V + (int64_t)(j + 1) * n;
+  for (int it = 0; it < iters && j < kmax; ++it) {
+    const double *vj = V + (int64_t)j * n;
+    double *vn = V + (int64_t)(j + 1) * n;
     __syncthreads();  // previous iteration done with th, wv and hb
     for (int e = tid; e < n; e += NTS) th[e] = vj[e];
     __syncthreads();
@@ -449,8 +453,8 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
       double *h = hb + pass * LZ_HMAX;
       for (int i = wave; i <= j; i += 2 * NW) {
         const bool two = i + NW <= j;
-        const double2 *va = reinterpret_cast<const double2 *>(p.V + (int64_t)i * n);
-        const double2 *vb = reinterpret_cast<const double2 *>(p.V + (int64_t)(two ? i + NW : i) * n);
+        const double2 *va = reinterpret_cast<const double2 *>(V + (int64_t)i * n);
+        const double2 *vb = reinterpret_cast<const double2 *>(V + (int64_t)(two ? i + NW : i) * n);
         double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
         int e = lane;
         for (; e + 192 < n2; e += 256) {
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
       __syncthreads();
       double loc = 0.0;
       for (int e = tid; e < n2; e += NTS) {
-        const double2 *ve = reinterpret_cast<const double2 *>(p.V) + e;
+        const double2 *ve = reinterpret_cast<const double2 *>(V) + e;
         double2 acc = {0.0, 0.0};
         int i = 0;
         for (; i + 16 <= j + 1; i += 16) {
@@ -523,8 +527,8 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
       else __syncthreads();
     }
     if (tid == 0) {
-      p.rec[2 * j] = hb[j];  // alpha_j from the first pass
-      p.rec[2 * j + 1] = b2;
+      rec[2 * j] = hb[j];  // alpha_j from the first pass
+      rec[2 * j + 1] = b2;
     }
     // the host stops a chain at beta_j < 1e-14 (or a non-finite record): same predicate here
     const double beta = sqrt(b2);
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
   }
   if (tid == 0) {
     *p.j = j;
-    p.rec[2 * LZ_HMAX - 1] = (double)j;  // read back with the records (they end below 2 LZ_HMAX - 2)
+    rec[2 * LZ_HMAX - 1] = (double)j;  // read back with the records (they end below 2 LZ_HMAX - 2)
   }
 }
 

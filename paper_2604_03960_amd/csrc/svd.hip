@@ -551,6 +551,7 @@ __global__ __launch_bounds__(256) void jacobi_tiny_kernel(const SvdMat *mats, in
   }
   (void)vs_dummy;
   const double floor2 = row_floor2(a, *a.fro2);
+  const double tol2 = a.tol * a.tol;  // read once: inside the rounds a descriptor load is a memory round trip
   const int nvp = R + (R & 1), P = nvp / 2;
   int sw = 0, conv = 0;
   __syncthreads();
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(256) void jacobi_tiny_kernel(const SvdMat *mats, in
       al = row16_sum(al);
       be = row16_sum(be);
       ga = row16_sum(ga);
-      if (i >= 0 && al > floor2 && be > floor2 && al > 0.0 && be > 0.0 && ga * ga > a.tol * a.tol * (al * be)) {
+      if (i >= 0 && al > floor2 && be > floor2 && al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be)) {
         double c, s;
         jacobi_rot(al, be, ga, c, s);
 #pragma unroll
