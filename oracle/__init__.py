@@ -20,9 +20,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", "-fno-fast-math"]
 
-LOG_FIELDS = 22
+LOG_FIELDS = 50
 LOG_NAMES = ["sweep", "dir", "bond", "m", "n", "k", "chi_ctrl", "E", "S", "S_ema", "eps", "wdisc", "gap",
-             "lanczos_iters", "svd_sweeps", "P", "I", "D", "u", "lanczos_ok", "sigma0", "sigma_kept_last"]
+             "lanczos_iters", "svd_sweeps", "P", "I", "D", "u", "lanczos_ok", "sigma0", "sigma_kept_last",
+             "k_needed", "chi_sched", "fallback"]  # then 25 scheduler inputs ("feat")
 
 MODEL_XXZ, MODEL_J1J2, MODEL_TFIM = 0, 1, 2
 
@@ -50,7 +51,8 @@ class PidState(C.Structure):
 class DmrgOpts(C.Structure):
     _fields_ = [("n_sweeps", C.c_int), ("lanczos_kmax", C.c_int), ("lanczos_restarts", C.c_int),
                 ("fixed_iters", C.c_int), ("lanczos_tol", C.c_double), ("fixed_chi", C.c_int), ("pad", C.c_int),
-                ("chi_rule", C.c_int), ("pad2", C.c_int), ("rule_param", C.c_double)]
+                ("chi_rule", C.c_int), ("pad2", C.c_int), ("rule_param", C.c_double),
+                ("eps_target", C.c_double), ("sched_pred", C.POINTER(C.c_int))]
 
 
 _lib = None
@@ -81,6 +83,11 @@ def lib():
         _lib.or_dmrg_run.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, ip, C.POINTER(PidParams),
                                      C.POINTER(DmrgOpts), dp, dp, ip, C.POINTER(PidState)]
         _lib.or_right_canonical.argtypes = [C.c_int, C.c_int, dp, ip, dp, ip]
+        _lib.or_sched_features.argtypes = [dp, C.c_int, dp, C.c_int, C.c_int, C.c_int, dp]
+        _lib.or_sched_features.restype = None
+        _lib.or_trunc_error.argtypes = [C.c_int, dp, C.c_int]
+        _lib.or_trunc_error.restype = C.c_double
+        _lib.or_k_needed.argtypes = [C.c_int, dp, C.c_double]
         _lib.or_mlp_forward.argtypes = [dp, C.c_int, dp, dp]
         _lib.or_mlp_forward.restype = None
         _lib.or_mlp_loss_grad.argtypes = [dp, C.c_int, dp, dp, dp]
@@ -248,20 +255,54 @@ def right_canonical(N, d, A_packed, chi):
 
 
 def dmrg_run(W, A_packed, chi_init, pp: PidParams, n_sweeps, lanczos_tol=1e-12, kmax=100, restarts=5,
-             fixed_iters=0, fixed_chi=0, chi_rule=0, rule_param=0.0):
-    """Runs the two-site DMRG; returns dict(log=[records], E=[per sweep], chi=[final], pid=[states], rc)."""
+             fixed_iters=0, fixed_chi=0, chi_rule=0, rule_param=0.0, eps_target=1e-8, sched_pred=None):
+    """Runs the two-site DMRG; returns dict(log=[records], E=[per sweep], chi=[final], pid=[states], rc).
+    sched_pred: optional rank proposal per visit in run order (0 = none), applied with the scheduler's
+    fallback rule (the proposals are inputs; no network runs here)."""
     W = _f64(W)
     N, D, _, d, _ = W.shape
-    opts = DmrgOpts(n_sweeps, kmax, restarts, fixed_iters, lanczos_tol, fixed_chi, 0, chi_rule, 0, rule_param)
     nrec = n_sweeps * 2 * (N - 1)
+    pred = None
+    if sched_pred is not None:
+        pred = np.ascontiguousarray(sched_pred, dtype=np.int32)
+        assert pred.shape == (nrec,)
+    opts = DmrgOpts(n_sweeps, kmax, restarts, fixed_iters, lanczos_tol, fixed_chi, 0, chi_rule, 0, rule_param,
+                    eps_target, _ip(pred) if pred is not None else None)
     log = np.zeros((nrec, LOG_FIELDS))
     E = np.zeros(n_sweeps)
     chi = np.zeros(N - 1, dtype=np.int32)
     pid = (PidState * (N - 1))()
     rc = lib().or_dmrg_run(N, d, D, _p(W), _p(_f64(A_packed)), _ip(np.asarray(chi_init, dtype=np.int32)),
                            C.byref(pp), C.byref(opts), _p(log), _p(E), _ip(chi), pid)
-    recs = [dict(zip(LOG_NAMES, row)) for row in log]
+    recs = []
+    for row in log:
+        r = dict(zip(LOG_NAMES, row))
+        r["feat"] = row[25:50].copy()
+        recs.append(r)
     return dict(log=recs, log_array=log, E=E, chi=chi, pid=pid, rc=rc)
+
+
+# ---------------------------------------------------------------- learned-scheduler inputs and labels
+def sched_features(ema_hist, S, bond: int, N: int) -> np.ndarray:
+    """The 25 scheduler inputs of one visit: last 8 EMA entropies of the bond (oldest first, front-padded
+    with the oldest), ln of the 16 largest singular values floored at ln 1e-16, (bond + 1) / N."""
+    h = _f64(ema_hist)
+    S = _f64(S)
+    f = np.zeros(25)
+    lib().or_sched_features(_p(h), len(h), _p(S), len(S), int(bond), int(N), _p(f))
+    return f
+
+
+def trunc_error(S, k: int) -> float:
+    """Eq. (4) with k values kept."""
+    S = _f64(S)
+    return float(lib().or_trunc_error(len(S), _p(S), int(k)))
+
+
+def k_needed(S, eps_target: float) -> int:
+    """Smallest k >= 1 whose truncation error (Eq. 4) is at most eps_target."""
+    S = _f64(S)
+    return int(lib().or_k_needed(len(S), _p(S), float(eps_target)))
 
 
 # ---------------------------------------------------------------- learned scheduler (MLP)

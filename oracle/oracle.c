@@ -793,13 +793,65 @@ typedef struct {
                     r = #{sigma > rule_param} (at least 1; Sec. 10); 2: Algorithm 1, gamma = rule_param */
   int pad2;
   double rule_param;
+  double eps_target;      /* truncation-error target of the learned scheduler's rule (> 0) */
+  const int *sched_pred;  /* NULL, or one rank proposal per visit in run order (0 = none): the
+                             scheduler's proposals are inputs here, the network is not run */
 } or_dmrg_opts;
 
-#define OR_LOG_FIELDS 22
+#define OR_LOG_FIELDS 50
 /* log record per visit (doubles):
  * 0 sweep, 1 dir (0 L->R, 1 R->L), 2 bond, 3 m, 4 n, 5 k, 6 chi_ctrl, 7 E,
  * 8 S, 9 S_ema, 10 eps, 11 wdisc, 12 gap, 13 lanczos_iters, 14 svd_sweeps,
- * 15 P, 16 I, 17 D, 18 u, 19 lanczos_ok, 20 sigma_0, 21 sigma_last_kept */
+ * 15 P, 16 I, 17 D, 18 u, 19 lanczos_ok, 20 sigma_0, 21 sigma_last_kept,
+ * 22 k_needed, 23 proposal used (0 = none), 24 fallback, 25..49 scheduler inputs */
+
+/* ------------------------------------------------------------------------ */
+/* Learned-scheduler inputs, labels and fallback rule.  The network stands   */
+/* in for the predictive scheduler of Sec. 7 (Eq. 16-17): it sees the bond's */
+/* recent entropy history and its singular-value tail.  Definitions:        */
+/*  - inputs (25): the last 8 EMA entropies of the bond (Eq. 8), oldest      */
+/*    first; with fewer than 8 visits so far the oldest one fills the front;  */
+/*    then ln sigma_j of the 16 largest singular values of the full spectrum */
+/*    (descending), floored at ln 1e-16, a missing value counting as the     */
+/*    floor; then the relative bond position (b + 1) / N.                    */
+/*  - label: the smallest k >= 1 whose truncation error of Eq. (4),          */
+/*    sqrt(sum_{j>=k} sigma_j^2), is at most eps_target (k = R always is).   */
+/*  - rule: a proposal k_p is used unless the truncation error it would      */
+/*    leave, Eq. (4) at min(k_p, R), exceeds eps_target; then the controller */
+/*    decides (fallback).                                                    */
+/* ------------------------------------------------------------------------ */
+void or_sched_features(const double *ema_hist, int nhist, const double *S, int R, int bond, int N, double *f) {
+  /* ema_hist: the bond's EMA entropies of all its visits so far, oldest first (nhist >= 1) */
+  int have = nhist < 8 ? nhist : 8;
+  const double *last = ema_hist + (nhist - have);
+  for (int r = 0; r < 8; ++r) {
+    int src = r - (8 - have);
+    f[r] = last[src < 0 ? 0 : src];
+  }
+  const double lnfloor = log(1e-16);
+  for (int r = 0; r < 16; ++r) {
+    double v = lnfloor;
+    if (r < R && S[r] > 0.0) {
+      double l = log(S[r]);
+      v = l > lnfloor ? l : lnfloor;
+    }
+    f[8 + r] = v;
+  }
+  f[24] = (double)(bond + 1) / (double)N;
+}
+
+/* truncation error of Eq. (4) when k values are kept (tail summed smallest-first) */
+double or_trunc_error(int R, const double *S, int k) {
+  double tail = 0.0;
+  for (int j = R - 1; j >= k; --j) tail += S[j] * S[j];
+  return sqrt(tail);
+}
+
+int or_k_needed(int R, const double *S, double eps_target) {
+  for (int k = 1; k < R; ++k)
+    if (or_trunc_error(R, S, k) <= eps_target) return k;
+  return R;
+}
 
 static void right_canonicalize(int N, int d, int *chi, double **A) {
   for (int b = N - 1; b >= 1; --b) {
@@ -863,6 +915,10 @@ int or_dmrg_run(int N, int d, int D, const double *W, const double *A_init, cons
   }
   or_pid_state *ps = (or_pid_state *)calloc((size_t)(N - 1), sizeof(or_pid_state));
   for (int b = 0; b < N - 1; ++b) ps[b].chi = pp->chi_min;
+  /* every visit's EMA entropy per bond (two visits per bond and sweep) */
+  const size_t hist_cap = 2 * (size_t)(op->n_sweeps > 0 ? op->n_sweeps : 1);
+  double *hist = dalloc(hist_cap * (size_t)(N - 1));
+  int *nhist = (int *)calloc((size_t)(N - 1), sizeof(int));
   int rc_all = OR_OK;
   size_t rec = 0;
   for (int sw = 0; sw < op->n_sweeps; ++sw) {
@@ -895,6 +951,20 @@ int or_dmrg_run(int N, int d, int D, const double *W, const double *A_init, cons
           if (r < 1) r = 1;
           keep = r < pp->chi_max ? r : pp->chi_max;
         }
+        /* scheduler inputs and label of this visit; the bond's EMA history grows by one */
+        double epst = op->eps_target > 0.0 ? op->eps_target : 1e-8;
+        hist[(size_t)b * hist_cap + nhist[b]] = terms[4];
+        nhist[b] += 1;
+        double feat[25];
+        or_sched_features(hist + (size_t)b * hist_cap, nhist[b], S, Rk, b, N, feat);
+        int kneed = or_k_needed(Rk, S, epst);
+        int prop = 0, fallback = 0;
+        if (op->sched_pred && op->fixed_chi <= 0 && op->chi_rule == 0 && op->sched_pred[rec] > 0) {
+          prop = op->sched_pred[rec];
+          int kp = prop < Rk ? prop : Rk;
+          if (or_trunc_error(Rk, S, kp) > epst) fallback = 1;
+          else keep = prop;
+        }
         int k = keep < Rk ? keep : Rk;
         or_spectrum(Rk, S, k, sp);
         double nk = 0.0;
@@ -907,6 +977,8 @@ int or_dmrg_run(int N, int d, int D, const double *W, const double *A_init, cons
           r[8] = sp[1]; r[9] = terms[4]; r[10] = sp[2]; r[11] = sp[3]; r[12] = gap; r[13] = iters;
           r[14] = sinfo; r[15] = terms[0]; r[16] = terms[1]; r[17] = terms[2]; r[18] = terms[3];
           r[19] = rc == OR_OK; r[20] = S[0]; r[21] = S[k - 1];
+          r[22] = kneed; r[23] = prop; r[24] = fallback;
+          for (int q = 0; q < 25; ++q) r[25 + q] = feat[q];
         }
         ++rec;
         double *Ab = dalloc((size_t)m * k), *Ab1 = dalloc((size_t)k * n);
@@ -935,7 +1007,7 @@ int or_dmrg_run(int N, int d, int D, const double *W, const double *A_init, cons
   if (chi_final) memcpy(chi_final, chi, sizeof(int) * (size_t)(N - 1));
   if (pid_final) memcpy(pid_final, ps, sizeof(or_pid_state) * (size_t)(N - 1));
   for (int i = 0; i < N; ++i) { free(A[i]); free(Le[i]); free(Re[i]); }
-  free(A); free(Le); free(Re); free(chi); free(ps);
+  free(A); free(Le); free(Re); free(chi); free(ps); free(hist); free(nhist);
 #undef CL
 #undef CR
   return rc_all;

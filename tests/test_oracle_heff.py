@@ -121,3 +121,36 @@ def test_heff_element_equals_full_product():
     full = oracle.heff_apply(L, W[2], W[3], R, th)
     for idx in np.ndindex(full.shape):
         assert abs(oracle.heff_element(L, W[2], W[3], R, th, idx) - full[idx]) <= 1e-13 * np.abs(full).max()
+
+
+@pytest.mark.parametrize("k", [1, 3, 6, 10])
+def test_fixed_iteration_lanczos_is_rayleigh_ritz_on_the_krylov_space(k):
+    """After exactly k matvecs from theta0 (fixed-iteration mode, no restart), the Ritz value is the
+    minimum of the Rayleigh quotient over span{theta0, H theta0, ..., H^(k-1) theta0}, and the returned
+    vector is the minimiser.  The reference projects the explicit H_eff onto an orthonormal basis of
+    that Krylov space made by numpy's QR of the power vectors."""
+    As, Bs, W, L, R, chl, chr_ = _setup(0, [1, 1, 0], 10, 4, 8)
+    dim = chl * 4 * chr_
+    H = np.stack([oracle.heff_apply(L, W[4], W[5], R, e.reshape(chl, 2, 2, chr_)).reshape(dim)
+                  for e in np.eye(dim)], 1)
+    H = 0.5 * (H + H.T)
+    th0 = synth.random_matrix(dim, 1, 17).reshape(dim)
+    K = np.zeros((dim, k))
+    x = th0 / np.linalg.norm(th0)
+    for i in range(k):
+        K[:, i] = x
+        x = H @ x
+        x /= np.linalg.norm(x)
+    Q, _ = np.linalg.qr(K)
+    w, Y = np.linalg.eigh(Q.T @ H @ Q)
+    ref_E, ref_v = w[0], Q @ Y[:, 0]
+    E, th, it, rc = oracle.lanczos_heff(L, W[4], W[5], R, th0.reshape(chl, 2, 2, chr_), tol=1e-300,
+                                        restarts=0, fixed_iters=k)
+    assert rc == 0 and it == k
+    assert abs(E - ref_E) <= 1e-10 * abs(ref_E)
+    v = th.reshape(dim)
+    assert abs(abs(v @ ref_v) - 1.0) <= 1e-8
+    if k > 1:  # more matvecs lower the Ritz value
+        E1, _, _, _ = oracle.lanczos_heff(L, W[4], W[5], R, th0.reshape(chl, 2, 2, chr_), tol=1e-300,
+                                          restarts=0, fixed_iters=k - 1)
+        assert E < E1

@@ -94,3 +94,29 @@ def test_training_fits_a_smooth_target():
         oracle.adam_step(p, g, m, v, step, lr=3e-3)
     l1, _ = oracle.mlp_loss_grad(p, x, t)
     assert l1 < 0.1 * l0
+
+
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    # with a constant gradient the bias-corrected moments are exactly g and g^2 at every step t, so each
+    # step moves p by lr * g / (|g| + eps); a wrong bias correction (power, step index or a missing
+    # correction of v) breaks this from t = 2 on
+    g = np.array([0.3, -4.0, 2e-3, 1.0])
+    p = np.zeros(4)
+    m, v = np.zeros(4), np.zeros(4)
+    for t in range(1, 6):
+        oracle.adam_step(p, g, m, v, t, lr=0.01)
+        assert np.allclose(p, -t * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-16), t
+
+
+def test_adam_second_step_with_opposing_gradient_stands_still():
+    # first moment after g1 then g2 = -b1 g1: (1-b1)(b1 g1 + g2) = 0, so the second step leaves p
+    # where the first put it, whatever the second moment is
+    b1 = 0.9
+    g1 = np.array([0.5, -2.0, 1e-3])
+    p = np.array([1.0, 2.0, 3.0])
+    m, v = np.zeros(3), np.zeros(3)
+    oracle.adam_step(p, g1, m, v, 1, lr=0.05, b1=b1)
+    after1 = p.copy()
+    oracle.adam_step(p, -b1 * g1, m, v, 2, lr=0.05, b1=b1)
+    assert np.allclose(p, after1, rtol=0, atol=1e-15)
+    assert np.allclose(after1, [1.0, 2.0, 3.0] - 0.05 * g1 / (np.abs(g1) + 1e-8), rtol=1e-13)

@@ -114,3 +114,19 @@ def test_tfim_critical_free_fermions_closed_form():
     import math
     for N in (5, 20, 40):
         assert abs(tfim_free_fermion_energy(N, 1.0, 1.0) - (1 - 1 / math.sin(math.pi / (2 * (2 * N + 1))))) < 1e-11
+
+
+@pytest.mark.parametrize("N", [4, 6, 8, 10, 12, 14, 16])
+def test_j1j2_majumdar_ghosh_point(N):
+    # J2 = J1/2 on an open chain of even length: the dimer product state is the exact ground state,
+    # E0 = -3N/8 (Majumdar-Ghosh)
+    E, _, _, rc = oracle.ed_ground(oracle.MODEL_J1J2, N, [1.0, 0.5], tol=1e-13)
+    assert rc == 0
+    assert abs(E - (-3.0 * N / 8.0)) <= 1e-11 * N
+
+
+def test_j1j2_mpo_at_majumdar_ghosh_point():
+    # the J1-J2 MPO (not the matrix-free Hamiltonian) has the same ground energy
+    N = 8
+    H = oracle.mpo_dense(oracle.mpo(oracle.MODEL_J1J2, N, [1.0, 0.5]))
+    assert abs(np.linalg.eigvalsh(H)[0] - (-3.0)) <= 1e-12
