@@ -52,9 +52,10 @@ typedef struct tna_ctx_s *tna_ctx;
 /* Creates a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the null stream). */
 tna_status tna_create(tna_ctx *out, int device, void *hip_stream);
-/* Objects made from a context (DMRG runs, batches, networks) must be
- * destroyed before the context. */
-void tna_destroy(tna_ctx ctx);
+/* Destroys the context.  Objects made from it (DMRG runs, batches, networks) must
+ * be destroyed first: while any is alive the call returns TNA_ERR_ARG and frees
+ * nothing (a host-side count, no HIP call).  NULL is a no-op. */
+tna_status tna_destroy(tna_ctx ctx);
 tna_status tna_set_stream(tna_ctx ctx, void *hip_stream);
 /* Waits for all work the context enqueued.  Synchronises. */
 tna_status tna_synchronize(tna_ctx ctx);
@@ -102,8 +103,10 @@ tna_status tna_heff_apply(tna_ctx ctx, int chi_l, int chi_r, int d, int D, const
 /* ---------------------------------------------------------------- SVD */
 /* Truncated SVD of Eq. (3)/(19), A = U diag(S) Vt, by blocked one-sided
  * Jacobi, plus the spectrum sums of Eq. (4)-(5).
- *  A       device, m x n, dtype (TNA_F64: double, TNA_F32: float; F32 runs
- *          the Gram and rotation products in FP32, the rotations in FP64)
+ *  A       device, m x n, dtype (TNA_F64: double, TNA_F32: float; an F32
+ *          input is widened to FP64 on load, the whole Jacobi runs in FP64
+ *          and U, Vt are rounded to FP32 on output, so the F32 error is the
+ *          rounding of the input and of the outputs)
  *  chi_keep  k = min(chi_keep, m, n) vectors are returned (chi_keep >= 1)
  *  S       device double[min(m,n)]: full spectrum, descending
  *  U       device, m x k (same dtype as A);  Vt device, k x n
@@ -208,6 +211,29 @@ tna_status tna_dmrg_create(tna_ctx ctx, int N, int d, int D, const double *W_hos
  * environment.  E_out (host) receives the last Ritz value; log (host, may be
  * NULL) receives 2*(N-1) records.  Synchronises. */
 tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log);
+/* One bond visit (Sec. 10, Eq. 18-19): the same steps as one visit of a sweep, on
+ * bond `bond` (sites bond, bond+1) in direction dir (0: left to right, leaving the
+ * orthogonality centre on site bond+1 and growing the left environment; 1: right to
+ * left, leaving it on site bond and growing the right environment).  The centre
+ * must be on site bond (dir 0) or bond+1 (dir 1); it is on site 0 after create and
+ * after every sweep, and tna_dmrg_sweep needs it there.  A visit back and forth on
+ * one bond repeats the same-shape step with unchanged environments.  E_out and log
+ * (host, may be NULL) as for one record of a sweep; log->sweep is the number of
+ * sweeps done.  TNA_ERR_ARG (nothing launched) on a bad bond, direction or centre.
+ * Synchronises. */
+tna_status tna_dmrg_visit(tna_dmrg dm, int bond, int dir, double *E_out, tna_visit_log *log);
+/* Site of the orthogonality centre (-1 for a null handle).  Host only. */
+int tna_dmrg_centre(tna_dmrg dm);
+/* Counters of the run's step engine since create (tna_batch_stats below; ms_total stays 0 and
+ * steps is the number of sweeps done).  Host only. */
+typedef struct tna_batch_stats_s tna_batch_stats;
+tna_status tna_dmrg_get_stats(tna_dmrg dm, tna_batch_stats *out);
+/* Copies one environment tensor into dst (device or host memory, capacity in doubles):
+ * side 0 the left environment of `site` (sites 0..site-1, layout L[a][w][a'], current
+ * for site <= centre), side 1 the right environment of `site` (sites site+1..N-1,
+ * R[b][w][b'], current for site >= centre).  *count receives chi*D*chi; dst NULL only
+ * queries it.  TNA_ERR_ARG for an environment that is not current.  Synchronises. */
+tna_status tna_dmrg_get_env(tna_dmrg dm, int side, int site, double *dst, size_t capacity, size_t *count);
 /* Current realised bond dims (N-1) and controller states (N-1), host. */
 tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid);
 /* Copies the MPS packed site after site into A_host (capacity given in
@@ -218,7 +244,8 @@ tna_status tna_dmrg_get_mps(tna_dmrg dm, double *A_host, size_t capacity, size_t
  * scheduler history to `path` (binary, this library's own format); load recreates
  * the run on ctx from them (right-canonicalisation and environments as in
  * tna_dmrg_create) and restores the controller state, so the next sweep continues
- * the saved run.  A learned scheduler is not saved (attach it again).  Errors:
+ * the saved run.  A learned scheduler is not saved: attach it again, and the
+ * proposals it had pending at the save are used as if it had never left.  Errors:
  * TNA_ERR_ARG on a file that cannot be opened, is not a checkpoint or is truncated. */
 tna_status tna_dmrg_save(tna_dmrg dm, const char *path);
 tna_status tna_dmrg_load(tna_ctx ctx, const char *path, tna_dmrg *out);
@@ -233,14 +260,20 @@ void tna_dmrg_destroy(tna_dmrg dm);
  * as a HIP graph once per step and replayed.  Controllers, Lanczos options
  * and precision as for tna_dmrg_create (pid and opts are shared by all
  * chains; opts.heff_prec F32 runs the H_eff contractions in FP32).  The work
- * runs on a stream the batch owns (default priority).  Synchronises. */
+ * runs on the context's stream; a context created on the null stream (which
+ * cannot be captured into a graph) gets a private non-blocking stream of
+ * default priority instead.  Either way the call waits for the context
+ * stream's earlier work first and synchronises before returning.  The same
+ * holds for tna_dmrg_sweep and tna_dmrg_visit.  Synchronises. */
 typedef struct tna_dmrg_batch_s *tna_dmrg_batch;
-typedef struct {
+struct tna_batch_stats_s {
   double ms_total, ms_lanczos, ms_svd, ms_env;
   long lanczos_iters, graph_launches;
   long small_launches;   /* launches of the single-workgroup Lanczos path (short theta) */
+  long heff_f32_iters;   /* Lanczos iterations the FP32 H_eff kernels executed (counted per launch on the
+                            device side, so at least lanczos_iters under heff_prec F32; 0 under F64) */
   int autotune_entries, steps;
-} tna_batch_stats;
+};
 tna_status tna_dmrg_batch_create(tna_ctx ctx, int nchains, const int *N, int d, int D, const double *const *W_host,
                                  const double *const *A_host, const int *const *chi_init, const tna_pid_params *pid,
                                  const tna_dmrg_opts *opts, tna_dmrg_batch *out);
@@ -294,7 +327,8 @@ void tna_mlp_destroy(tna_mlp n);
  * second visit on, the bond keeps k = clamp(round(2^y), chi_min, chi_max)
  * predicted at its previous visit, unless that k would leave a truncation
  * error above opts.eps_target, in which case the controller's chi is used
- * (fallback).  The controller keeps running either way. */
+ * (fallback).  The controller keeps running either way.  Replacing or detaching a
+ * network drops its pending proposals. */
 tna_status tna_dmrg_set_scheduler(tna_dmrg dm, tna_mlp net);
 
 #ifdef __cplusplus

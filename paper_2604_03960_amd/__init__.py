@@ -73,6 +73,7 @@ class VisitLog(C.Structure):
 class BatchStats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_lanczos", C.c_double), ("ms_svd", C.c_double), ("ms_env", C.c_double),
                 ("lanczos_iters", C.c_long), ("graph_launches", C.c_long), ("small_launches", C.c_long),
+                ("heff_f32_iters", C.c_long),
                 ("autotune_entries", C.c_int),
                 ("steps", C.c_int)]
 
@@ -80,7 +81,7 @@ class BatchStats(C.Structure):
 _vp, _dp, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
 _SIGS = {
     "tna_create": ([C.POINTER(C.c_void_p), C.c_int, _vp], C.c_int),
-    "tna_destroy": ([_vp], None),
+    "tna_destroy": ([_vp], C.c_int),
     "tna_set_stream": ([_vp, _vp], C.c_int),
     "tna_synchronize": ([_vp], C.c_int),
     "tna_last_error": ([], C.c_char_p),
@@ -96,6 +97,10 @@ _SIGS = {
     "tna_dmrg_create": ([_vp, C.c_int, C.c_int, C.c_int, _dp, _dp, _ip, C.POINTER(PidParams), C.POINTER(DmrgOpts),
                          C.POINTER(C.c_void_p)], C.c_int),
     "tna_dmrg_sweep": ([_vp, _dp, C.POINTER(VisitLog)], C.c_int),
+    "tna_dmrg_visit": ([_vp, C.c_int, C.c_int, _dp, C.POINTER(VisitLog)], C.c_int),
+    "tna_dmrg_centre": ([_vp], C.c_int),
+    "tna_dmrg_get_stats": ([_vp, C.POINTER(BatchStats)], C.c_int),
+    "tna_dmrg_get_env": ([_vp, C.c_int, C.c_int, _vp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "tna_dmrg_get_state": ([_vp, _ip, C.POINTER(PidState)], C.c_int),
     "tna_dmrg_get_mps": ([_vp, _dp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
     "tna_dmrg_destroy": ([_vp], None),
@@ -191,8 +196,9 @@ class Context:
         self.h = h
 
     def close(self):
+        """Destroys the context; raises TnaError (and keeps it) while runs or networks made from it live."""
         if getattr(self, "h", None):
-            _lib.tna_destroy(self.h)
+            _check(_lib.tna_destroy(self.h))
             self.h = None
 
     def __del__(self):
@@ -318,6 +324,34 @@ class Dmrg:
             d["feat"] = np.array(r.feat[:], dtype=np.float32)
             recs.append(d)
         return E.value, recs, st
+
+    def visit(self, bond: int, direction: int):
+        """One bond visit (0: left to right, 1: right to left); returns (E, visit dict, status)."""
+        log = VisitLog()
+        E = C.c_double(0.0)
+        st = _check(_lib.tna_dmrg_visit(self.h, bond, direction, C.byref(E), C.byref(log)), allow=(TNA_ERR_NOCONV,))
+        d = {f: getattr(log, f) for f, _ in VisitLog._fields_ if f != "feat"}
+        d["feat"] = np.array(log.feat[:], dtype=np.float32)
+        return E.value, d, st
+
+    def centre(self) -> int:
+        return _lib.tna_dmrg_centre(self.h)
+
+    def stats(self) -> dict:
+        """Step-engine counters since create (Lanczos iterations, launches per path, FP32 H_eff iterations)."""
+        st = BatchStats()
+        _check(_lib.tna_dmrg_get_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in BatchStats._fields_}
+
+    def env(self, side: int, site: int):
+        """Copy of the left (side 0) or right (side 1) environment of `site` as a device tensor (chi, D, chi)."""
+        torch = self.ctx.torch
+        cnt = C.c_size_t(0)
+        _check(_lib.tna_dmrg_get_env(self.h, side, site, None, 0, C.byref(cnt)))
+        chi = int(round((cnt.value / self.D) ** 0.5))
+        out = torch.empty((chi, self.D, chi), dtype=torch.float64, device="cuda")
+        _check(_lib.tna_dmrg_get_env(self.h, side, site, C.c_void_p(out.data_ptr()), cnt.value, C.byref(cnt)))
+        return out
 
     def save(self, path: str):
         """Checkpoint (MPS, MPO, controller state) to a file; see tna_dmrg_save."""

@@ -455,8 +455,13 @@ tna_status tna_create(tna_ctx *out, int device, void *hip_stream) {
   return TNA_OK;
 }
 
-void tna_destroy(tna_ctx c) {
-  if (!c) return;
+tna_status tna_destroy(tna_ctx c) {
+  if (!c) return TNA_OK;
+  if (c->children > 0) {
+    set_error("tna_destroy: " + std::to_string(c->children) +
+              " DMRG run(s) or network(s) made from this context are still alive; destroy them first");
+    return TNA_ERR_ARG;
+  }
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (DevBuf *b : {&c->x, &c->z, &c->lf, &c->rf, &c->m12, &c->part, &c->misc, &c->spec}) b->release();
@@ -464,6 +469,7 @@ void tna_destroy(tna_ctx c) {
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   delete c;
+  return TNA_OK;
 }
 
 tna_status tna_set_stream(tna_ctx c, void *hip_stream) {

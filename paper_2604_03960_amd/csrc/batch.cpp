@@ -194,6 +194,7 @@ constexpr int NT_SMALL = 512;               // its workgroup size
 constexpr size_t LZ_SLOT = 128;             // per-chain h1/h2/y/nrm2 slots
 constexpr size_t LZ_PER = 3 * LZ_SLOT + 8;  // doubles per chain before the partials
 constexpr size_t LZ_PART = 128 * 512;       // partial-sum slots per chain and array
+constexpr double LZ_TOL_F32 = 1e-6;         // least Lanczos residual tolerance with the FP32 operator
 
 }  // namespace
 
@@ -216,6 +217,7 @@ struct tna_engine_s {
   std::vector<int> lz_last;  // per slot: Lanczos iterations of the previous visit (launch sizing)
   long small_launches = 0;
   long graph_launches = 0, lanczos_iters = 0;
+  long heff_f32_iters = 0;  // Lanczos iterations whose H_eff ran on FP32 operands
   double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
 };
 
@@ -275,6 +277,7 @@ void engine_stats(tna_engine e, tna_batch_stats *st) {
   st->lanczos_iters = e->lanczos_iters;
   st->graph_launches = e->graph_launches;
   st->small_launches = e->small_launches;
+  st->heff_f32_iters = e->heff_f32_iters;
   st->autotune_entries = (int)g_tune.table.size();
 }
 
@@ -283,14 +286,32 @@ void engine_stats(tna_engine e, tna_batch_stats *st) {
 tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std::vector<int> &slot,
                        const std::vector<int> &bond, const std::vector<int> &half, std::vector<double> &E_out,
                        std::vector<tna_visit_log *> &logs, tna_status *worst) {
-  hipStream_t s = en->stream;
   const int nc = (int)ch.size();
   if (nc == 0) return TNA_OK;
+  // the context's stream; a context on the null stream (which cannot be captured) uses the engine's own
+  hipStream_t s = ch[0]->ctx->stream ? ch[0]->ctx->stream : en->stream;
   const int d = ch[0]->d, D = ch[0]->D;
   const int I1 = D * d, I2 = D * d * d;
   const int prec = ch[0]->opts.heff_prec;
   const bool f32 = prec == TNA_HEFF_F32;
+  // residual tolerance of the Lanczos stop rule; with the FP32 operator its rounding (~1e-7 of the
+  // operator norm) sets a floor on the residual estimate, so the test uses at least 1e-6 relative
+  auto tol_of = [&](tna_dmrg dm) { return f32 ? std::max(dm->opts.lanczos_tol, LZ_TOL_F32) : dm->opts.lanczos_tol; };
   arena_begin(en->ar);  // the previous step ended with a synchronisation
+  // the captured iteration is released, and the stream drained (the pinned arena of this step may
+  // still feed copies), on every way out of the step, errors included
+  struct StepGuard {
+    hipStream_t s;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    ~StepGuard() {
+      (void)hipStreamSynchronize(s);
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+  } guard{s};
+  hipGraph_t &graph = guard.graph;
+  hipGraphExec_t &gexec = guard.gexec;
   auto t0 = std::chrono::steady_clock::now();
   struct Visit {
     int b, half, chl, chm, chr, m, n, kmax, fixed;
@@ -420,8 +441,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       const Visit &v = vs[q];
       if (v.nv > LZ_SMALL_N) continue;
       int ac = std::max(1, std::min(v.chl, NT_SMALL / std::max(1, v.chr)));
-      while (ac > 1 && lz_small_lds(v.chl, v.chr, d, D, ac) > LZ_SMALL_LDS_MAX) ac /= 2;
-      const size_t need = lz_small_lds(v.chl, v.chr, d, D, ac);
+      while (ac > 1 && lz_small_lds(v.chl, v.chr, d, D, ac, f32) > LZ_SMALL_LDS_MAX) ac /= 2;
+      const size_t need = lz_small_lds(v.chl, v.chr, d, D, ac, f32);
       if (need > LZ_SMALL_LDS_MAX) continue;
       small[q] = 1;
       sm_ac[q] = ac;
@@ -434,8 +455,6 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   const MixProb *dmx = nullptr;
   const GemmProb *dp1 = nullptr, *dp4 = nullptr;
   int tot1 = 0, tot4 = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
   const bool use_graph = !(timing_may_match("gemmg") || timing_may_match("mixg") || timing_may_match("lz."));
   double lz_bytes = 0.0;  // one CGS pass at the current iteration, all chains (timing only)
   auto lz_hint = [&](int it) {
@@ -484,17 +503,13 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       if (cs == TNA_OK) cs = gemm_grouped(g4, dp4, nc, tot4, s);
       if (cs == TNA_OK) cs = lz_iteration(dlp, nc, maxG, maxk, 0.0, s);
       hipError_t ce = hipStreamEndCapture(s, &graph);
-      if (cs != TNA_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cs;
-      }
+      if (cs != TNA_OK) return cs;
       if (ce != hipSuccess) {
         set_error(std::string("graph capture: ") + hipGetErrorString(ce));
         return TNA_ERR_DEVICE;
       }
       hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
       if (ie != hipSuccess) {
-        (void)hipGraphDestroy(graph);
         set_error(std::string("graph instantiate: ") + hipGetErrorString(ie));
         return TNA_ERR_DEVICE;
       }
@@ -517,7 +532,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     bool stop = false;
     if (vs[q].fixed > 0) {
       if (nn >= vs[q].kmax || be[q][nn - 1] < 1e-14) stop = conv[q] = 1;
-    } else if (resid <= ch[q]->opts.lanczos_tol * std::max(1.0, std::fabs(Ec[q])) || be[q][nn - 1] < 1e-14) {
+    } else if (resid <= tol_of(ch[q]) * std::max(1.0, std::fabs(Ec[q])) || be[q][nn - 1] < 1e-14) {
       stop = conv[q] = 1;
     } else if (nn >= vs[q].kmax) {
       stop = true;
@@ -549,7 +564,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     auto solve = [&](int nn) {
       yv[q].assign(nn, 0.0);
       Ec[q] = tridiag_lowest_host(nn, al[q].data(), be[q].data(), yv[q].data());
-      return std::fabs(be[q][nn - 1] * yv[q][nn - 1]) <= ch[q]->opts.lanczos_tol * std::max(1.0, std::fabs(Ec[q]));
+      return std::fabs(be[q][nn - 1] * yv[q][nn - 1]) <= tol_of(ch[q]) * std::max(1.0, std::fabs(Ec[q]));
     };
     int stop_at = 0;
     bool converged = false;
@@ -650,21 +665,24 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       if (!live) break;
       for (int q = 0; q < nc; ++q) en->hflags[en->nslot + slot[q]] = small[q] && act[q];
       TNA_TRY(push_act());
-      TNA_TRY(lz_small(dsp, (int)sp.size(), D, d * d, chunk, lds_small, s));
+      TNA_TRY(lz_small(dsp, (int)sp.size(), D, d * d, chunk, lds_small, f32, s));
       en->small_launches += 1;
       TNA_HIP(hipMemcpyAsync(en->h_rec, rec_small, sizeof(double) * 2 * LZ_HMAX * en->nslot, hipMemcpyDeviceToHost,
                              s));
       TNA_HIP(hipStreamSynchronize(s));
       for (int q : sq) en->h_j[slot[q]] = (int)en->h_rec[(size_t)2 * LZ_HMAX * slot[q] + 2 * LZ_HMAX - 1];
-      if (timing_wanted("lz.small")) {
+      const char *tname = f32 ? "lz.small.f32" : "lz.small";
+      if (timing_wanted(tname)) {
         double fl = 0.0, by = 0.0;
         for (int q : sq)
           for (int t = jdev[q]; t < en->h_j[slot[q]]; ++t) {
             fl += it_flops(q, t);
             by += it_bytes(q, t);
           }
-        timer_add_work("lz.small", fl, by);
+        timer_add_work(tname, fl, by);
       }
+      if (f32)
+        for (int q : sq) en->heff_f32_iters += en->h_j[slot[q]] - jdev[q];
       for (int q : sq) jdev[q] = en->h_j[slot[q]];
       for (int q : sq) {
         if (!act[q]) continue;
@@ -719,6 +737,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
       break;
     }
     if (use_graph) en->graph_launches += 1;
+    if (f32)
+      for (int q = 0; q < nc; ++q) en->heff_f32_iters += act[q];
     bool changed = false;
     for (int q = 0; q < nc; ++q) {
       if (!act[q]) continue;
@@ -739,6 +759,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
   if (graph) (void)hipGraphDestroy(graph);
+  gexec = nullptr;
+  graph = nullptr;
   if (lst != TNA_OK) return lst;
   // ---- Ritz vectors
   for (int q = 0; q < nc; ++q) {
@@ -793,6 +815,11 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   if (sst == TNA_ERR_NOCONV && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
   TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * SPEC * nc, hipMemcpyDeviceToHost, s));
   TNA_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < nc; ++q)
+    if (!std::isfinite(en->h_dbl[SPEC * q]) || !std::isfinite(en->h_dbl[SPEC * q + 1])) {
+      set_error("dmrg visit: non-finite two-site spectrum");
+      return TNA_ERR_NONFINITE;
+    }
   for (int q = 0; q < nc; ++q)  // single-workgroup Jacobi paths: sweeps and convergence from spec[7]
     if (mats[q].fused) {
       const double f = en->h_dbl[SPEC * q + 7];

@@ -245,17 +245,21 @@ __global__ __launch_bounds__(NT) void lz_ritz1_kernel(const LzProb *probs) {
 
 // ------------------------------------------------------------------ single-workgroup Lanczos
 // Whole Lanczos iterations of one short theta inside one workgroup (grid x =
-// chain).  H_eff (Eq. 1's contraction in the order L, W_i W_{i+1}, R) runs as
-// three small FP64 MFMA products on LDS-resident operands, a chunk of `ac`
-// left indices at a time:
+// chain).  H_eff (Eq. 18's contraction in the order L, W_i W_{i+1}, R) runs as
+// three small MFMA products on LDS-resident operands, a chunk of `ac` left
+// indices at a time:
 //   X[(a,w)][(s',t',c')] = sum_a' L[(a,w)][a'] theta[a'][(s',t',c')]
 //   Z[o=(s,t,w'')][(a,c')] = sum_i M[o][i=(w,s',t')] X[a][i][c']
 //   out[(a,s,t)][c] = sum_{(w'',c')} Z[a][(s,t,w'')][c'] R[c][(w'',c')]
-// CGS2 against the basis in global memory follows (dot products eight at a
-// time); alpha_j, beta_j^2 of every iteration go to rec[2j], rec[2j+1].  A
+// The operand type T is double (v_mfma_f64_16x16x4_f64) or float (the
+// mixed-precision form: L, R, M and theta rounded to FP32 in LDS, products on
+// v_mfma_f32_16x16x4_f32 with FP32 accumulation, the result stored as FP64).
+// CGS2 against the FP64 basis in global memory follows (dot products eight at
+// a time); alpha_j, beta_j^2 of every iteration go to rec[2j], rec[2j+1].  A
 // workgroup stops at kmax, after `iters` iterations, or when beta_j is
 // negligible.
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int NTS = 512;  // threads of the single-workgroup Lanczos (8 waves)
 
 // x / d for 0 <= x < 2^16 and 1 <= d < 2^16 with one multiply-high by ceil(2^32 / d) (exact in
@@ -267,45 +271,60 @@ struct FastDiv {
   __device__ int div(int x) const { return d > 1 ? (int)__umulhi((unsigned)x, m) : x; }
 };
 
-// One 16 x 16 output tile, C(i, j) = sum_{kb <= k < ke} A(i, k) B(k, j), on
-// v_mfma_f64_16x16x4_f64.  Operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
-// result D[i][j] in lane j + 16 (i % 4), register i / 4.  Rows and columns past the matrix edge
-// read the last valid row/column (their results are discarded by the caller), so only a final
-// partial k-step needs a guard.  The operands of four k-steps are read together and fed to two
-// independent accumulator chains.
-template <class FA, class FB>
-__device__ inline v4d tile_mfma(int kb, int ke, int ia, int jb, int lk, FA a_at, FB b_at) {
-  v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+// 16 x 16 x 4 MFMA step and result layout per operand type.  Operands: A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k.  Result register r of lane group lk = lane / 16 holds row 4r + lk
+// (f64) or 4lk + r (f32), column lane % 16.
+template <class T> struct Mf;
+template <> struct Mf<double> {
+  typedef v4d acc;
+  __device__ static acc step(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int r) { return 4 * r + lk; }
+};
+template <> struct Mf<float> {
+  typedef v4f acc;
+  __device__ static acc step(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// One 16 x 16 output tile, C(i, j) = sum_{kb <= k < ke} A(i, k) B(k, j).  Rows and columns past
+// the matrix edge read the last valid row/column (their results are discarded by the caller), so
+// only a final partial k-step needs a guard.  The operands of four k-steps are read together and
+// fed to two independent accumulator chains.
+template <class T, class FA, class FB>
+__device__ inline typename Mf<T>::acc tile_mfma(int kb, int ke, int ia, int jb, int lk, FA a_at, FB b_at) {
+  typedef typename Mf<T>::acc A4;
+  A4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
   const int k16 = kb + ((ke - kb) & ~15), k4 = kb + ((ke - kb) & ~3);
   int k0 = kb;
   for (; k0 < k16; k0 += 16) {
-    double av[4], bv[4];
+    T av[4], bv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       av[u] = a_at(ia, k0 + 4 * u + lk);
       bv[u] = b_at(k0 + 4 * u + lk, jb);
     }
-    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], c0, 0, 0, 0);
-    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], c1, 0, 0, 0);
-    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], bv[2], c0, 0, 0, 0);
-    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], bv[3], c1, 0, 0, 0);
+    c0 = Mf<T>::step(av[0], bv[0], c0);
+    c1 = Mf<T>::step(av[1], bv[1], c1);
+    c0 = Mf<T>::step(av[2], bv[2], c0);
+    c1 = Mf<T>::step(av[3], bv[3], c1);
   }
-  for (; k0 < k4; k0 += 4) c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_at(ia, k0 + lk), b_at(k0 + lk, jb), c0, 0, 0, 0);
+  for (; k0 < k4; k0 += 4) c0 = Mf<T>::step(a_at(ia, k0 + lk), b_at(k0 + lk, jb), c0);
   if (k0 < ke) {
     const bool in = k0 + lk < ke;
-    const double av = in ? a_at(ia, k0 + lk) : 0.0, bv = in ? b_at(k0 + lk, jb) : 0.0;
-    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c1, 0, 0, 0);
+    const T av = in ? a_at(ia, k0 + lk) : T(0), bv = in ? b_at(k0 + lk, jb) : T(0);
+    c1 = Mf<T>::step(av, bv, c1);
   }
   return c0 + c1;
 }
 
 // C = A B over the whole workgroup, the waves taking 16 x 16 tiles in turn.  With no more than
-// half as many tiles as waves (and `part` holding tiles x 256 doubles within part_cap), each
+// half as many tiles as waves (and `part` holding tiles x 256 values within part_cap), each
 // tile's k range is split between two waves and the second half's partial sums pass through
 // `part` in LDS.
-template <class FA, class FB, class FC>
-__device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_put, double *part = nullptr,
+template <class T, class FA, class FB, class FC>
+__device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_put, T *part = nullptr,
                                   int part_cap = 0) {
+  typedef typename Mf<T>::acc A4;
   const int lane = threadIdx.x & 63, nw = NTS / 64;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -316,8 +335,8 @@ __device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_pu
     const int t = second ? wave - tiles : wave;
     const int i0 = (t / tn) << 4, j0 = (t - (t / tn) * tn) << 4;
     const int ia = min(i0 + lr, M - 1), jb = j0 + lr, jc = min(jb, N - 1);
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    if (have) acc = tile_mfma(second ? kh : 0, second ? K : kh, ia, jc, lk, a_at, b_at);
+    A4 acc = {0, 0, 0, 0};
+    if (have) acc = tile_mfma<T>(second ? kh : 0, second ? K : kh, ia, jc, lk, a_at, b_at);
     if (have && second)
 #pragma unroll
       for (int r = 0; r < 4; ++r) part[(t * 64 + lane) * 4 + r] = acc[r];
@@ -325,7 +344,7 @@ __device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_pu
     if (have && !second)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 4 * r + lk;
+        const int i = i0 + Mf<T>::row(lk, r);
         if (i < M && jb < N) c_put(i, jb, acc[r] + part[(t * 64 + lane) * 4 + r]);
       }
     return;
@@ -333,10 +352,10 @@ __device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_pu
   for (int t = wave; t < tiles; t += nw) {
     const int i0 = (t / tn) << 4, j0 = (t - (t / tn) * tn) << 4;
     const int ia = min(i0 + lr, M - 1), jb = j0 + lr, jc = min(jb, N - 1);
-    const v4d acc = tile_mfma(0, K, ia, jc, lk, a_at, b_at);
+    const A4 acc = tile_mfma<T>(0, K, ia, jc, lk, a_at, b_at);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = i0 + 4 * r + lk;
+      const int i = i0 + Mf<T>::row(lk, r);
       if (i < M && jb < N) c_put(i, jb, acc[r]);
     }
   }
@@ -344,8 +363,9 @@ __device__ inline void block_gemm(int M, int N, int K, FA a_at, FB b_at, FC c_pu
 
 // NB independent products C_b = A B_b (one shared A), the tiles of all products dealt to the
 // waves in turn.
-template <class FA, class FB, class FC>
+template <class T, class FA, class FB, class FC>
 __device__ inline void block_gemm_nb(int NB, int M, int N, int K, FA a_at, FB b_at, FC c_put) {
+  typedef typename Mf<T>::acc A4;
   const int lane = threadIdx.x & 63, nw = NTS / 64;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -354,10 +374,10 @@ __device__ inline void block_gemm_nb(int NB, int M, int N, int K, FA a_at, FB b_
     const int b = t / tpb, tt = t - b * tpb;
     const int i0 = (tt / tn) << 4, j0 = (tt - (tt / tn) * tn) << 4;
     const int ia = min(i0 + lr, M - 1), jb = j0 + lr, jc = min(jb, N - 1);
-    const v4d acc = tile_mfma(0, K, ia, jc, lk, a_at, [&](int k, int j) { return b_at(b, k, j); });
+    const A4 acc = tile_mfma<T>(0, K, ia, jc, lk, a_at, [&](int k, int j) { return b_at(b, k, j); });
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = i0 + 4 * r + lk;
+      const int i = i0 + Mf<T>::row(lk, r);
       if (i < M && jb < N) c_put(b, i, jb, acc[r]);
     }
   }
@@ -375,6 +395,7 @@ __device__ inline double block_total(double v, double *sh) {
   return r;
 }
 
+template <class T>
 __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int iters) {
   extern __shared__ double lds[];
   const LzSmall &p = probs[blockIdx.x];
@@ -390,56 +411,56 @@ __global__ __launch_bounds__(NTS) void lz_small_kernel(const LzSmall *probs, int
   double *const rec = p.rec;
   const int n = chl * dd * chr, nr = dd * chr;
   // Rows that the MFMA operand reads walk down (sixteen lanes, one row each) are stored with an
-  // odd stride in doubles, so those lanes fall on distinct LDS banks.
+  // odd stride in elements, so those lanes fall on distinct LDS banks.
   const int ldl = chl | 1, ldr = (D * chr) | 1, ldm = DD | 1, ldz = (D * chr) | 1;
   const FastDiv divD(D), divC(chr);
-  double *th = lds;                                  // n: V_j
-  double *wv = th + n;                               // n: H V_j, then orthogonalised
-  double *Ls = wv + n;                               // L[a][w][a'], rows (a, w) of stride ldl
-  double *Rs = Ls + (size_t)chl * D * ldl;           // R[c][w''][c'], rows c of stride ldr
-  double *Ms = Rs + (size_t)chr * ldr;               // M[o][i], rows o of stride ldm
-  double *Xc = Ms + DD * ldm;                        // X[al][i][c'] of a chunk
-  double *Zc = Xc + (size_t)ac * DD * chr;           // Z[al][s t][w''][c'], rows (al, s t) of stride ldz
-  double *hb = Zc + (size_t)ac * dd * ldz;           // h of the two CGS passes
+  double *wv = lds;                                  // n: H V_j, then orthogonalised (FP64)
+  double *hb = wv + n;                               // h of the two CGS passes
   double *red = hb + 2 * LZ_HMAX;                    // per-wave partial sums
-  for (int e = tid; e < chl * D * chl; e += NTS) Ls[(e / chl) * ldl + e % chl] = p.L[e];
-  for (int e = tid; e < chr * D * chr; e += NTS) Rs[(e / (D * chr)) * ldr + e % (D * chr)] = p.R[e];
-  for (int e = tid; e < DD * DD; e += NTS) Ms[(e / DD) * ldm + e % DD] = p.M[e];
+  T *th = reinterpret_cast<T *>(red + 16 * NW);      // n: V_j in the operand type
+  T *Ls = th + n;                                    // L[a][w][a'], rows (a, w) of stride ldl
+  T *Rs = Ls + (size_t)chl * D * ldl;                // R[c][w''][c'], rows c of stride ldr
+  T *Ms = Rs + (size_t)chr * ldr;                    // M[o][i], rows o of stride ldm
+  T *Xc = Ms + DD * ldm;                             // X[al][i][c'] of a chunk
+  T *Zc = Xc + (size_t)ac * DD * chr;                // Z[al][s t][w''][c'], rows (al, s t) of stride ldz
+  for (int e = tid; e < chl * D * chl; e += NTS) Ls[(e / chl) * ldl + e % chl] = (T)p.L[e];
+  for (int e = tid; e < chr * D * chr; e += NTS) Rs[(e / (D * chr)) * ldr + e % (D * chr)] = (T)p.R[e];
+  for (int e = tid; e < DD * DD; e += NTS) Ms[(e / DD) * ldm + e % DD] = (T)p.M[e];
   int j = *p.j;
   for (int it = 0; it < iters && j < kmax; ++it) {
     const double *vj = V + (int64_t)j * n;
     double *vn = V + (int64_t)(j + 1) * n;
     __syncthreads();  // previous iteration done with th, wv and hb
-    for (int e = tid; e < n; e += NTS) th[e] = vj[e];
+    for (int e = tid; e < n; e += NTS) th[e] = (T)vj[e];
     __syncthreads();
     for (int a0 = 0; a0 < chl; a0 += ac) {
       const int na = chl - a0 < ac ? chl - a0 : ac;
-      block_gemm(na * D, nr, chl, [&](int i, int k) { return Ls[(a0 * D + i) * ldl + k]; },
-                 [&](int k, int c) { return th[k * nr + c]; },
-                 [&](int i, int c, double v) { Xc[i * nr + c] = v; });
+      block_gemm<T>(na * D, nr, chl, [&](int i, int k) { return Ls[(a0 * D + i) * ldl + k]; },
+                    [&](int k, int c) { return th[k * nr + c]; },
+                    [&](int i, int c, T v) { Xc[i * nr + c] = v; });
       __syncthreads();
       // output row o = (s t, w'') goes to Zc row (al, s t) at column w'' chr + c'
       if (chr >= 16)  // one product per row index al: no division in the operand addressing
-        block_gemm_nb(na, DD, chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
-                      [&](int al, int i, int c) { return Xc[(al * DD + i) * chr + c]; },
-                      [&](int al, int o, int c, double v) {
-                        const int st = divD.div(o);
-                        Zc[(al * dd + st) * ldz + (o - st * D) * chr + c] = v;
-                      });
+        block_gemm_nb<T>(na, DD, chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
+                         [&](int al, int i, int c) { return Xc[(al * DD + i) * chr + c]; },
+                         [&](int al, int o, int c, T v) {
+                           const int st = divD.div(o);
+                           Zc[(al * dd + st) * ldz + (o - st * D) * chr + c] = v;
+                         });
       else  // narrow right bond: the al blocks side by side in one product, so tiles stay full
-        block_gemm(DD, na * chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
-                   [&](int i, int c) {
-                     const int al = divC.div(c);
-                     return Xc[(al * DD + i) * chr + (c - al * chr)];
-                   },
-                   [&](int o, int c, double v) {
-                     const int al = divC.div(c), st = divD.div(o);
-                     Zc[(al * dd + st) * ldz + (o - st * D) * chr + (c - al * chr)] = v;
-                   });
+        block_gemm<T>(DD, na * chr, DD, [&](int o, int i) { return Ms[o * ldm + i]; },
+                      [&](int i, int c) {
+                        const int al = divC.div(c);
+                        return Xc[(al * DD + i) * chr + (c - al * chr)];
+                      },
+                      [&](int o, int c, T v) {
+                        const int al = divC.div(c), st = divD.div(o);
+                        Zc[(al * dd + st) * ldz + (o - st * D) * chr + (c - al * chr)] = v;
+                      });
       __syncthreads();
-      block_gemm(na * dd, chr, D * chr, [&](int i, int q) { return Zc[i * ldz + q]; },
-                 [&](int q, int c) { return Rs[c * ldr + q]; },
-                 [&](int i, int c, double v) { wv[(a0 * dd + i) * chr + c] = v; }, Xc, ac * DD * chr);
+      block_gemm<T>(na * dd, chr, D * chr, [&](int i, int q) { return Zc[i * ldz + q]; },
+                    [&](int q, int c) { return Rs[c * ldr + q]; },
+                    [&](int i, int c, T v) { wv[(a0 * dd + i) * chr + c] = (double)v; }, Xc, ac * DD * chr);
       __syncthreads();
     }
     // CGS2 against V_0..V_j (n is a multiple of 4: element pairs, 16-byte accesses).  Dot
@@ -616,14 +637,16 @@ tna_status lz_ritz(const LzProb *d, int nch, int maxG, hipStream_t s) {
   return TNA_OK;
 }
 
-size_t lz_small_lds(int chl, int chr, int d, int D, int ac) {
+size_t lz_small_lds(int chl, int chr, int d, int D, int ac, int f32) {
   const size_t n = (size_t)chl * d * d * chr, DD = (size_t)D * d * d;
   const size_t ldl = chl | 1, ldr = (D * chr) | 1, ldm = DD | 1, ldz = ldr;
-  return sizeof(double) * (2 * n + (size_t)chl * D * ldl + (size_t)chr * ldr + DD * ldm + (size_t)ac * DD * chr +
-                           (size_t)ac * d * d * ldz + 2 * LZ_HMAX + 16 * (NTS / 64));
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  return sizeof(double) * (n + 2 * LZ_HMAX + 16 * (NTS / 64)) +
+         es * (n + (size_t)chl * D * ldl + (size_t)chr * ldr + DD * ldm + (size_t)ac * DD * chr +
+               (size_t)ac * d * d * ldz);
 }
 
-tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, hipStream_t s) {
+tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, int f32, hipStream_t s) {
   if (nch < 1) return TNA_OK;
   if (dsq != 4) {
     set_error("lz_small: physical dimension 2 only");
@@ -633,19 +656,22 @@ tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t
     set_error("lz_small: MPO bond dimension above 16");
     return TNA_ERR_UNSUPPORTED;
   }
-  static bool attr_set = false;
-  if (!attr_set) {
-    TNA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(lz_small_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)LZ_SMALL_LDS_MAX));
-    attr_set = true;
+  static bool attr_set[2] = {false, false};
+  const void *fn = f32 ? reinterpret_cast<const void *>(lz_small_kernel<float>)
+                       : reinterpret_cast<const void *>(lz_small_kernel<double>);
+  if (!attr_set[f32 ? 1 : 0]) {
+    TNA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LZ_SMALL_LDS_MAX));
+    attr_set[f32 ? 1 : 0] = true;
   }
   if (lds > LZ_SMALL_LDS_MAX) {
     set_error("lz_small: LDS need above the limit");
     return TNA_ERR_ARG;
   }
-  timer_begin("lz.small", s);
-  hipLaunchKernelGGL(lz_small_kernel, dim3(nch), dim3(NTS), lds, s, d, iters);
-  timer_end("lz.small", 0.0, 0.0, s);
+  const char *name = f32 ? "lz.small.f32" : "lz.small";
+  timer_begin(name, s);
+  if (f32) hipLaunchKernelGGL(lz_small_kernel<float>, dim3(nch), dim3(NTS), lds, s, d, iters);
+  else hipLaunchKernelGGL(lz_small_kernel<double>, dim3(nch), dim3(NTS), lds, s, d, iters);
+  timer_end(name, 0.0, 0.0, s);
   TNA_LAUNCHED("lanczos.small");
   return TNA_OK;
 }

@@ -194,6 +194,7 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
                            s));
   }
   TNA_HIP(hipStreamSynchronize(s));
+  c->children += 1;
   *out = dm.release();
   return TNA_OK;
 }
@@ -201,6 +202,10 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
 tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
   if (!dm) {
     set_error("dmrg_sweep: null handle");
+    return TNA_ERR_ARG;
+  }
+  if (dm->centre != 0) {
+    set_error("dmrg_sweep: the orthogonality centre must be at site 0 (single visits moved it)");
     return TNA_ERR_ARG;
   }
   if (!dm->engine) TNA_TRY(engine_create(1, &dm->engine));
@@ -221,6 +226,7 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
       half[0] = h;
       if (log) lg[0] = log + h * (N - 1) + step;
       TNA_TRY(engine_step(dm->engine, cs, slot, bond, half, Es, lg, &worst));
+      dm->centre = h == 0 ? bond[0] + 1 : bond[0];
       E = Es[0];
       if (progress) {
         const auto now = std::chrono::steady_clock::now();
@@ -235,6 +241,67 @@ tna_status tna_dmrg_sweep(tna_dmrg dm, double *E_out, tna_visit_log *log) {
   dm->sweeps_done += 1;
   if (E_out) *E_out = E;
   return worst;
+}
+
+tna_status tna_dmrg_visit(tna_dmrg dm, int bond, int dir, double *E_out, tna_visit_log *log) {
+  if (!dm || bond < 0 || bond > dm->N - 2 || (dir != 0 && dir != 1)) {
+    set_error("dmrg_visit: bad handle, bond or direction");
+    return TNA_ERR_ARG;
+  }
+  if (dm->centre != (dir == 0 ? bond : bond + 1)) {
+    set_error("dmrg_visit: a left-to-right visit of bond b needs the orthogonality centre on site b, a "
+              "right-to-left one on site b+1");
+    return TNA_ERR_ARG;
+  }
+  if (!dm->engine) TNA_TRY(engine_create(1, &dm->engine));
+  TNA_HIP(hipStreamSynchronize(dm->ctx->stream));
+  tna_status worst = TNA_OK;
+  std::vector<tna_dmrg> cs{dm};
+  std::vector<int> slot{0}, bd{bond}, half{dir};
+  std::vector<double> Es(1, 0.0);
+  std::vector<tna_visit_log *> lg(log ? 1 : 0, log);
+  TNA_TRY(engine_step(dm->engine, cs, slot, bd, half, Es, lg, &worst));
+  dm->centre = dir == 0 ? bond + 1 : bond;
+  if (E_out) *E_out = Es[0];
+  return worst;
+}
+
+int tna_dmrg_centre(tna_dmrg dm) { return dm ? dm->centre : -1; }
+
+tna_status tna_dmrg_get_stats(tna_dmrg dm, tna_batch_stats *out) {
+  if (!dm || !out) {
+    set_error("dmrg_get_stats: null argument");
+    return TNA_ERR_ARG;
+  }
+  std::memset(out, 0, sizeof *out);
+  if (dm->engine) engine_stats(dm->engine, out);
+  out->steps = dm->sweeps_done;
+  return TNA_OK;
+}
+
+tna_status tna_dmrg_get_env(tna_dmrg dm, int side, int site, double *dst, size_t capacity, size_t *count) {
+  if (!dm || (side != 0 && side != 1) || site < 0 || site >= dm->N) {
+    set_error("dmrg_get_env: bad handle, side or site");
+    return TNA_ERR_ARG;
+  }
+  // left environment of site i: sites 0..i-1, valid for i <= centre; right one: sites i+1..N-1, i >= centre
+  if (side == 0 ? site > dm->centre : site < dm->centre) {
+    set_error("dmrg_get_env: that environment is not current (wrong side of the orthogonality centre)");
+    return TNA_ERR_ARG;
+  }
+  const size_t chi = side == 0 ? (size_t)dm->CL(site) : (size_t)dm->CR(site);
+  const size_t n = chi * dm->D * chi;
+  if (count) *count = n;
+  if (!dst) return TNA_OK;
+  if (capacity < n) {
+    set_error("dmrg_get_env: capacity too small");
+    return TNA_ERR_ARG;
+  }
+  if (dm->engine) TNA_HIP(hipStreamSynchronize(engine_stream(dm->engine)));
+  const tna::DevBuf &src = side == 0 ? dm->Le[site] : dm->Re[site];
+  TNA_HIP(hipMemcpyAsync(dst, src.ptr, sizeof(double) * n, hipMemcpyDefault, dm->ctx->stream));
+  TNA_HIP(hipStreamSynchronize(dm->ctx->stream));
+  return TNA_OK;
 }
 
 tna_status tna_dmrg_get_state(tna_dmrg dm, int *chi, tna_pid_state *pid) {
@@ -377,8 +444,10 @@ tna_status tna_dmrg_set_scheduler(tna_dmrg dm, tna_mlp net) {
     set_error("dmrg_set_scheduler: null handle");
     return TNA_ERR_ARG;
   }
+  // proposals pending from a previous network are dropped; a run fresh from a checkpoint keeps the
+  // saved ones for the network that is attached again
+  if (dm->sched) std::fill(dm->pred.begin(), dm->pred.end(), 0);
   dm->sched = net;
-  std::fill(dm->pred.begin(), dm->pred.end(), 0);
   return TNA_OK;
 }
 
@@ -391,6 +460,7 @@ void tna_dmrg_destroy(tna_dmrg dm) {
   for (DevBuf *b : {&dm->W, &dm->M12, &dm->Ml, &dm->Mr, &dm->V, &dm->T1, &dm->T2, &dm->spec, &dm->S}) b->release();
   if (dm->host_stage) (void)hipHostFree(dm->host_stage);
   engine_destroy(dm->engine);
+  dm->ctx->children -= 1;
   delete dm;
 }
 

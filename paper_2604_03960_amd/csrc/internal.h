@@ -176,6 +176,7 @@ struct SvdGroup {
   void *host = nullptr;
   size_t host_cap = 0;
   int *host_ctr = nullptr;
+  double *host_fro = nullptr;  // pinned: squared Frobenius norms of the inputs (finiteness check)
   void release();
 };
 tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a);
@@ -231,9 +232,10 @@ struct LzSmall {
   const int *active;
   double *rec;             // 2 (kmax + 1): alpha_j, beta_j^2
 };
-size_t lz_small_lds(int chl, int chr, int d, int D, int ac);
+// LDS bytes of one workgroup; f32: the H_eff operands are held and multiplied in FP32
+size_t lz_small_lds(int chl, int chr, int d, int D, int ac, int f32);
 // Runs up to `iters` iterations for every active chain; lds = max over chains.
-tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, hipStream_t s);
+tna_status lz_small(const LzSmall *d, int nch, int D, int dsq, int iters, size_t lds, int f32, hipStream_t s);
 struct CvtProb {
   const double *src;
   float *dst;
@@ -276,6 +278,7 @@ struct tna_ctx_s {
   tna::SvdGroup svd;
   int *host_ctr = nullptr;     // pinned
   double *host_scal = nullptr; // pinned, 64 doubles
+  int children = 0;            // live DMRG runs and networks made from this context
 };
 
 // ------------------------------------------------------------------ DMRG chain state
@@ -290,6 +293,7 @@ struct tna_dmrg_s {
   tna::DevBuf W, M12, Ml, Mr;           // MPO tensors and mixing matrices (device)
   tna::DevBuf V, T1, T2, spec, S;       // Lanczos basis, env scratch, spectrum
   int sweeps_done = 0;
+  int centre = 0;                       // site of the orthogonality centre (0 after create and after a sweep)
   double *host_stage = nullptr;         // pinned: per-visit readbacks
   // learned scheduler
   tna_mlp sched = nullptr;

@@ -263,6 +263,7 @@ tna_status tna_mlp_create(tna_ctx c, const float *params_host, tna_mlp *out) {
     delete n;
     return TNA_ERR_DEVICE;
   }
+  c->children += 1;
   *out = n;
   return TNA_OK;
 }
@@ -355,6 +356,7 @@ void tna_mlp_destroy(tna_mlp n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->ctx->stream);
   for (DevBuf *b : {&n->p, &n->m, &n->v, &n->g, &n->part, &n->lpart, &n->mean, &n->istd, &n->scratch}) b->release();
+  n->ctx->children -= 1;
   delete n;
 }
 

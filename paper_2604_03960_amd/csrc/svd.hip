@@ -1299,6 +1299,19 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     set_error("svd: at most 4096 matrices per group");
     return TNA_ERR_ARG;
   }
+  // a NaN or Inf anywhere in an input shows in its squared Frobenius norm; the callers that defer
+  // their reads (the sweep engine) check the spectrum sums they read anyway
+  if (!defer_fused) {
+    if (!g.host_fro) TNA_HIP(hipHostMalloc((void **)&g.host_fro, sizeof(double) * 4096, hipHostMallocDefault));
+    for (int z = 0; z < nm; ++z)
+      TNA_HIP(hipMemcpyAsync(g.host_fro + z, mats[z].fro2, sizeof(double), hipMemcpyDeviceToHost, s));
+    TNA_HIP(hipStreamSynchronize(s));
+    for (int z = 0; z < nm; ++z)
+      if (!std::isfinite(g.host_fro[z])) {
+        set_error("svd: non-finite entry in input matrix " + std::to_string(z));
+        return TNA_ERR_NONFINITE;
+      }
+  }
   double gram_flops = 0, gram_bytes = 0, apply_flops = 0, apply_bytes = 0;
   for (auto &a : mats) {
     const double pairs = a.nb / 2, b2 = 4096.0;
@@ -1456,8 +1469,10 @@ void SvdGroup::release() {
   work_i.release();
   if (host) (void)hipHostFree(host);
   if (host_ctr) (void)hipHostFree(host_ctr);
+  if (host_fro) (void)hipHostFree(host_fro);
   host = nullptr;
   host_ctr = nullptr;
+  host_fro = nullptr;
   host_cap = 0;
 }
 

@@ -12,7 +12,7 @@ E12 = -5.142090632840529
 
 
 def _both(N, chi_init, chi_min, chi_max, sweeps, gains, s_target, model=0, params=(1.0, 1.0, 0.0), prec=0,
-          fixed_chi=0):
+          fixed_chi=0, with_stats=False):
     import paper_2604_03960_amd as tna
     W = oracle.mpo(model, N, list(params))
     A, chi, _ = synth.random_mps(N, 2, chi_init, 0)
@@ -26,6 +26,8 @@ def _both(N, chi_init, chi_min, chi_max, sweeps, gains, s_target, model=0, param
         E, recs, st = dm.sweep()
         Es.append(E)
         logs += recs
+    if with_stats:
+        return ro, np.array(Es), logs, dm.stats()
     return ro, np.array(Es), logs
 
 
@@ -71,7 +73,104 @@ def test_j1j2_and_xxz_models():
 
 
 def test_mixed_precision_energy():
+    """G1 on the single-workgroup Lanczos path (theta <= 4096 elements): FP32 operands and products,
+    FP64 everything else.  The FP32 kernel must have run (iteration counter, and an energy that differs
+    from the FP64 oracle by more than FP64 rounding) and the energy must stay within 1e-7 per site."""
     import paper_2604_03960_amd as tna
-    ro, Es, logs = _both(12, 8, 16, 16, 3, (0.5, 0.05, 0.1), 0.5, prec=tna.HEFF_F32)
-    print("f32 E", Es, "oracle", ro["E"], "dE/N", (Es - ro["E"]) / 12)
-    assert np.all(np.abs(Es - ro["E"]) / 12 <= 1e-7)
+    ro, Es, logs, st = _both(12, 8, 16, 16, 3, (0.5, 0.05, 0.1), 0.5, prec=tna.HEFF_F32, with_stats=True)
+    dEN = np.abs(Es - ro["E"]) / 12
+    print("f32 E", Es, "oracle", ro["E"], "dE/N", dEN, "stats", st)
+    assert st["heff_f32_iters"] >= st["lanczos_iters"] > 0
+    assert st["graph_launches"] == 0 and st["small_launches"] > 0
+    assert np.all(dEN <= 1e-7)
+    assert np.max(np.abs(Es - ro["E"]) / np.abs(ro["E"])) > 1e-12  # not FP64 arithmetic
+    assert all(g["lanczos_ok"] for g in logs)  # the stop rule is reachable with the FP32 operator
+
+
+def test_mixed_precision_grouped_path():
+    """G1 where theta exceeds the single-workgroup limit: chi held at 40 on N = 16, so the middle bonds
+    (theta up to 80 x 80) run the FP32 grouped GEMMs, FP32 mixing and the FP32 copies of L and R inside
+    the graph-replayed Lanczos.  Energies per visit and per sweep within 1e-7 per site of the FP64
+    oracle; after an ambiguous cut (oracle gap below 1e-8) the comparison adds that cut's discarded
+    weight."""
+    import paper_2604_03960_amd as tna
+    N = 16
+    ro, Es, logs, st = _both(N, 8, 40, 40, 2, (2.0, 0.1, 0.5), 1.0, prec=tna.HEFF_F32, with_stats=True)
+    print("f32 grouped: stats", st, "E", Es, "oracle", ro["E"])
+    assert st["graph_launches"] > 0 and st["heff_f32_iters"] >= st["lanczos_iters"] > 0
+    assert all(g["lanczos_ok"] for g in logs)
+    amb_w = 0.0
+    for g, o in zip(logs, ro["log"]):
+        assert (g["bond"], g["dir"]) == (int(o["bond"]), int(o["dir"]))
+        if g["chi_ctrl"] != int(o["chi_ctrl"]) or g["k"] != int(o["k"]):
+            assert o["gap"] < 1e-8, (g, o)
+            amb_w = max(amb_w, float(o["wdisc"]))
+            break
+        assert abs(g["E"] - o["E"]) / N <= 1e-7 + amb_w * abs(o["E"]) / N, (g["E"], o["E"])
+        if o["gap"] < 1e-8 and int(o["k"]) < min(int(o["m"]), int(o["n"])):
+            amb_w = max(amb_w, float(o["wdisc"]))
+    dEN = np.abs(Es - ro["E"]) / N
+    assert np.all(dEN <= 1e-7 + amb_w * np.abs(ro["E"]) / N), dEN
+    assert np.max(np.abs(Es - ro["E"]) / np.abs(ro["E"])) > 1e-12
+
+
+def _compare_amb(ro, Es, logs, etol, N):
+    """Visit by visit until the first ambiguous cut (oracle gap below 1e-8 with values discarded, or a
+    differing decision there); the per-sweep energies then get that cut's discarded weight (times |E|)
+    added to the tolerance."""
+    amb_w = 0.0
+    for g, o in zip(logs, ro["log"]):
+        assert (g["bond"], g["dir"]) == (int(o["bond"]), int(o["dir"]))
+        if g["chi_ctrl"] != int(o["chi_ctrl"]) or g["k"] != int(o["k"]):
+            assert o["gap"] < 1e-8, (g, o)
+            amb_w = max(float(o["wdisc"]), 1e-300)
+            break
+        assert abs(g["E"] - o["E"]) <= etol * abs(o["E"]), (g["bond"], g["dir"], g["E"], o["E"])
+        assert abs(g["S"] - o["S"]) <= 1e-8
+        if o["gap"] < 1e-8 and int(o["k"]) < min(int(o["m"]), int(o["n"])):
+            amb_w = max(float(o["wdisc"]), 1e-300)
+            break
+    assert np.all(np.abs(Es - ro["E"]) <= etol * np.abs(ro["E"]) + amb_w * np.abs(ro["E"]))
+    return amb_w
+
+
+def test_c2_headline_first_sweep():
+    """The adaptive configuration the sweep rate is quoted for: Heisenberg N = 100, PID gains (2, 0.1, 0.5),
+    S_target 1 nat, chi in [16, 1024], eps_target 1e-8, Lanczos tol 1e-12, the bench's initial MPS (seed 0,
+    chi 16).  One sweep, every visit against the oracle: controller decisions bit for bit, energies
+    within 1e-10 relative."""
+    import paper_2604_03960_amd as tna
+    N = 100
+    W = oracle.mpo(oracle.MODEL_XXZ, N, [1.0, 1.0, 0.0])
+    A, chi, _ = synth.random_mps(N, 2, 16, seed=0)
+    ro = oracle.dmrg_run(W, A, chi, oracle.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 16, 1024), 1, eps_target=1e-8)
+    dm = tna.Dmrg(ctx(), W, A, chi, tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 16, 1024), eps_target=1e-8)
+    E, recs, st = dm.sweep()
+    amb = _compare_amb(ro, np.array([E]), recs, 1e-10, N)
+    print(f"c2 first sweep: E/N gpu {E / N:.12f} oracle {ro['E'][0] / N:.12f} ambiguous_w {amb:.1e}")
+    assert len(recs) == 2 * (N - 1) and st in (0, tna.TNA_ERR_NOCONV)
+    assert abs(E - ro["E"][0]) / N <= 1e-10 + amb
+
+
+def test_fixed_iterations_grouped_path():
+    """The fixed-profile throughput mode (a fixed number of matvecs per Lanczos, every bond at
+    min(chi, rank)) at a chi that sends the middle bonds through the grouped, graph-replayed Lanczos:
+    N = 14, chi 40, 12 matvecs per visit, two sweeps, against the oracle's fixed-iteration Lanczos."""
+    import paper_2604_03960_amd as tna
+    N, chi_f, its = 14, 40, 12
+    W = oracle.mpo(oracle.MODEL_XXZ, N, [1.0, 1.0, 0.0])
+    A, chi, _ = synth.random_mps(N, 2, 8, seed=4)
+    pp = (2.0, 0.1, 0.5, 1.0, 0.3, 8, chi_f)
+    ro = oracle.dmrg_run(W, A, chi, oracle.pid_params(*pp), 2, fixed_iters=its, fixed_chi=chi_f)
+    dm = tna.Dmrg(ctx(), W, A, chi, tna.pid_params(*pp), fixed_iters=its, fixed_chi=chi_f)
+    Es, logs = [], []
+    for _ in range(2):
+        E, recs, st = dm.sweep()
+        Es.append(E)
+        logs += recs
+    st = dm.stats()
+    assert st["graph_launches"] > 0 and st["small_launches"] > 0
+    assert max(g["lanczos_iters"] for g in logs) == its
+    assert all(int(o["lanczos_iters"]) == g["lanczos_iters"] for g, o in zip(logs, ro["log"]))
+    amb = _compare_amb(ro, np.array(Es), logs, 1e-10, N)
+    print("fixed-iteration mode: E", Es, "oracle", ro["E"], "ambiguous_w", amb)

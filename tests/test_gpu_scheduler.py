@@ -55,3 +55,64 @@ def test_learned_scheduler_gain():
     assert s_ml["frac_eps_ok"] > s_pid["frac_eps_ok"]
     assert E_ml <= E_pid + 1e-10
     assert s_ml["scheduler_visits"] > 0
+    # ... at a cost: against the trivial predictor that always proposes chi_max (which meets the target
+    # wherever the rank allows), the learned proposals must be cheaper (sum of k^3 over the last sweep)
+    E_max, r_max = _run(ctx, 1, [1.0, 0.241], 20, 4, net=_constant_net(ctx, CHI[1]))
+    s_max = scheduler.summarize(r_max[-38:], EPS_T)
+    print("PID+chi_max", s_max, "E", E_max)
+    assert s_ml["sum_k3"] < s_max["sum_k3"]
+
+
+def _constant_net(ctx, k):
+    """A network whose output is log2(k) for every input (all weights zero, output bias log2 k)."""
+    import paper_2604_03960_amd as tna
+    p = np.zeros(tna.MLP_NPARAM, dtype=np.float32)
+    p[-1] = np.float32(np.log2(k))
+    return tna.Mlp(ctx, p)
+
+
+def test_scheduler_inputs_labels_and_fallback_match_oracle():
+    """The sweep's scheduler plumbing against the oracle's definitions, visit by visit: a network whose
+    output is the constant log2(20) proposes rank 20 at every visit after a bond's first, so the proposals
+    are known without running any network; the oracle receives the same proposals as inputs.  Compared:
+    the 25 inputs (FP32 on the GPU against FP64), k_needed (the label), the proposal used, the fallback
+    decision, the kept rank and the energy."""
+    import paper_2604_03960_amd as tna
+    ctx = tna.Context(0)
+    N, sweeps, kp = 16, 3, 20
+    W = oracle.mpo(0, N, [1.0, 1.0, 0.0])
+    A, chi, _ = synth.random_mps(N, 2, CHI[0], seed=5)
+    pid = (2.0, 0.1, 0.5, 1.0, 0.3, *CHI)
+    # run order: every L->R visit of the first sweep is a bond's first visit (no proposal)
+    pred = np.full(sweeps * 2 * (N - 1), kp, dtype=np.int32)
+    pred[:N - 1] = 0
+    ro = oracle.dmrg_run(W, A, chi, oracle.pid_params(*pid), sweeps, eps_target=EPS_T, sched_pred=pred)
+    dm = tna.Dmrg(ctx, W, A, chi, tna.pid_params(*pid), eps_target=EPS_T)
+    dm.set_scheduler(_constant_net(ctx, kp))
+    logs = []
+    for _ in range(sweeps):
+        logs += dm.sweep()[1]
+    nfb = nused = 0
+    for g, o in zip(logs, ro["log"]):
+        assert (g["bond"], g["dir"]) == (int(o["bond"]), int(o["dir"]))
+        S_o = float(o["sigma0"])
+        # the label: exact unless the oracle's tail sum sits within rounding of the target at the cut
+        if g["k_needed"] != int(o["k_needed"]):
+            pytest.fail(f"k_needed {g['k_needed']} vs {int(o['k_needed'])} at {g['bond']},{g['dir']}")
+        assert g["chi_sched"] == int(o["chi_sched"]) and g["fallback"] == int(o["fallback"])
+        if g["chi_ctrl"] != int(o["chi_ctrl"]) or g["k"] != int(o["k"]):
+            assert o["gap"] < 1e-8, (g, o)  # ambiguous cut: stop comparing this run
+            break
+        f_o = np.asarray(o["feat"], dtype=np.float64)
+        f_g = np.asarray(g["feat"], dtype=np.float64)
+        assert np.all(np.abs(f_g[:8] - f_o[:8]) <= 1e-6 * np.maximum(1.0, np.abs(f_o[:8])))
+        ln_floor = np.log(1e-16)
+        big = f_o[8:24] >= np.log(1e-10 * S_o)  # sigma well above the rounding level of either side
+        assert np.all(np.abs(f_g[8:24][big] - f_o[8:24][big]) <= 1e-5), (f_g[8:24], f_o[8:24])
+        assert np.all(f_g[8:24][~big] <= np.log(1e-9 * S_o) + 1e-6) and np.all(f_g[8:24] >= ln_floor - 1e-4)
+        assert f_g[24] == np.float32(f_o[24])
+        assert abs(g["E"] - o["E"]) <= 1e-10 * abs(o["E"])
+        nused += g["chi_sched"] > 0
+        nfb += g["fallback"]
+    print(f"scheduler plumbing: {nused} proposals, {nfb} fallbacks over {len(logs)} visits")
+    assert nused > 0 and 0 < nfb < nused  # both branches of the rule ran

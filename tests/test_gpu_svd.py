@@ -117,3 +117,34 @@ def test_prescribed_spectrum_chi1024_closed_form():
     Ad = torch.from_numpy(A).cuda()
     rec = (U * S[:k]) @ Vt
     assert (rec - U @ (U.T @ Ad)).abs().max().item() <= 64 * n * EPS
+
+
+def test_svd_batched_c3_against_closed_form_and_oracle():
+    """The isolated-SVD configuration at batch 16: sixteen 512 x 512 FP64 matrices (chi = 256) with
+    spectra exp(-k/8) and exp(-k/64) alternating, one batched call.  Every member's sigma against the
+    closed form, its kept factors orthonormal and reconstructing the kept part of A, its entropy
+    against the closed form; member 1 (tau = 64) against the oracle's Jacobi SVD as well."""
+    import torch
+    n, k, B = 512, 256, 16
+    taus = [8.0 if i % 2 == 0 else 64.0 for i in range(B)]
+    As = np.stack([synth.svd_test_matrix(n, taus[i], seed=0, index=i) for i in range(B)])
+    c = ctx()
+    Ad = torch.from_numpy(As).cuda()
+    S, U, Vt, spec, sw, st = c.svd_truncate_batched(Ad, k)
+    assert st == 0
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    for i in range(B):
+        sig = synth.svd_test_spectrum(n, taus[i])
+        Si = S[i].cpu().numpy()
+        assert np.abs(Si - sig).max() <= 64 * n * EPS, (i, np.abs(Si - sig).max())
+        assert (U[i].T @ U[i] - eye).abs().max().item() <= 64 * n * EPS
+        assert (Vt[i] @ Vt[i].T - eye).abs().max().item() <= 64 * n * EPS
+        rec = (U[i] * S[i, :k]) @ Vt[i]
+        assert (rec - U[i] @ (U[i].T @ Ad[i])).abs().max().item() <= 64 * n * EPS
+        q = math.exp(-2.0 / taus[i])
+        ent = -math.log((1 - q) / (1 - q ** n)) - (q / (1 - q) - n * q ** n / (1 - q ** n)) * math.log(q)
+        assert abs(spec[i, 1].item() - ent) <= 1e-10
+    So = oracle.svd(As[1])[0]
+    big = So >= 1e-4 * So[0]
+    S1 = S[1].cpu().numpy()
+    assert np.all(np.abs(S1[big] - So[big]) <= 1e-10 * So[big])
