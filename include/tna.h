@@ -167,7 +167,10 @@ typedef struct {
   int lanczos_fixed_iters;/* >0: exactly this many matvecs per visit (throughput mode) */
   int heff_prec;          /* tna_prec */
   int fixed_chi;          /* >0: keep min(fixed_chi, m, n) regardless of the controller */
-  int svd_max_sweeps;     /* default 60 */
+  int svd_max_sweeps;     /* default 60.  A visit whose Jacobi stops at this cap makes the sweep return
+                             TNA_ERR_NOCONV; the truncation then uses the stopped iteration's factors (the
+                             accumulated rotations stay orthonormal, the other factor does not), so the MPS
+                             is no longer in canonical form after it: a diagnostic setting */
   double eps_target;      /* truncation-error target that is reported (and used by schedulers) */
   int chi_rule;           /* rank rule: TNA_CHI_PID (Algorithm 2, default), TNA_CHI_THRESHOLD,
                              TNA_CHI_ENTROPY (Algorithm 1); fixed_chi > 0 overrides all three */

@@ -133,17 +133,8 @@ tna_status post_launch(const char *what) {
 }
 
 // ---------------------------------------------------------------- contraction recipes
-struct HeffOp {
-  int chl, chr, d, D;
-  const void *L;  // double or float (prec)
-  const void *R;
-  const double *M12;
-  void *X, *Z;    // scratch, D d^2 chl chr elements each
-  int prec;
-};
-
 // out = H_eff x (Eq. 18): S1 X = L x; S2 Z = W12-mix(X); S4 out = Z R^T.
-static tna_status heff_device(const HeffOp &h, const double *x, double *out, hipStream_t s) {
+tna_status heff_device(const HeffOp &h, const double *x, double *out, hipStream_t s) {
   const int chl = h.chl, chr = h.chr, d = h.d, D = h.D;
   const bool f32 = h.prec != TNA_HEFF_F64;
   const int tc = f32 ? G_F32 : G_F64;
@@ -427,6 +418,33 @@ tna_status entropy_update(const tna_pid_params *p, double gamma, tna_pid_state *
 
 using namespace tna;
 
+namespace tna {
+tna_status heff_check_args(tna_ctx c, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
+                           const double *W2, const double *R, const double *theta, double *out, int prec) {
+  if (!c || !L || !W1 || !W2 || !R || !theta || !out) {
+    set_error("heff_apply: null argument");
+    return TNA_ERR_ARG;
+  }
+  if (chi_l < 1 || chi_r < 1 || d < 1 || D < 1 || D * d * d > 32) {
+    set_error("heff_apply: need chi >= 1 and D*d*d <= 32");
+    return TNA_ERR_ARG;
+  }
+  if (prec < 0 || prec > 2) {
+    set_error("heff_apply: bad precision");
+    return TNA_ERR_ARG;
+  }
+  if (theta == out) {
+    set_error("heff_apply: out must not alias theta");
+    return TNA_ERR_ARG;
+  }
+  if (prec == TNA_HEFF_BF16X3) {
+    set_error("heff_apply: BF16x3 not built");
+    return TNA_ERR_UNSUPPORTED;
+  }
+  return TNA_OK;
+}
+}  // namespace tna
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -629,28 +647,10 @@ static tna_status svd_scratch(tna_ctx c, int batch, int m, int n, int dtype, Scr
   return TNA_OK;
 }
 
+
 tna_status tna_heff_apply(tna_ctx c, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
                           const double *W2, const double *R, const double *theta, double *out, int prec) {
-  if (!c || !L || !W1 || !W2 || !R || !theta || !out) {
-    set_error("heff_apply: null argument");
-    return TNA_ERR_ARG;
-  }
-  if (chi_l < 1 || chi_r < 1 || d < 1 || D < 1 || D * d * d > 32) {
-    set_error("heff_apply: need chi >= 1 and D*d*d <= 32");
-    return TNA_ERR_ARG;
-  }
-  if (prec < 0 || prec > 2) {
-    set_error("heff_apply: bad precision");
-    return TNA_ERR_ARG;
-  }
-  if (theta == out) {
-    set_error("heff_apply: out must not alias theta");
-    return TNA_ERR_ARG;
-  }
-  if (prec == TNA_HEFF_BF16X3) {
-    set_error("heff_apply: BF16x3 not built");
-    return TNA_ERR_UNSUPPORTED;
-  }
+  TNA_TRY(heff_check_args(c, chi_l, chi_r, d, D, L, W1, W2, R, theta, out, prec));
   hipStream_t s = c->stream;
   TNA_TRY(bind_scratch(c, heff_scratch(c, chi_l, chi_r, d, D, prec)));
   TNA_TRY(build_mix_matrix(0, d, D, W1, W2, c->m12.as<double>(), s));

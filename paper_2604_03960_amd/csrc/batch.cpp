@@ -874,7 +874,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     TNA_TRY(put_dev(en->ar, en->h_feat, (size_t)32 * nc, en->feat_d.as<float>(), s));
     for (size_t i = 0; i < want_pred.size(); ++i) {
       const int q = want_pred[i];
-      TNA_TRY(mlp_forward_dev(ch[q]->sched, 1, en->feat_d.as<float>() + 32 * q, en->y_d.as<float>() + 4 * q));
+      TNA_TRY(mlp_forward_dev(ch[q]->sched, 1, en->feat_d.as<float>() + 32 * q, en->y_d.as<float>() + 4 * q, s));
     }
     std::vector<float> yb(4 * nc);
     TNA_HIP(hipMemcpyAsync(yb.data(), en->y_d.ptr, sizeof(float) * 4 * nc, hipMemcpyDeviceToHost, s));

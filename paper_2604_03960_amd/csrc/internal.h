@@ -255,6 +255,19 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
                        std::vector<tna_visit_log *> &logs, tna_status *worst);
 double tridiag_lowest_host(int n, const double *a, const double *b, double *y);
 
+// ------------------------------------------------------------------ stand-alone H_eff (api.cpp)
+struct HeffOp {
+  int chl, chr, d, D;
+  const void *L;  // double or float (prec)
+  const void *R;
+  const double *M12;
+  void *X, *Z;    // scratch, D d^2 chl chr elements each
+  int prec;
+};
+tna_status heff_device(const HeffOp &h, const double *x, double *out, hipStream_t s);
+tna_status heff_check_args(tna_ctx c, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
+                           const double *W2, const double *R, const double *theta, double *out, int prec);
+
 // ------------------------------------------------------------------ host-side steps (api.cpp)
 tna_status env_left(int chl, int k, int d, int D, const double *L, const double *Ml, const double *A, double *T1,
                     double *T2, double *Ln, hipStream_t s);
@@ -263,7 +276,9 @@ tna_status env_right(int k, int chr, int d, int D, const double *R, const double
 tna_status pid_update(const tna_pid_params *p, tna_pid_state *st, double s_raw, int *chi_next, double *terms);
 tna_status entropy_update(const tna_pid_params *p, double gamma, tna_pid_state *st, double s_raw, int *chi_next,
                           double *terms);
-tna_status mlp_forward_dev(tna_mlp n, int B, const float *X, float *y);
+// forward pass on stream s (the caller's stream: the sweep engine passes its own, so the inputs it
+// uploaded and the outputs it reads back stay ordered with the launch)
+tna_status mlp_forward_dev(tna_mlp n, int B, const float *X, float *y, hipStream_t s);
 
 }  // namespace tna
 

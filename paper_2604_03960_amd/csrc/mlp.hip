@@ -234,9 +234,8 @@ static tna_status mlp_adam(tna_mlp n, const float *grad, float lr) {
 
 namespace tna {
 // forward of B samples already on the device (used by the DMRG scheduler)
-tna_status mlp_forward_dev(tna_mlp n, int B, const float *X, float *y) {
-  hipLaunchKernelGGL(forward_kernel, dim3((B + SB - 1) / SB), dim3(256), 0, n->ctx->stream, n->p.as<float>(), X, B,
-                     norm_of(n), y);
+tna_status mlp_forward_dev(tna_mlp n, int B, const float *X, float *y, hipStream_t s) {
+  hipLaunchKernelGGL(forward_kernel, dim3((B + SB - 1) / SB), dim3(256), 0, s, n->p.as<float>(), X, B, norm_of(n), y);
   TNA_LAUNCHED("mlp.forward");
   return TNA_OK;
 }
@@ -308,7 +307,7 @@ tna_status tna_mlp_forward(tna_mlp n, int B, const float *X, float *y) {
     set_error("mlp_forward: bad argument");
     return TNA_ERR_ARG;
   }
-  return mlp_forward_dev(n, B, X, y);
+  return mlp_forward_dev(n, B, X, y, n->ctx->stream);
 }
 
 tna_status tna_mlp_loss_grad(tna_mlp n, int B, const float *X, const float *T, float *grad, float *loss) {
