@@ -100,6 +100,23 @@ tna_status tna_mpo_build(int model, int N, const double *params, double *W, int 
 tna_status tna_heff_apply(tna_ctx ctx, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
                           const double *W2, const double *R, const double *theta, double *out, int prec);
 
+/* Allocation-free form of tna_heff_apply, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as tna_heff_apply, and the same
+ * kernels; the intermediates live in one fixed device array of
+ * TNA_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of
+ * context or workspace memory, and the call makes no allocation of any kind.  A
+ * shape whose scratch (tna_heff_apply_noalloc_bytes) exceeds the array returns
+ * TNA_ERR_ARG with nothing launched.  Every call on one GPU uses the same array:
+ * calls that overlap on a GPU (other streams, other contexts, other host threads)
+ * race, so the caller orders them (one stream, or events).  Nothing in the array
+ * needs clearing: each call overwrites what it reads. */
+#define TNA_NOALLOC_SCRATCH_BYTES (64u << 20)
+tna_status tna_heff_apply_noalloc(tna_ctx ctx, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
+                                  const double *W2, const double *R, const double *theta, double *out, int prec);
+/* Scratch bytes tna_heff_apply_noalloc needs for a shape (host only). */
+tna_status tna_heff_apply_noalloc_bytes(int chi_l, int chi_r, int d, int D, int prec, size_t *bytes);
+
 /* ---------------------------------------------------------------- SVD */
 /* Truncated SVD of Eq. (3)/(19), A = U diag(S) Vt, by blocked one-sided
  * Jacobi, plus the spectrum sums of Eq. (4)-(5).

@@ -89,6 +89,9 @@ _SIGS = {
     "tna_kernel_stats": ([_vp, C.c_char_p, C.c_size_t, C.c_int], C.c_int),
     "tna_mpo_build": ([C.c_int, C.c_int, _dp, _dp, _ip], C.c_int),
     "tna_heff_apply": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int], C.c_int),
+    "tna_heff_apply_noalloc": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int],
+                               C.c_int),
+    "tna_heff_apply_noalloc_bytes": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "tna_svd_truncate": ([_vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp, _vp, _vp, _vp, _ip, _ip], C.c_int),
     "tna_svd_truncate_batched": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_int, _vp, C.c_int64,
                                   _vp, C.c_int64, _vp, C.c_int64, _vp, _ip], C.c_int),
@@ -147,6 +150,15 @@ def _check(status, allow=()):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # TNA_NOALLOC_SCRATCH_BYTES
+
+
+def heff_apply_noalloc_bytes(chi_l, chi_r, d, D, prec=HEFF_F64) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.tna_heff_apply_noalloc_bytes(chi_l, chi_r, d, D, prec, C.byref(out)))
+    return out.value
 
 
 # ------------------------------------------------------------------ host-only helpers
@@ -254,6 +266,19 @@ class Context:
             out = torch.empty_like(theta)
         _check(_lib.tna_heff_apply(self.h, chl, chr_, d, D, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R), _ptr(theta),
                                    _ptr(out), prec))
+        return out
+
+    def heff_apply_noalloc(self, L, W1, W2, R, theta, out, prec=HEFF_F64):
+        """tna_heff_apply on the library's fixed device scratch: no allocation (out is caller-provided)."""
+        torch = self.torch
+        chl, D, _ = L.shape
+        chr_ = R.shape[0]
+        d = W1.shape[2]
+        for t in (L, W1, W2, R, theta, out):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        assert theta.shape == (chl, d, d, chr_) and out.shape == theta.shape
+        _check(_lib.tna_heff_apply_noalloc(self.h, chl, chr_, d, D, _ptr(L), _ptr(W1), _ptr(W2), _ptr(R),
+                                           _ptr(theta), _ptr(out), prec))
         return out
 
     # -------------------------------------------------------------- SVD

@@ -462,6 +462,7 @@ tna_status tna_create(tna_ctx *out, int device, void *hip_stream) {
     return TNA_ERR_ARG;
   }
   TNA_HIP(hipSetDevice(device));
+  TNA_TRY(noalloc_init(device));  // device address of the fixed scratch of tna_heff_apply_noalloc
   auto c = std::make_unique<tna_ctx_s>();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);

@@ -267,6 +267,8 @@ struct HeffOp {
 tna_status heff_device(const HeffOp &h, const double *x, double *out, hipStream_t s);
 tna_status heff_check_args(tna_ctx c, int chi_l, int chi_r, int d, int D, const double *L, const double *W1,
                            const double *W2, const double *R, const double *theta, double *out, int prec);
+// noalloc.cpp: records the calling device's address of the fixed scratch array (device current)
+tna_status noalloc_init(int device);
 
 // ------------------------------------------------------------------ host-side steps (api.cpp)
 tna_status env_left(int chl, int k, int d, int D, const double *L, const double *Ml, const double *A, double *T1,
