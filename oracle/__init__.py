@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "circuit.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", "-fno-fast-math"]
@@ -30,9 +31,9 @@ MODEL_XXZ, MODEL_J1J2, MODEL_TFIM = 0, 1, 2
 
 def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -53,6 +54,10 @@ class DmrgOpts(C.Structure):
                 ("fixed_iters", C.c_int), ("lanczos_tol", C.c_double), ("fixed_chi", C.c_int), ("pad", C.c_int),
                 ("chi_rule", C.c_int), ("pad2", C.c_int), ("rule_param", C.c_double),
                 ("eps_target", C.c_double), ("sched_pred", C.POINTER(C.c_int))]
+
+
+class CircuitOpts(C.Structure):
+    _fields_ = [("fixed_chi", C.c_int), ("pad", C.c_int)]
 
 
 _lib = None
@@ -95,6 +100,13 @@ def lib():
         _lib.or_adam_step.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_double]
         _lib.or_adam_step.restype = None
+        _lib.or_circuit_gates.argtypes = [C.c_int, C.c_int]
+        _lib.or_circuit_statevector.argtypes = [C.c_int, C.c_int, ip, dp, dp]
+        _lib.or_circuit_statevector.restype = None
+        _lib.or_circuit_run.argtypes = [C.c_int, C.c_int, ip, dp, C.POINTER(PidParams), C.POINTER(CircuitOpts), dp, ip,
+                                        dp, C.c_size_t, ip, dp, C.c_size_t]
+        _lib.or_mps_amplitudes.argtypes = [C.c_int, dp, ip, dp]
+        _lib.or_mps_amplitudes.restype = None
     return _lib
 
 
@@ -327,3 +339,52 @@ def mlp_loss_grad(params, x, t):
 def adam_step(params, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """In place on params, m, v (float64 arrays)."""
     lib().or_adam_step(len(params), _p(params), _p(_f64(g)), _p(m), _p(v), int(t), lr, b1, b2, eps)
+
+
+# ---------------------------------------------------------------- circuits with adaptive bond dimensions (Sec. 8)
+CIRC_LOG_NAMES = ["op", "bond", "m", "n", "k", "chi_ctrl", "S", "S_ema", "eps", "wdisc", "gap", "sigma0",
+                  "sigma_last", "u", "svd_sweeps", "Z"]
+
+
+def circuit_statevector(N: int, parity, gates, psi0=None) -> np.ndarray:
+    """Exact state vector after the ops (qubit 0 the most significant bit); starts from |0...0>."""
+    par = np.ascontiguousarray(parity, dtype=np.int32)
+    psi = np.zeros(1 << N)
+    if psi0 is None:
+        psi[0] = 1.0
+    else:
+        psi[:] = psi0
+    lib().or_circuit_statevector(N, len(par), _ip(par), _p(_f64(gates)), _p(psi))
+    return psi
+
+
+def circuit_run(N: int, parity, gates, pp: PidParams, fixed_chi: int = 0):
+    """The adaptive-chi MPS simulation of the ops from |0...0>: dict(log=[per-gate records], chimap (ops x
+    N-1), B (packed site tensors), chi (N-1), lam (list of Schmidt-value arrays))."""
+    par = np.ascontiguousarray(parity, dtype=np.int32)
+    ngate = sum(int(lib().or_circuit_gates(N, int(p))) for p in par)
+    log = np.zeros((ngate, len(CIRC_LOG_NAMES)))
+    chimap = np.zeros((len(par), N - 1), dtype=np.int32)
+    cap = 2 * N * 4096 * 4096 if N > 24 else 2 * N * (1 << N)
+    cap = min(cap, 1 << 26)
+    B = np.zeros(cap)
+    lam = np.zeros(N * 4096)
+    chi = np.zeros(N - 1, dtype=np.int32)
+    rc = lib().or_circuit_run(N, len(par), _ip(par), _p(_f64(gates)), C.byref(pp), C.byref(CircuitOpts(fixed_chi, 0)),
+                              _p(log), _ip(chimap), _p(B), cap, _ip(chi), _p(lam), len(lam))
+    if rc != 0:
+        raise ValueError("circuit_run: output capacity too small")
+    recs = [dict(zip(CIRC_LOG_NAMES, row)) for row in log]
+    n_b = sum((1 if i == 0 else int(chi[i - 1])) * 2 * (1 if i == N - 1 else int(chi[i])) for i in range(N))
+    lams, off = [], 0
+    for b in range(N - 1):
+        lams.append(lam[off:off + chi[b]].copy())
+        off += chi[b]
+    return dict(log=recs, chimap=chimap, B=B[:n_b].copy(), chi=chi, lam=lams)
+
+
+def mps_amplitudes(N: int, A_packed, chi) -> np.ndarray:
+    """psi(s_0..s_{N-1}) of an open-chain MPS (d = 2) by contraction, N <= 24."""
+    psi = np.zeros(1 << N)
+    lib().or_mps_amplitudes(N, _p(_f64(A_packed)), _ip(np.asarray(chi, dtype=np.int32)), _p(psi))
+    return psi

@@ -114,3 +114,39 @@ def xxz_chain_set(n_chains: int = 64, seed: int = 0, lengths=CHAIN_LENGTHS):
         idx = min(int(u[2 * c + 1] * len(lengths)), len(lengths) - 1)
         out.append((float(delta), int(lengths[idx])))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Circuit workload: a hardware-efficient ansatz of real gates (single-qubit
+# rotations RY(theta) = [[cos theta/2, -sin theta/2], [sin theta/2, cos theta/2]]
+# and CNOTs, control on the left qubit), as a list of ops.  One ansatz layer is
+# two ops: parity 0 applies CNOT (RY x RY) to the pairs (0,1), (2,3), ...;
+# parity 1 applies CNOT to (1,2), (3,4), ... (and, for odd N, the last qubit's
+# rotation before its CNOT).  Angles uniform in [0, 2 pi) from stream `seed`,
+# one per qubit per layer.  Gates are real 4 x 4 matrices G[2s+t][2s'+t'],
+# packed op after op in increasing bond.
+# ----------------------------------------------------------------------------
+_CNOT = np.array([[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 0, 1.0], [0, 0, 1.0, 0]])
+
+
+def ry(theta: float) -> np.ndarray:
+    c, s = math.cos(0.5 * theta), math.sin(0.5 * theta)
+    return np.array([[c, -s], [s, c]])
+
+
+def hea_circuit(N: int, layers: int, seed: int = 0):
+    """Returns (parity list, packed gates (float64), angles (layers x N))."""
+    ang = 2.0 * math.pi * uniform53(seed, 0, layers * N).reshape(layers, N)
+    parity, gates = [], []
+    eye = np.eye(2)
+    for l in range(layers):
+        parity.append(0)
+        for b in range(0, N - 1, 2):
+            gates.append(_CNOT @ np.kron(ry(ang[l, b]), ry(ang[l, b + 1])))
+        parity.append(1)
+        for b in range(1, N - 1, 2):
+            left = eye
+            right = ry(ang[l, b + 1]) if (N % 2 == 1 and b + 1 == N - 1) else eye
+            gates.append(_CNOT @ np.kron(left, right))
+    g = np.concatenate([x.ravel() for x in gates]) if gates else np.zeros(0)
+    return parity, g, ang
