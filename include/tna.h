@@ -313,6 +313,43 @@ int tna_autotune_entries(void);
 /* Empties the table (the next launches measure again). */
 void tna_autotune_clear(void);
 
+/* ---------------------------------------------------------------- circuits */
+/* Circuit simulation with adaptive bond dimensions (Sec. 8, circuit-level bond
+ * dimension maps; the TEBD scheme of Sec. 2).  An MPS of N qubits (d = 2) starts
+ * in |0...0>.  tna_circuit_layer applies one layer of real two-qubit gates to the
+ * disjoint pairs (b, b+1) with b = parity, parity + 2, ..., b <= N - 2 (gates_host:
+ * one row-major 4 x 4 matrix G[2s+t][2s'+t'] per pair in increasing b, s on qubit
+ * b; qubit 0 is the most significant bit of a basis state).  At every gate bond:
+ * the two-site tensor B_b B_{b+1}, the gate, the Schmidt-value scaling of the left
+ * bond, the Jacobi SVD (Eq. 3) of the full two-site matrix, its entropy (Eq. 5),
+ * the bond's EMA + PID (Eq. 8-11, Algorithm 2; the DMRG controller) or the fixed
+ * chi, truncation to k = min(chi, rank) with the kept values renormalised, then
+ * B_{b+1} <- Y_k^T and B_b <- (G B_b B_{b+1}) Y_k / |S_k|, so the MPS stays
+ * right-canonical with the Schmidt values of every bond and no division by one.
+ * All gates of a layer go through the same grouped launches (one group of SVDs);
+ * controllers of bonds the layer does not touch are left alone.  chi_row (host,
+ * N-1, may be NULL) receives the bond dimensions after the layer: one row of the
+ * bond-dimension map.  log (host, one record per gate, may be NULL).  Runs on the
+ * context stream (a private one when that is the null stream).  Synchronises. */
+typedef struct tna_circuit_s *tna_circuit;
+typedef struct {
+  int fixed_chi;       /* > 0: keep min(fixed_chi, rank) regardless of the controller */
+  int one_at_a_time;   /* 1: the gates of a layer run one after another (the unbatched form) */
+  int svd_max_sweeps;  /* default 60 */
+  int pad;
+} tna_circuit_opts;
+typedef struct {
+  int layer, bond, m, n, k, chi_ctrl, svd_sweeps, pad;
+  double S, S_ema, eps, wdisc, gap, sigma0, sigma_last, u;
+} tna_gate_log;
+tna_status tna_circuit_create(tna_ctx ctx, int N, const tna_pid_params *pid, const tna_circuit_opts *opts,
+                              tna_circuit *out);
+tna_status tna_circuit_layer(tna_circuit c, int parity, const double *gates_host, tna_gate_log *log, int *chi_row);
+/* Site tensors packed site after site (B_i: chi_{i-1} x 2 x chi_i) and the bond dimensions (N-1, may be
+ * NULL); B_host NULL only queries *count (doubles).  Synchronises. */
+tna_status tna_circuit_get_mps(tna_circuit c, double *B_host, size_t capacity, size_t *count, int *chi);
+void tna_circuit_destroy(tna_circuit c);
+
 /* ---------------------------------------------------------------- learned scheduler */
 /* A 25 -> 64 -> 64 -> 1 perceptron (tanh hidden units, linear output), the
  * learned stand-in for the predictive scheduler of Sec. 7, trained and run

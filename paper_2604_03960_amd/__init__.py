@@ -78,6 +78,15 @@ class BatchStats(C.Structure):
                 ("steps", C.c_int)]
 
 
+class CircuitOpts(C.Structure):
+    _fields_ = [("fixed_chi", C.c_int), ("one_at_a_time", C.c_int), ("svd_max_sweeps", C.c_int), ("pad", C.c_int)]
+
+
+class GateLog(C.Structure):
+    _fields_ = [(n, C.c_int) for n in ("layer", "bond", "m", "n", "k", "chi_ctrl", "svd_sweeps", "pad")] + \
+               [(n, C.c_double) for n in ("S", "S_ema", "eps", "wdisc", "gap", "sigma0", "sigma_last", "u")]
+
+
 _vp, _dp, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
 _SIGS = {
     "tna_create": ([C.POINTER(C.c_void_p), C.c_int, _vp], C.c_int),
@@ -125,6 +134,11 @@ _SIGS = {
     "tna_dmrg_batch_sweep": ([_vp, _dp, C.POINTER(VisitLog), C.POINTER(C.c_int64), C.POINTER(BatchStats)], C.c_int),
     "tna_dmrg_batch_get_state": ([_vp, C.c_int, _ip, C.POINTER(PidState)], C.c_int),
     "tna_dmrg_batch_destroy": ([_vp], None),
+    "tna_circuit_create": ([_vp, C.c_int, C.POINTER(PidParams), C.POINTER(CircuitOpts), C.POINTER(C.c_void_p)],
+                           C.c_int),
+    "tna_circuit_layer": ([_vp, C.c_int, _dp, C.POINTER(GateLog), _ip], C.c_int),
+    "tna_circuit_get_mps": ([_vp, _dp, C.c_size_t, C.POINTER(C.c_size_t), _ip], C.c_int),
+    "tna_circuit_destroy": ([_vp], None),
     "tna_autotune_save": ([C.c_char_p], C.c_int),
     "tna_autotune_load": ([C.c_char_p], C.c_int),
     "tna_autotune_entries": ([], C.c_int),
@@ -543,6 +557,63 @@ class DmrgBatch:
     def close(self):
         if getattr(self, "h", None):
             _lib.tna_dmrg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Circuit:
+    """Circuit simulation with adaptive bond dimensions: an MPS from |0...0> through layers of real
+    two-qubit gates (one grouped launch sequence per layer)."""
+
+    def __init__(self, ctx: Context, N: int, pid: PidParams, fixed_chi=0, one_at_a_time=False, svd_max_sweeps=60):
+        self.ctx, self.N = ctx, N
+        self.opts = CircuitOpts(fixed_chi, int(one_at_a_time), svd_max_sweeps, 0)
+        self.pid = pid
+        h = C.c_void_p()
+        _check(_lib.tna_circuit_create(ctx.h, N, C.byref(pid), C.byref(self.opts), C.byref(h)))
+        self.h = h
+
+    def layer(self, parity: int, gates):
+        """Applies one layer; returns (bond dimensions after it, list of per-gate dicts, status)."""
+        g = np.ascontiguousarray(gates, dtype=np.float64).ravel()
+        ng = len(range(parity, self.N - 1, 2))
+        assert g.size == 16 * ng
+        logs = (GateLog * max(ng, 1))()
+        row = np.zeros(self.N - 1, dtype=np.int32)
+        st = _check(_lib.tna_circuit_layer(self.h, parity, g.ctypes.data_as(_dp), logs, row.ctypes.data_as(_ip)),
+                    allow=(TNA_ERR_NOCONV,))
+        recs = [{f: getattr(r, f) for f, _ in GateLog._fields_} for r in logs[:ng]]
+        return row, recs, st
+
+    def run(self, parity, gates):
+        """All ops of a circuit (parity list, packed gates); returns (map: ops x (N-1), records)."""
+        g = np.ascontiguousarray(gates, dtype=np.float64).ravel()
+        rows, recs, off = [], [], 0
+        for p in parity:
+            ng = len(range(p, self.N - 1, 2))
+            row, r, _ = self.layer(p, g[off:off + 16 * ng])
+            off += 16 * ng
+            rows.append(row)
+            recs += r
+        return np.array(rows), recs
+
+    def mps(self):
+        cnt = C.c_size_t(0)
+        chi = np.zeros(self.N - 1, dtype=np.int32)
+        _check(_lib.tna_circuit_get_mps(self.h, None, 0, C.byref(cnt), chi.ctypes.data_as(_ip)))
+        out = np.zeros(cnt.value)
+        _check(_lib.tna_circuit_get_mps(self.h, out.ctypes.data_as(_dp), cnt.value, C.byref(cnt),
+                                        chi.ctypes.data_as(_ip)))
+        return out, chi
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tna_circuit_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtna.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "mlp.hip", "batch.hip", "api.cpp", "dmrg.cpp", "batch.cpp", "noalloc.cpp"]
+SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "mlp.hip", "batch.hip", "api.cpp", "dmrg.cpp", "batch.cpp", "noalloc.cpp", "circuit.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=fast",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]

@@ -782,7 +782,12 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   std::vector<SvdMat> mats(nc);
   size_t nd = 0, ni = 0, ns = 0;
   for (int q = 0; q < nc; ++q) {
-    TNA_TRY(svd_plan_mat(vs[q].m, vs[q].n, TNA_F64, nc, &mats[q]));
+    // the isometric factor comes from the accumulated rotations (orthonormal whatever the
+    // convergence of rows at the rounding level): left to right the rows of theta are
+    // orthogonalised (U isometric, Vt scaled), right to left its columns (Vt isometric, U scaled);
+    // a rectangular theta keeps the orientation its shape needs
+    TNA_TRY(svd_plan_mat(vs[q].m, vs[q].n, TNA_F64, nc, &mats[q], vs[q].half == 0 ? 1 : 2));
+    mats[q].rows_scaled = vs[q].half == 0 ? !mats[q].trans : mats[q].trans;
     nd += svd_work_doubles(mats[q]);
     ni += svd_work_ints(mats[q]);
     ns += mats[q].R;

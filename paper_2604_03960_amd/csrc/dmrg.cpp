@@ -49,7 +49,9 @@ static tna_status check_dmrg_args(int N, int d, int D, const double *W, const do
 static tna_status svd_start(tna_dmrg dm, int m, int n, const double *src, SvdMat *mat, int *sweeps) {
   tna_ctx c = dm->ctx;
   SvdMat a;
-  TNA_TRY(svd_plan_mat(m, n, TNA_F64, 1, &a));
+  // Vt becomes the right-canonical tensor (from the rotations when the shape allows), U S the left one
+  TNA_TRY(svd_plan_mat(m, n, TNA_F64, 1, &a, 2));
+  a.rows_scaled = a.trans;
   const size_t nd = svd_work_doubles(a), ni = svd_work_ints(a);
   TNA_TRY(c->svd.work_d.ensure(sizeof(double) * nd));
   TNA_TRY(c->svd.work_i.ensure(sizeof(int) * ni));

@@ -170,6 +170,10 @@ struct SvdMat {
   int precond, pad2_;                          // 1: rows start from the R factor of a Householder QR
   int *cperm, *pinv;                           // work: original column at position c, and its inverse (C each)
   double *qv, *qws;                            // work: reflectors as rows (R x R), blocked-product scratch
+  int rows_scaled;  // 1: the factor built from the orthogonalised rows (Vt, or U when trans) leaves the call
+                    // multiplied by the singular values or unused, so it need not be orthonormal: rows at the
+                    // rounding level stay unrotated after the QR start too, and null vectors are not completed
+  int pad4_;
 };
 struct SvdGroup {
   DevBuf desc, work_d, work_i;
@@ -179,7 +183,8 @@ struct SvdGroup {
   double *host_fro = nullptr;  // pinned: squared Frobenius norms of the inputs (finiteness check)
   void release();
 };
-tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a);
+// orient (square matrices only): 0 by shape (rows of A), 1 rows of A, 2 rows of A^T (columns of A)
+tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a, int orient = 0);
 size_t svd_work_doubles(const SvdMat &a);
 size_t svd_work_ints(const SvdMat &a);
 void svd_bind_work(SvdMat *a, double *dw, int *iw);

@@ -124,6 +124,7 @@ __device__ inline double bsum256(double v, double *red) {
 // 64 x 64 Gram of the rows of blocks p and q over columns [kb, ke) on MFMA:
 // wave (qi, qj) holds the 32 x 32 quadrant (qi, qj) as 2 x 2 16 x 16 tiles.
 constexpr int GBK = 32;
+// The next 32-column slab is loaded into registers while the current one is multiplied.
 __device__ inline void gram_acc(const SvdMat &a, int p, int q, int np, int nq, int64_t kb, int64_t ke,
                                 double (*Ts)[65], v4d acc[2][2]) {
   const double *B = a.bw;
@@ -134,16 +135,28 @@ __device__ inline void gram_acc(const SvdMat &a, int p, int q, int np, int nq, i
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+  // thread tid loads column tid % 32 of rows tid / 32 + 8u, u < 8
+  const int col = tid % GBK, r0 = tid / GBK;
+  const double *rowp[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int r = r0 + 8 * u;
+    const bool valid = r < 32 ? (r < np) : (r - 32 < nq);
+    const int grow = r < 32 ? p * BS + r : q * BS + (r - 32);
+    rowp[u] = valid ? B + (int64_t)grow * a.C : nullptr;
+  }
+  double nx[8];
+  auto load = [&](int64_t k0) {
+    const int64_t gc = k0 + col;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) nx[u] = (rowp[u] && gc < ke) ? rowp[u][gc] : 0.0;
+  };
+  if (kb < ke) load(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int col = tid % GBK, r = tid / GBK + 8 * u;
-      const bool valid = r < 32 ? (r < np) : (r - 32 < nq);
-      const int grow = r < 32 ? p * BS + r : q * BS + (r - 32);
-      const int64_t gc = k0 + col;
-      Ts[col][r] = (valid && gc < ke) ? B[(int64_t)grow * a.C + gc] : 0.0;
-    }
+    for (int u = 0; u < 8; ++u) Ts[col][r0 + 8 * u] = nx[u];
     __syncthreads();
+    if (k0 + GBK < ke) load(k0 + GBK);  // in flight during the products below
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       double av[2], bv[2];
@@ -212,10 +225,12 @@ struct EigLds {
 // row are neither tested nor rotated (the relative test could never settle on them).
 // Skipping a coupling g_ij <= sigma_i sigma_floor moves sigma_i by at most
 // sigma_floor^2 / sigma_i; kept vectors below the floor are completed afterwards.
-// After the QR start even rows at the rounding level
-// settle under the relative test, so no floor is used there.
+// After the QR start such rows do settle under the relative test, but only after many
+// more sweeps (a numerically low-rank matrix can need twice as many), so the floor is
+// used there only when the factor built from the rows leaves scaled by the singular
+// values (rows_scaled): then nothing needs their directions.
 __device__ inline double row_floor2(const SvdMat &a, double fro2) {
-  if (a.precond) return 0.0;
+  if (a.precond && !a.rows_scaled) return 0.0;
   const double f = 0.1 * EPS53 * (double)a.C;
   return f * f * fro2;
 }
@@ -437,11 +452,13 @@ __device__ inline void apply_tile(double *X, int ld, int c0, double (*As)[65], d
     }
 }
 
-// grid (pairs, groups of APPLY_TPW column tiles of B then of Jt, matrices): the pair's
-// rotation is read into LDS once and applied to each tile of the group in turn
+// grid (pairs, groups of APPLY_TPW column tiles of B then of Jt, matrices).  Each wave
+// keeps its 16 rows of the pair's rotation Qt as MFMA A-operands in registers (read once);
+// the 64 x 64 tile of X passes through LDS, and the next tile of the group is loaded into
+// registers while the current one is multiplied and written back, so one workgroup keeps
+// a tile's loads in flight at all times.  33 KB of LDS: four workgroups per CU.
 constexpr int APPLY_TPW = 4;
 __global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step) {
-  __shared__ double As[64][65];  // As[k][i] = Qt[i][k]
   __shared__ double Xs[64][65];  // Xs[k][j] = X[row(k)][c0 + j]
   const SvdMat &a = mats[blockIdx.z];
   const int pair = blockIdx.x;
@@ -454,19 +471,56 @@ __global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step
   const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
   auto grow = [&](int r) { return r < 32 ? p * BS + r : q * BS + (r - 32); };
-  const double *Qt = a.qt + (int64_t)pair * 4096;
-  for (int e = threadIdx.x; e < 4096; e += 256) {
-    const int i = e >> 6, k = e & 63;
-    As[k][i] = Qt[e];
-  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // A(i, k) = Qt[i][k] for the wave's output rows i = 16 wave + lr, k = 4 kk + lk
+  const double *Qt = a.qt + (int64_t)pair * 4096 + (16 * wave + lr) * 64 + lk;
+  double aq[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) aq[kk] = Qt[4 * kk];
   const int t1 = t0 + APPLY_TPW < ntile_b + ntile_j ? t0 + APPLY_TPW : ntile_b + ntile_j;
-  for (int tile = t0; tile < t1; ++tile) {
-    double *X;
-    int ld, c0;
+  // thread tid loads rows (tid >> 6) + 4u, u < 16, at column tid & 63 of a tile
+  const int lrow = tid >> 6, lcol = tid & 63;
+  auto tile_of = [&](int tile, double *&X, int &ld, int &c0) {
     if (tile < ntile_b) { X = a.bw; ld = a.C; c0 = tile * 64; }
     else { X = a.jt; ld = a.R; c0 = (tile - ntile_b) * 64; }
-    apply_tile(X, ld, c0, As, Xs, valid, grow);
-    __syncthreads();  // Xs is refilled by the next tile
+  };
+  double nx[16];
+  auto load = [&](int tile) {
+    double *X;
+    int ld, c0;
+    tile_of(tile, X, ld, c0);
+    const bool colok = c0 + lcol < ld;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = lrow + 4 * u;
+      nx[u] = (colok && valid(k)) ? X[(int64_t)grow(k) * ld + c0 + lcol] : 0.0;
+    }
+  };
+  load(t0);
+  for (int tile = t0; tile < t1; ++tile) {
+    __syncthreads();  // the previous tile's products have read Xs
+#pragma unroll
+    for (int u = 0; u < 16; ++u) Xs[lrow + 4 * u][lcol] = nx[u];
+    __syncthreads();
+    if (tile + 1 < t1) load(tile + 1);  // in flight during the products below
+    v4d acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = v4d{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = mfma16(aq[kk], Xs[4 * kk + lk][16 * t + lr], acc[t]);
+    double *X;
+    int ld, c0;
+    tile_of(tile, X, ld, c0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int so = 16 * wave + 4 * r + lk, col = 16 * t + lr;  // f64 result layout
+        if (valid(so) && c0 + col < ld) X[(int64_t)grow(so) * ld + c0 + col] = acc[t][r];
+      }
   }
 }
 
@@ -977,10 +1031,10 @@ __global__ __launch_bounds__(256) void trunc_kernel(const SvdMat *mats) {
 
 // Kept values at or below this are null: at the rounding level of sigma_0 or under the
 // Jacobi row floor (whose rows were never orthogonalised against the others).  With the
-// QR start every row with a nonzero norm was orthogonalised, so only rows whose
-// squares underflow count as null there.
+// QR start and no floor (rows_scaled off) every row with a nonzero norm was
+// orthogonalised, so only rows whose squares underflow count as null there.
 __device__ inline double null_threshold(const SvdMat &a) {
-  if (a.precond) return 1e-150 * a.S[0];
+  if (a.precond && !a.rows_scaled) return 1e-150 * a.S[0];
   const double C = (double)(a.m > a.n ? a.m : a.n);
   return EPS53 * C * fmax(a.S[0], 0.1 * sqrt(*a.fro2));
 }
@@ -1072,7 +1126,7 @@ __global__ __launch_bounds__(256) void complete_kernel(const SvdMat *mats) {
   __shared__ double red[4];
   __shared__ int ok;
   const SvdMat &a = mats[blockIdx.x];
-  if (a.k < 1) return;
+  if (a.k < 1 || a.rows_scaled) return;  // the factor to complete leaves scaled by (near-)zero values
   // only matrices with a kept null vector do any work
   const double thr = null_threshold(a);
   if (a.S[a.k - 1] > thr && a.S[a.k - 1] > 0.0) return;
@@ -1136,7 +1190,7 @@ constexpr int QR_MIN_ROWS = QR_MIN_ROWS_DEV;
 }  // namespace
 
 // ====================================================================== host
-tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
+tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a, int orient) {
   if (m < 1 || n < 1) {
     set_error("svd: dimensions must be positive");
     return TNA_ERR_ARG;
@@ -1144,7 +1198,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a) {
   *a = SvdMat{};
   a->m = m;
   a->n = n;
-  a->trans = m > n;
+  a->trans = m > n || (m == n && orient == 2);
   a->R = m < n ? m : n;
   a->C = m < n ? n : m;
   a->dtype = dtype;
