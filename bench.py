@@ -53,7 +53,9 @@ def parse():
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--roofline-kernel", default="", help="kernel-name prefix to time (default: auto)")
     ap.add_argument("--workload", choices=["chi2048", "heisenberg100", "xxz_batch", "svd", "fixed_chi", "scheduler",
-                                           "rules"], default="chi2048")
+                                           "rules", "circuit"], default="chi2048")
+    ap.add_argument("--qubits", type=int, default=64, help="circuit: number of qubits")
+    ap.add_argument("--layers", type=int, default=24, help="circuit: ansatz layers (two gate layers each)")
     ap.add_argument("--no-f32", action="store_true", help="chi2048: skip the FP32-H_eff companion run")
     ap.add_argument("--no-pid", action="store_true", help="chi2048: skip the N=100 PID parity and rate")
     ap.add_argument("--chi", type=int, default=256, help="fixed_chi: bond dimension")
@@ -109,6 +111,13 @@ def progress(msg):
 
 
 def roofline_from(stats, dominant):
+    """Roofline of the kernel (or kernel family: every timer name that starts with `dominant`) from HIP
+    events: algorithmic flops or bytes per launch over the mean launch time."""
+    fam = [r for r in stats if r["name"].startswith(dominant) and r["count"] > 0]
+    if len(fam) > 1:
+        agg = {"name": dominant, "count": sum(r["count"] for r in fam), "ms": sum(r["ms"] for r in fam),
+               "flops": sum(r["flops"] for r in fam), "bytes": sum(r["bytes"] for r in fam)}
+        stats = [agg]
     for r in stats:
         if r["name"] == dominant and r["count"] > 0:
             avg_ms = r["ms"] / r["count"]
@@ -498,7 +507,13 @@ def run_chi2048(a):
     for _ in range(max(a.warmup, 1) - 1):
         _visit(dm, c, dirn)
         dirn ^= 1
-    dominant = a.roofline_kernel or (max(ranking, key=lambda r: r["ms"])["name"] if ranking else "")
+    # dominant kernel family (timer names up to the tile suffix: the H_eff GEMMs' NN and NT forms are one
+    # kernel template, gemm_grouped_kernel) by time in the ranking visit
+    fams = {}
+    for r in ranking:
+        f = ".".join(r["name"].split(".")[:2])
+        fams[f] = fams.get(f, 0.0) + r["ms"]
+    dominant = a.roofline_kernel or (max(fams, key=fams.get) if fams else "")
     if dominant:
         ctx.set_timing(True, dominant)
     torch.cuda.synchronize()
@@ -540,14 +555,17 @@ def run_chi2048(a):
     if not a.no_f32:
         dm32, t32, E_sweep32 = prepare(tna.HEFF_F32, "f32")
         E_first32, _, _ = _visit(dm32, c, 0)
-        k32 = min(3, a.steps)
+        k32 = 4  # two visits in each direction, like the timed steps
         tt = 0.0
         dd = 1
+        ph32 = []
         for _ in range(k32):
-            _, _, dt = _visit(dm32, c, dd)
+            _, r32, dt = _visit(dm32, c, dd)
             dd ^= 1
             tt += dt
+            ph32.append(r32)
         g1 = {"ms_per_step": 1e3 * tt / k32, "steps": k32,
+              "phase_ms_per_step": {k: float(np.mean([r[k] for r in ph32])) for k in ("ms_lanczos", "ms_svd", "ms_other")},
               "sweeps_per_s_N100": 1.0 / (sum(t for (b, h), t in t32.items() if b != c) + N_FULL * tt / k32),
               "dE_per_site_vs_f64_first_centre_visit": abs(E_first32 - E_first64) / Nv,
               "dE_per_site_vs_f64_after_warmup_sweep": abs(E_sweep32 - E_sweep64) / Nv}
@@ -615,6 +633,46 @@ def run_chi2048(a):
         "cpu_baseline": cpu.get("cpu_baseline"),
         "kernel_ranking_one_step": sorted(ranking, key=lambda r: -r["ms"])[:10],
     }
+    print(json.dumps(out))
+
+
+def run_circuit(a):
+    """Circuit simulation with adaptive bond dimensions (the circuit-level bond-dimension map): a
+    hardware-efficient ansatz (RY rotations and CNOT brickwork) of N qubits and L layers, the PID
+    choosing each gate bond's dimension (chi in [chi_min, chi_max]); every gate layer's SVDs as one
+    group, against the same gates one at a time."""
+    import numpy as np
+    import torch
+
+    import paper_2604_03960_amd as tna
+    import synth
+    ctx = tna.Context(0)
+    N, L = a.qubits, a.layers
+    par, g, _ = synth.hea_circuit(N, L, seed=0)
+    pid = tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 4, a.chi_max)
+    out_runs = {}
+    for name, one in (("batched", False), ("one_at_a_time", True)):
+        circ = tna.Circuit(ctx, N, pid, one_at_a_time=one)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cmap, recs = circ.run(par, g)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out_runs[name] = {"s": dt, "gates_per_s": len(recs) / dt, "layers_per_s": L / dt,
+                          "chi_max_reached": int(cmap.max()), "chi_mean_last": float(cmap[-1].mean()),
+                          "trunc_err_sum": float(sum(r["eps"] for r in recs))}
+        if name == "batched":
+            chi_map = cmap
+        circ.close()
+        progress(f"circuit {name} done")
+    b, s = out_runs["batched"], out_runs["one_at_a_time"]
+    out = {"metric": f"gate layers/s, {N}-qubit hardware-efficient ansatz with adaptive chi", "value": b["layers_per_s"],
+           "unit": "layers/s", "n_gpus": 1, "steps": L, "warmup": 0, "ms_per_step": 1e3 * b["s"] / L,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"hea_N{N}_L{L}_pid_chi4-{a.chi_max}", "qubits": N, "ansatz_layers": L,
+                      "gate_layers": 2 * L},
+           "runs": out_runs, "speedup_batched_vs_one_at_a_time": s["s"] / b["s"],
+           "chi_map_every_4th_layer": chi_map[::8].tolist()}
     print(json.dumps(out))
 
 
@@ -719,7 +777,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
     runs = {"chi2048": run_chi2048, "heisenberg100": run_pid100, "xxz_batch": run_batch, "svd": run_svd,
-            "fixed_chi": run_fixed_chi, "scheduler": run_scheduler, "rules": run_rules}
+            "fixed_chi": run_fixed_chi, "scheduler": run_scheduler, "rules": run_rules, "circuit": run_circuit}
     return runs[a.workload](a)
 
 

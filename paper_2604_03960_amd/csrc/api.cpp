@@ -643,7 +643,7 @@ static tna_status svd_scratch(tna_ctx c, int batch, int m, int n, int dtype, Scr
   const size_t nd = svd_work_doubles(*proto), ni = svd_work_ints(*proto);
   *out = ScratchList{{&c->svd.work_d, sizeof(double) * nd * batch},
                      {&c->svd.work_i, sizeof(int) * ni * batch},
-                     {&c->spec, sizeof(double) * 24 * batch},
+                     {&c->spec, sizeof(double) * 32 * batch},
                      {&c->svd.desc, sizeof(SvdMat) * batch}};
   return TNA_OK;
 }
@@ -694,7 +694,7 @@ static tna_status svd_common(tna_ctx c, int batch, int m, int n, int dtype, cons
     svd_bind_work(&a, c->svd.work_d.as<double>() + nd * z, c->svd.work_i.as<int>() + ni * z);
     a.A = static_cast<const char *>(A) + el * strideA * z;
     a.S = S + strideS * z;
-    a.spec = c->spec.as<double>() + 24 * z;
+    a.spec = c->spec.as<double>() + 32 * z;
     a.U = static_cast<char *>(U) + el * strideU * z;
     a.Vt = static_cast<char *>(Vt) + el * strideVt * z;
     a.k = k;
@@ -707,7 +707,7 @@ static tna_status svd_common(tna_ctx c, int batch, int m, int n, int dtype, cons
   tna_status st = svd_group_run(mats, c->svd, 60, sweeps, s);
   if (st != TNA_OK && st != TNA_ERR_NOCONV) return st;
   TNA_TRY(svd_group_outputs(mats, c->svd, s));
-  TNA_HIP(hipMemcpy2DAsync(spec, 6 * sizeof(double), c->spec.ptr, 24 * sizeof(double), 6 * sizeof(double), batch,
+  TNA_HIP(hipMemcpy2DAsync(spec, 6 * sizeof(double), c->spec.ptr, 32 * sizeof(double), 6 * sizeof(double), batch,
                            hipMemcpyDeviceToDevice, s));
   if (k_out) *k_out = k;
   if (sweeps_out) *sweeps_out = sweeps.empty() ? 0 : *std::max_element(sweeps.begin(), sweeps.end());

@@ -414,8 +414,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     max_mix = std::max<int64_t>(max_mix, (int64_t)v.chl * v.chr);
   }
   const int tc = f32 ? G_F32 : G_F64;
-  GemmGroup g1{0, 0, tc, G_F64, tc, tc, 64, 1.0, 0.0, 0.0, 0.0};
-  GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, 0.0, 0.0, 0.0};
+  GemmGroup g1{0, 0, tc, G_F64, tc, tc, 64, 1.0, 0.0, 0.0, 0.0, "heff"};  // the H_eff products S1 and S4
+  GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, 0.0, 0.0, 0.0, "heff"};
   for (int q = 0; q < nc; ++q) {
     en->hflags[slot[q]] = 0;
     en->hflags[en->nslot + slot[q]] = 1;
@@ -455,7 +455,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   const MixProb *dmx = nullptr;
   const GemmProb *dp1 = nullptr, *dp4 = nullptr;
   int tot1 = 0, tot4 = 0;
-  const bool use_graph = !(timing_may_match("gemmg") || timing_may_match("mixg") || timing_may_match("lz."));
+  const bool use_graph =
+      !(timing_may_match("heff") || timing_may_match("gemmg") || timing_may_match("mixg") || timing_may_match("lz."));
   double lz_bytes = 0.0;  // one CGS pass at the current iteration, all chains (timing only)
   auto lz_hint = [&](int it) {
     double b = 0.0;
@@ -788,6 +789,14 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     // a rectangular theta keeps the orientation its shape needs
     TNA_TRY(svd_plan_mat(vs[q].m, vs[q].n, TNA_F64, nc, &mats[q], vs[q].half == 0 ? 1 : 2));
     mats[q].rows_scaled = vs[q].half == 0 ? !mats[q].trans : mats[q].trans;
+    // with the FP32 operator theta carries noise of about 1e-7 of its norm: rows below it are
+    // rounding-level rows for the Jacobi, and the numerical rank is counted above it
+    if (f32) mats[q].noise_rel = 1e-7;
+    // a numerically low-rank theta (at most a quarter of its values above 1e-12 sigma_0 at the bond's
+    // previous visit) skips the QR start: with the rounding-level rows left unrotated the Jacobi settles
+    // in as few sweeps without it, and the panel factorisation is the dearer part
+    const int nr = ch[q]->nrank[vs[q].b];
+    if (mats[q].rows_scaled && mats[q].precond && nr > 0 && 4 * nr <= mats[q].R) mats[q].precond = 0;
     nd += svd_work_doubles(mats[q]);
     ni += svd_work_ints(mats[q]);
     ns += mats[q].R;
@@ -840,6 +849,7 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     const Visit &v = vs[q];
     const double *h = en->h_dbl + SPEC * q;
     const double Sent = h[1];
+    dm->nrank[v.b] = (int)h[25];
     kneed[q] = (int)h[6];
     // rank rule: Algorithm 2 (PID, also run and logged under the threshold rule) or Algorithm 1
     if (dm->opts.chi_rule == TNA_CHI_ENTROPY)

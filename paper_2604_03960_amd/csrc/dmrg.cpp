@@ -120,6 +120,7 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
   dm->hist.assign(N - 1, std::array<double, 8>{});
   dm->nhist.assign(N - 1, 0);
   dm->pred.assign(N - 1, 0);
+  dm->nrank.assign(N - 1, 0);
   // MPO and mixing matrices
   const size_t wsz = (size_t)D * D * d * d;
   TNA_TRY(dm->W.ensure(sizeof(double) * wsz * N));
@@ -143,7 +144,7 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
     TNA_HIP(hipMemcpy(dm->A[i].ptr, A_host + off, sizeof(double) * n, hipMemcpyHostToDevice));
     off += n;
   }
-  TNA_TRY(dm->spec.ensure(sizeof(double) * 24));
+  TNA_TRY(dm->spec.ensure(sizeof(double) * 32));
   // right-canonicalise on the device: A_b = U S Vt -> A_b <- Vt, A_{b-1} <- A_{b-1} U S
   DevBuf Ub, Vb, Tb;
   for (int b = N - 1; b >= 1; --b) {

@@ -242,8 +242,8 @@ tna_status launch_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int 
   if (grid < 1) return TNA_OK;
   char name[64] = "";
   if (timing_on()) {
-    std::snprintf(name, sizeof name, "gemmg.%s.%dx%d.%c%c", sizeof(T) == 8 ? "f64" : "f32", BM, BN,
-                  g.transA ? 'T' : 'N', g.transB ? 'T' : 'N');
+    std::snprintf(name, sizeof name, "%s.%s.%dx%d.%c%c", g.tag ? g.tag : "gemmg", sizeof(T) == 8 ? "f64" : "f32", BM,
+                  BN, g.transA ? 'T' : 'N', g.transB ? 'T' : 'N');
     timer_begin(name, s);
   }
   if (!g.transA && !g.transB)

@@ -101,6 +101,7 @@ struct GemmGroup {
   int transA, transB, typeA, typeB, typeC, compute, tile;
   double alpha, beta;
   double flops, bytes;  // algorithmic work of the whole launch (timing only)
+  const char *tag = nullptr;  // timer name prefix (default "gemmg")
 };
 // Assigns tile ranges for a square tile of the given size; returns the total.
 int gemm_group_tiles(std::vector<GemmProb> &probs, int tile);
@@ -163,13 +164,17 @@ struct SvdMat {
   const void *A;                               // m x n (dtype)
   double *bw, *jt, *gram, *qt, *sig;           // work
   double *S;                                   // R sorted values (output)
-  double *spec;                                // 24 doubles: Z, S_vN, eps, eps^2/Z, |S_k|, gap, k_needed, sweeps, S_0..S_15
+  double *spec;                                // 32 doubles: Z, S_vN, eps, eps^2/Z, |S_k|, gap, k_needed, sweeps,
+                                               // S_0..S_15, [24] values above thr, [25] values above 1e-12 S_0
   int *skip, *perm, *ctr;                      // work
   void *U, *Vt;                                // m x k, k x n (out_type)
   double *fro2;                                // work: |A|_F^2 (device scalar)
   int precond, pad2_;                          // 1: rows start from the R factor of a Householder QR
   int *cperm, *pinv;                           // work: original column at position c, and its inverse (C each)
   double *qv, *qws;                            // work: reflectors as rows (R x R), blocked-product scratch
+  double noise_rel;  // > 0: the input carries noise of about noise_rel |A|_F (an FP32 operator upstream); rows
+                     // below it count as rounding-level rows, and the numerical rank spec[25] counts values above
+                     // noise_rel S_0 (default: 1e-12 S_0)
   int rows_scaled;  // 1: the factor built from the orthogonalised rows (Vt, or U when trans) leaves the call
                     // multiplied by the singular values or unused, so it need not be orthonormal: rows at the
                     // rounding level stay unrotated after the QR start too, and null vectors are not completed
@@ -321,6 +326,7 @@ struct tna_dmrg_s {
   tna_mlp sched = nullptr;
   std::vector<std::array<double, 8>> hist;  // last EMA entropies per bond (oldest first)
   std::vector<int> nhist, pred;             // history length, pending proposal (0 = none)
+  std::vector<int> nrank;                   // per bond: values above 1e-12 sigma_0 at its last visit (0 = none yet)
   tna::tna_engine engine = nullptr;          // the step engine this chain's sweeps run on
   int CL(int i) const { return i == 0 ? 1 : chi[i - 1]; }
   int CR(int i) const { return i == N - 1 ? 1 : chi[i]; }

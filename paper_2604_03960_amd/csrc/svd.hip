@@ -218,6 +218,8 @@ struct EigLds {
   int slot_of[64];
   int vs[64];                   // valid slots in order
   unsigned short sched[63][32]; // round-robin pairs (i | j << 8) of one sweep
+  unsigned short pcol[63][64];  // per round and column: partner | pair << 6 | (first of its pair) << 11
+  double rc[63][32], rs[63][32];  // the rotations of one inner sweep, applied to Q after it
 };
 
 // Rows whose squared norm is at or below row_floor2 = (0.1 eps C)^2 |A|_F^2 are at the
@@ -228,10 +230,11 @@ struct EigLds {
 // After the QR start such rows do settle under the relative test, but only after many
 // more sweeps (a numerically low-rank matrix can need twice as many), so the floor is
 // used there only when the factor built from the rows leaves scaled by the singular
-// values (rows_scaled): then nothing needs their directions.
+// values (rows_scaled): then nothing needs their directions.  An input that carries
+// noise of noise_rel |A|_F (rows_scaled only) raises the floor to that level.
 __device__ inline double row_floor2(const SvdMat &a, double fro2) {
   if (a.precond && !a.rows_scaled) return 0.0;
-  const double f = 0.1 * EPS53 * (double)a.C;
+  const double f = fmax(0.1 * EPS53 * (double)a.C, a.rows_scaled ? a.noise_rel : 0.0);
   return f * f * fro2;
 }
 
@@ -252,6 +255,32 @@ __device__ inline bool eig_needs_rotation(EigLds &L, double tol, double floor2) 
   if (__any(loc) && (tid & 63) == 0) atomicOr(&L.need, 1);
   __syncthreads();
   return L.need != 0;
+}
+
+// Q <- Q J_1 ... J_nr for the rotations logged over one inner sweep: each wave holds 64 / waves rows
+// of Q in registers, lane l column l; a rotation on columns (i, j) takes Q[k][i] <- c Q[k][i] - s Q[k][j]
+// and Q[k][j] <- s Q[k][i] + c Q[k][j], the partner's value arriving by a lane shuffle.
+template <int NTE>
+__device__ inline void eig_apply_log(EigLds &L, int nr) {
+  constexpr int RPW = 64 / (NTE / 64);  // rows per wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double q[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) q[r] = L.Q[wave * RPW + r][lane];
+  for (int rr = 0; rr < nr; ++rr) {
+    const unsigned pc = L.pcol[rr][lane];
+    const int partner = pc & 63, t = (pc >> 6) & 31;
+    const bool first = (pc >> 11) & 1;
+    const double c = L.rc[rr][t], sn = partner == lane ? 0.0 : L.rs[rr][t];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const double pv = __shfl(q[r], partner, 64);
+      if (sn != 0.0) q[r] = first ? c * q[r] - sn * pv : sn * pv + c * q[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) L.Q[wave * RPW + r][lane] = q[r];
+  __syncthreads();
 }
 
 // Q <- Q J over sweeps of a round-robin ordering of the nv valid slots (np of block p at
@@ -276,6 +305,18 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
     if (j < 0) j = i;
     L.sched[rr][t] = (unsigned short)((i < j ? i : j) | ((i < j ? j : i) << 8));
   }
+  // column view of the same table (columns outside the valid slots are their own partner)
+  for (int e = tid; e < (nvp - 1) * 64; e += NTE) L.pcol[e >> 6][e & 63] = (unsigned short)(e & 63);
+  __syncthreads();
+  for (int e = tid; e < (nvp - 1) * P; e += NTE) {
+    const int rr = e / P, t = e - rr * P;
+    const unsigned pr = L.sched[rr][t];
+    const int i = pr & 0xff, j = pr >> 8;
+    if (i != j) {
+      L.pcol[rr][i] = (unsigned short)(j | (t << 6) | (1 << 11));
+      L.pcol[rr][j] = (unsigned short)(i | (t << 6));
+    }
+  }
   const double tol_in = 4.0 * EPS53;
   for (int sweep = 0; sweep < inner_max; ++sweep) {
     __syncthreads();  // every thread has read rot_any of the previous sweep (and the table is set)
@@ -296,6 +337,7 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
           }
         }
         L.cs[tid] = c; L.sn[tid] = s; L.pi[tid] = i; L.pj[tid] = j;
+        L.rc[rr][tid] = c; L.rs[rr][tid] = s;
       }
       __syncthreads();
       // G <- J^T G J one 2 x 2 block (pair t rows, pair u columns) at a time, t <= u, and
@@ -331,27 +373,9 @@ __device__ inline void eig_inner(EigLds &L, int inner_max, double floor2, int np
           L.G[b0][a0] = z00; L.G[b1][a0] = z01; L.G[b0][a1] = z10; L.G[b1][a1] = z11;
         }
       }
-      // Q <- Q J over the valid rows: a pair's rotation read once per thread, NTE / 32 threads
-      // per pair walking the rows
-      {
-        constexpr int TPP = NTE / 32;
-        const int u = tid / TPP, r0 = tid - u * TPP;
-        if (u < P) {
-          const double su = L.sn[u];
-          if (su != 0.0) {
-            const double cu = L.cs[u];
-            const int i = L.pi[u], j = L.pj[u];
-            for (int kk = r0; kk < nv; kk += TPP) {
-              const int k = L.vs[kk];
-              const double qi_ = L.Q[k][i], qj_ = L.Q[k][j];
-              L.Q[k][i] = cu * qi_ - su * qj_;
-              L.Q[k][j] = su * qi_ + cu * qj_;
-            }
-          }
-        }
-      }
       __syncthreads();
     }
+    eig_apply_log<NTE>(L, nvp - 1);
     const int any = L.rot_any;
     if (!any) break;
   }
@@ -965,6 +989,21 @@ __global__ __launch_bounds__(1024) void sort_kernel(const SvdMat *mats) {
       int c = 0;
       for (int w = 0; w < 16; ++w) c += cnt_w[w];
       a.spec[24] = (double)c;
+    }
+  }
+  // spec[25]: numerical rank, the number of values above 1e-12 S_0
+  {
+    __shared__ int nr_w[16];
+    const double cut = (a.noise_rel > 0.0 ? a.noise_rel : 1e-12) * key[0];
+    int cnt = 0;
+    for (int i = threadIdx.x; i < a.R; i += 1024) cnt += key[i] > cut;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) nr_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int c = 0;
+      for (int w = 0; w < 16; ++w) c += nr_w[w];
+      a.spec[25] = (double)c;
     }
   }
   // spec[6]: smallest k >= 1 with sqrt(sum_{j>=k} S_j^2) <= eps_target (k = R always qualifies)
