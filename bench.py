@@ -88,6 +88,7 @@ def copy_probe():
 # is unchanged since the counters were taken (sha256 recorded next to the figure)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 KERNEL_SOURCE = {"lz.small": "paper_2604_03960_amd/csrc/batch.hip", "svd.fused": "paper_2604_03960_amd/csrc/svd.hip",
+                 "heff.f64": "paper_2604_03960_amd/csrc/gemm.hip", "heff.f32": "paper_2604_03960_amd/csrc/gemm.hip",
                  "svd.apply": "paper_2604_03960_amd/csrc/svd.hip", "svd.eigen": "paper_2604_03960_amd/csrc/svd.hip"}
 
 
@@ -516,6 +517,7 @@ def run_chi2048(a):
     dominant = a.roofline_kernel or (max(fams, key=fams.get) if fams else "")
     if dominant:
         ctx.set_timing(True, dominant)
+    st0 = dm.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = []
@@ -528,6 +530,8 @@ def run_chi2048(a):
     t1 = time.perf_counter()
     stats = ctx.kernel_stats(reset=True) if dominant else []
     ctx.set_timing(False)
+    st1 = dm.stats()
+    svd_rows_swept = (st1["svd_rows_swept"] - st0["svd_rows_swept"]) / a.steps
     step_s = (t1 - t0) / a.steps
     roof = roofline_from(stats, dominant) if dominant else None
     # H_eff at the run's own environments (stand-alone entry point, FP64 and FP32) for the oracle check
@@ -627,6 +631,7 @@ def run_chi2048(a):
                    "derivation": "sweeps/s = 1 / (edge visits of the N=24 warm-up sweep + 154 x step time)"},
         "centre_visits_per_s": 1.0 / step_s, "edge_visits_s": edge_s, "kept_rank": ks[:4],
         "phase_ms_per_step": phase, "svd_jacobi_sweeps_per_step": svd_sweeps[:4],
+        "svd_rows_swept_per_step": svd_rows_swept,
         "E_per_site_warmup_sweep_N24": E_sweep64 / Nv,
         "roofline": roof, "svd_chi2048": svd, "g1_f32_heff": g1, "pid_N100": pid100,
         "heff_chi2048_vs_oracle": cpu.get("heff_chi2048_sampled"),

@@ -292,6 +292,9 @@ struct tna_batch_stats_s {
   long small_launches;   /* launches of the single-workgroup Lanczos path (short theta) */
   long heff_f32_iters;   /* Lanczos iterations the FP32 H_eff kernels executed (counted per launch on the
                             device side, so at least lanczos_iters under heff_prec F32; 0 under F64) */
+  long svd_rows, svd_rows_swept; /* rows (min(m, n)) of the visits' SVDs, and the rows their Jacobi sweeps
+                            worked on: fewer where a QR start stopped because every later row was at the
+                            rounding level (those rows are never rotated) */
   int autotune_entries, steps;
 };
 tna_status tna_dmrg_batch_create(tna_ctx ctx, int nchains, const int *N, int d, int D, const double *const *W_host,

@@ -17,7 +17,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRCS = [_SRC, os.path.join(_HERE, "circuit.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# A checking build of the same sources (extra compiler flags, a library name of its own) is
+# selected through the environment: TNA_ORACLE_EXTRA_CFLAGS and TNA_ORACLE_LIB_SUFFIX.
+_EXTRA = os.environ.get("TNA_ORACLE_EXTRA_CFLAGS", "").split()
+_LIB = os.path.join(_HERE, "liboracle%s.so" % os.environ.get("TNA_ORACLE_LIB_SUFFIX", ""))
 
 CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", "-fno-fast-math"]
 
@@ -31,9 +34,10 @@ MODEL_XXZ, MODEL_J1J2, MODEL_TFIM = 0, 1, 2
 
 def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
+    if force or _EXTRA or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, *_EXTRA, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -218,6 +218,7 @@ struct tna_engine_s {
   long small_launches = 0;
   long graph_launches = 0, lanczos_iters = 0;
   long heff_f32_iters = 0;  // Lanczos iterations whose H_eff ran on FP32 operands
+  long svd_rows = 0, svd_rows_swept = 0;
   double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
 };
 
@@ -278,6 +279,8 @@ void engine_stats(tna_engine e, tna_batch_stats *st) {
   st->graph_launches = e->graph_launches;
   st->small_launches = e->small_launches;
   st->heff_f32_iters = e->heff_f32_iters;
+  st->svd_rows = e->svd_rows;
+  st->svd_rows_swept = e->svd_rows_swept;
   st->autotune_entries = (int)g_tune.table.size();
 }
 
@@ -792,11 +795,6 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     // with the FP32 operator theta carries noise of about 1e-7 of its norm: rows below it are
     // rounding-level rows for the Jacobi, and the numerical rank is counted above it
     if (f32) mats[q].noise_rel = 1e-7;
-    // a numerically low-rank theta (at most a quarter of its values above 1e-12 sigma_0 at the bond's
-    // previous visit) skips the QR start: with the rounding-level rows left unrotated the Jacobi settles
-    // in as few sweeps without it, and the panel factorisation is the dearer part
-    const int nr = ch[q]->nrank[vs[q].b];
-    if (mats[q].rows_scaled && mats[q].precond && nr > 0 && 4 * nr <= mats[q].R) mats[q].precond = 0;
     nd += svd_work_doubles(mats[q]);
     ni += svd_work_ints(mats[q]);
     ns += mats[q].R;
@@ -826,6 +824,10 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
   std::vector<int> sweeps;
   tna_status sst = svd_group_run(mats, en->svd, ch[0]->opts.svd_max_sweeps, sweeps, s, true);
   if (sst != TNA_OK && sst != TNA_ERR_NOCONV) return sst;
+  for (auto &a : mats) {
+    en->svd_rows += a.R;
+    en->svd_rows_swept += a.Ra;
+  }
   if (sst == TNA_ERR_NOCONV && *worst == TNA_OK) *worst = TNA_ERR_NOCONV;
   TNA_HIP(hipMemcpyAsync(en->h_dbl, en->spec.ptr, sizeof(double) * SPEC * nc, hipMemcpyDeviceToHost, s));
   TNA_HIP(hipStreamSynchronize(s));
@@ -849,7 +851,6 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     const Visit &v = vs[q];
     const double *h = en->h_dbl + SPEC * q;
     const double Sent = h[1];
-    dm->nrank[v.b] = (int)h[25];
     kneed[q] = (int)h[6];
     // rank rule: Algorithm 2 (PID, also run and logged under the threshold rule) or Algorithm 1
     if (dm->opts.chi_rule == TNA_CHI_ENTROPY)

@@ -120,7 +120,6 @@ tna_status tna_dmrg_create(tna_ctx c, int N, int d, int D, const double *W_host,
   dm->hist.assign(N - 1, std::array<double, 8>{});
   dm->nhist.assign(N - 1, 0);
   dm->pred.assign(N - 1, 0);
-  dm->nrank.assign(N - 1, 0);
   // MPO and mixing matrices
   const size_t wsz = (size_t)D * D * d * d;
   TNA_TRY(dm->W.ensure(sizeof(double) * wsz * N));

@@ -168,8 +168,10 @@ struct SvdMat {
                                                // S_0..S_15, [24] values above thr, [25] values above 1e-12 S_0
   int *skip, *perm, *ctr;                      // work
   void *U, *Vt;                                // m x k, k x n (out_type)
-  double *fro2;                                // work: |A|_F^2 (device scalar)
-  int precond, pad2_;                          // 1: rows start from the R factor of a Householder QR
+  double *fro2;                                // work: [0] |A|_F^2, [1] largest squared row norm below a QR stop
+  int precond;                                 // 1: rows start from the R factor of a Householder QR
+  int Ra;  // rows [0, Ra) take part in the sweeps: R, or the point where a QR start stopped because every later
+           // row was at the rounding level (rows_scaled only; such rows are never rotated)
   int *cperm, *pinv;                           // work: original column at position c, and its inverse (C each)
   double *qv, *qws;                            // work: reflectors as rows (R x R), blocked-product scratch
   double noise_rel;  // > 0: the input carries noise of about noise_rel |A|_F (an FP32 operator upstream); rows
@@ -185,7 +187,8 @@ struct SvdGroup {
   void *host = nullptr;
   size_t host_cap = 0;
   int *host_ctr = nullptr;
-  double *host_fro = nullptr;  // pinned: squared Frobenius norms of the inputs (finiteness check)
+  double *host_fro = nullptr;  // pinned: squared Frobenius norms of the inputs (finiteness check), then
+                               // (|A|_F^2, largest trailing row norm^2) pairs during a QR start
   void release();
 };
 // orient (square matrices only): 0 by shape (rows of A), 1 rows of A, 2 rows of A^T (columns of A)
@@ -195,6 +198,8 @@ size_t svd_work_ints(const SvdMat &a);
 void svd_bind_work(SvdMat *a, double *dw, int *iw);
 // Loads every A, runs Jacobi sweeps until a matrix's sweep rotates nothing
 // (one host read per sweep), then sorts and writes S, spec[0,1,6,7,8..23].
+// A rows_scaled matrix whose QR start stops early leaves with Ra < R and nb, ksplit
+// re-planned for its Ra rows (plan every call afresh).
 // Returns TNA_ERR_NOCONV if any matrix hit max_sweeps.  With defer_fused, the
 // matrices on the single-workgroup Jacobi paths are not read back here: their
 // sweep counts (negative when not converged) are in spec[7].
@@ -326,7 +331,6 @@ struct tna_dmrg_s {
   tna_mlp sched = nullptr;
   std::vector<std::array<double, 8>> hist;  // last EMA entropies per bond (oldest first)
   std::vector<int> nhist, pred;             // history length, pending proposal (0 = none)
-  std::vector<int> nrank;                   // per bond: values above 1e-12 sigma_0 at its last visit (0 = none yet)
   tna::tna_engine engine = nullptr;          // the step engine this chain's sweeps run on
   int CL(int i) const { return i == 0 ? 1 : chi[i - 1]; }
   int CR(int i) const { return i == N - 1 ? 1 : chi[i]; }

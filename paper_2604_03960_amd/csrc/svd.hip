@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const SvdMat *mats, int step)
   if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2 || ks >= a.ksplit) return;
   int p, q;
   rr_pair(a.nb, step, pair, p, q);
-  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
+  const int np = block_rows(a.Ra, p), nq = block_rows(a.Ra, q);
   int64_t chunk = (a.C + a.ksplit - 1) / a.ksplit;
   chunk = (chunk + GBK - 1) / GBK * GBK;
   const int64_t kb = chunk * ks;
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(EIG_NT) void eigen_kernel(const SvdMat *mats, int s
   const int tid = threadIdx.x;
   int p, q;
   rr_pair(a.nb, step, pair, p, q);
-  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
+  const int np = block_rows(a.Ra, p), nq = block_rows(a.Ra, q);
   int *skip = a.skip + pair;
   if (np + nq == 0) {
     if (tid == 0) *skip = 1;
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const SvdMat *mats, int step
   if (a.skip[pair]) return;
   int p, q;
   rr_pair(a.nb, step, pair, p, q);
-  const int np = block_rows(a.R, p), nq = block_rows(a.R, q);
+  const int np = block_rows(a.Ra, p), nq = block_rows(a.Ra, q);
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
   auto grow = [&](int r) { return r < 32 ? p * BS + r : q * BS + (r - 32); };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -775,12 +775,95 @@ __global__ void zero_ctr_kernel(const SvdMat *mats, int nmat) {
 // lower the sweep count; cperm / pinv keep the (identity) column order explicit.
 constexpr int QR_MIN_ROWS_DEV = 256;
 
-// grid (column blocks, 1, matrices): the identity column order (no pivoting is used)
+// grid (column blocks, 1, matrices): the identity column order
 __global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
   const SvdMat &a = mats[blockIdx.z];
   if (!a.active || !a.precond) return;
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j < a.C) a.cperm[j] = j;
+}
+
+// A rows_scaled matrix whose QR start may stop early takes its columns in order of decreasing
+// norm (ties: lower index first), decided once before the factorisation: the panels then meet
+// the heavy columns first, so the rows below the factored panels fall to the rounding level at
+// about the numerical rank whatever the input's column order (a two-site matrix is ordered
+// physical index first, so half of its columns by weight sit at the end).
+__device__ inline bool qr_sorts_columns(const SvdMat &a) { return a.active && a.precond && a.rows_scaled; }
+
+// grid (column blocks, 1, matrices): squared column norms of B into qws[2048 ..) (free until the QR)
+__global__ __launch_bounds__(256) void colnorm_kernel(const SvdMat *mats) {
+  const SvdMat &a = mats[blockIdx.z];
+  if (!qr_sorts_columns(a)) return;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= a.C) return;
+  double ss = 0.0;
+  for (int r = 0; r < a.R; ++r) {
+    const double v = a.bw[(int64_t)r * a.C + c];
+    ss += v * v;
+  }
+  a.qws[2048 + c] = ss;
+}
+
+// one block per matrix: cperm <- columns by decreasing norm (bitonic sort of (norm, index))
+__global__ __launch_bounds__(1024) void colsort_kernel(const SvdMat *mats) {
+  __shared__ double key[4096];
+  __shared__ int idx[4096];
+  const SvdMat &a = mats[blockIdx.x];
+  if (!qr_sorts_columns(a)) return;
+  int P = 1;
+  while (P < a.C) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += 1024) {
+    key[i] = i < a.C ? a.qws[2048 + i] : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += 1024) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool i_before_l = key[i] > key[l] || (key[i] == key[l] && idx[i] < idx[l]);
+          if ((i & k) == 0 ? !i_before_l : i_before_l) {
+            const double tk = key[i]; key[i] = key[l]; key[l] = tk;
+            const int ti = idx[i]; idx[i] = idx[l]; idx[l] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < a.C; i += 1024) a.cperm[i] = idx[i];
+}
+
+// grid (tiles, 1, matrices): B[r][c] <- row r of A (A^T when trans) at column cperm[c], read again
+// from the input (the natural-order load served the norms)
+__global__ __launch_bounds__(256) void permute_load_kernel(const SvdMat *mats) {
+  __shared__ double tile[32][33];
+  const SvdMat &a = mats[blockIdx.z];
+  if (!qr_sorts_columns(a)) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int ntc = (a.C + 31) / 32, ntr = (a.R + 31) / 32;
+  const int t = blockIdx.x;
+  if (t >= ntr * ntc) return;
+  const int r0 = (t / ntc) * 32, c0 = (t % ntc) * 32;
+  auto in = [&](int64_t e) {
+    return a.dtype == TNA_F64 ? static_cast<const double *>(a.A)[e] : (double)static_cast<const float *>(a.A)[e];
+  };
+  if (!a.trans) {  // B row r = A row r (length n = C): gather along the row
+    for (int rr = ty; rr < 32; rr += 8) {
+      const int r = r0 + rr, c = c0 + tx;
+      if (r < a.R && c < a.C) a.bw[(int64_t)r * a.C + c] = in((int64_t)r * a.n + a.cperm[c]);
+    }
+  } else {  // B row r = A column r; B column c = A row cperm[c]: read A rows along r, write through LDS
+    for (int cc = ty; cc < 32; cc += 8) {
+      const int c = c0 + cc, r = r0 + tx;
+      tile[cc][tx] = (c < a.C && r < a.R) ? in((int64_t)a.cperm[c] * a.n + r) : 0.0;
+    }
+    __syncthreads();
+    for (int rr = ty; rr < 32; rr += 8) {
+      const int r = r0 + rr, c = c0 + tx;
+      if (r < a.R && c < a.C) a.bw[(int64_t)r * a.C + c] = tile[tx][rr];
+    }
+  }
 }
 
 // grid (matrices), 1024 threads: Householder QR of the panel of columns k0 .. k0+31 of B
@@ -797,8 +880,9 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(const SvdMat *mats, int
   __shared__ double part[QP_RG][33];
   __shared__ double s_x0, s_nrm;
   const SvdMat &a = mats[blockIdx.x];
-  if (!a.active || !a.precond || k0 >= a.R) return;
+  if (!a.active || !a.precond || k0 >= a.Ra) return;
   const int R = a.R, C = a.C, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) a.fro2[1] = 0.0;  // the trailing-row maximum of this panel (qr_tail_kernel)
   const int kend = k0 + 32 < R ? k0 + 32 : R;
   const int cend = k0 + 32 < C ? k0 + 32 : C;
   double *B = a.bw;
@@ -875,7 +959,7 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(const SvdMat *mats, int
 // One workgroup per matrix; S at qws[0..1024), T at qws[1024..2048), 32 x 32 row-major.
 __global__ __launch_bounds__(64) void qr_tfactor_kernel(const SvdMat *mats, int k0) {
   const SvdMat &a = mats[blockIdx.x];
-  if (!a.active || !a.precond || k0 >= a.R) return;
+  if (!a.active || !a.precond || k0 >= a.Ra) return;
   const int nb = a.R - k0 < 32 ? a.R - k0 : 32;
   const double *S = a.qws;
   double *T = a.qws + 1024;
@@ -894,6 +978,23 @@ __global__ __launch_bounds__(64) void qr_tfactor_kernel(const SvdMat *mats, int 
     }
     __syncthreads();
   }
+}
+
+// grid (ceil((R - k1) / 4), 1, matrices): fro2[1] <- the largest squared norm of the rows k1.. of B
+// after the panels before k1 (their entries left of column k1 are zero), one wave per row.  Run
+// only while the QR start of a rows_scaled matrix is still going; the maximum is taken on the bit
+// patterns of the non-negative sums, which order like the values.
+__global__ __launch_bounds__(256) void qr_tail_kernel(const SvdMat *mats, int k1) {
+  const SvdMat &a = mats[blockIdx.z];
+  if (!a.active || !a.precond || !a.rows_scaled || k1 >= a.Ra) return;
+  const int r = k1 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= a.R) return;
+  const double *row = a.bw + (int64_t)r * a.C;
+  double ss = 0.0;
+  for (int c = k1 + lane; c < a.C; c += 64) ss += row[c] * row[c];
+  ss = wave_sum_d(ss);
+  if (lane == 0)
+    atomicMax(reinterpret_cast<unsigned long long *>(a.fro2 + 1), (unsigned long long)__double_as_longlong(ss));
 }
 
 // grid (column blocks, 1, matrices)
@@ -1240,6 +1341,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a, int 
   a->trans = m > n || (m == n && orient == 2);
   a->R = m < n ? m : n;
   a->C = m < n ? n : m;
+  a->Ra = a->R;
   a->dtype = dtype;
   if (a->C > 4096) {
     set_error("svd: max(m,n) > 4096 is not supported");
@@ -1337,7 +1439,7 @@ static tna_status qr_block_apply(const std::vector<SvdMat> &mats, const SvdMat *
                                  hipStream_t s) {
   bool any = false;
   for (auto &a : mats) {
-    if (!a.precond || k0 >= a.R) continue;
+    if (!a.precond || k0 >= a.Ra) continue;
     if (on_b && k0 + 32 >= a.C) continue;
     any = true;
     const int R = a.R, nbk = std::min(32, R - k0), K = R - k0;
@@ -1349,7 +1451,7 @@ static tna_status qr_block_apply(const std::vector<SvdMat> &mats, const SvdMat *
   hipLaunchKernelGGL(qr_tfactor_kernel, dim3(nm), dim3(64), 0, s, d, k0);
   TNA_LAUNCHED("svd.qr_tfactor");
   for (auto &a : mats) {
-    if (!a.precond || k0 >= a.R) continue;
+    if (!a.precond || k0 >= a.Ra) continue;
     if (on_b && k0 + 32 >= a.C) continue;
     const int R = a.R, nbk = std::min(32, R - k0), K = R - k0;
     const double *Vb = a.qv + (int64_t)k0 * R + k0;
@@ -1395,7 +1497,7 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
   // a NaN or Inf anywhere in an input shows in its squared Frobenius norm; the callers that defer
   // their reads (the sweep engine) check the spectrum sums they read anyway
   if (!defer_fused) {
-    if (!g.host_fro) TNA_HIP(hipHostMalloc((void **)&g.host_fro, sizeof(double) * 4096, hipHostMallocDefault));
+    if (!g.host_fro) TNA_HIP(hipHostMalloc((void **)&g.host_fro, sizeof(double) * 3 * 4096, hipHostMallocDefault));
     for (int z = 0; z < nm; ++z)
       TNA_HIP(hipMemcpyAsync(g.host_fro + z, mats[z].fro2, sizeof(double), hipMemcpyDeviceToHost, s));
     TNA_HIP(hipStreamSynchronize(s));
@@ -1404,14 +1506,6 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
         set_error("svd: non-finite entry in input matrix " + std::to_string(z));
         return TNA_ERR_NONFINITE;
       }
-  }
-  double gram_flops = 0, gram_bytes = 0, apply_flops = 0, apply_bytes = 0;
-  for (auto &a : mats) {
-    const double pairs = a.nb / 2, b2 = 4096.0;
-    gram_flops += 2.0 * b2 * a.C * pairs;
-    gram_bytes += 8.0 * (double)a.R * a.C;
-    apply_flops += 2.0 * b2 * (double)(a.C + a.R) * pairs;
-    apply_bytes += 16.0 * ((double)a.R * a.C + (double)a.R * a.R);
   }
   // QR start for the larger matrices
   int qr_rows = 0, qr_cblk = 0;
@@ -1422,16 +1516,71 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     }
   if (qr_rows > 0) {
     hipLaunchKernelGGL(qr_init_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
+    int sorted = 0, ptiles = 0;
+    for (auto &a : mats)
+      if (a.precond && a.rows_scaled) {
+        ++sorted;
+        ptiles = std::max(ptiles, ceil_div(a.R, 32) * ceil_div(a.C, 32));
+      }
+    if (sorted > 0) {
+      hipLaunchKernelGGL(colnorm_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(colsort_kernel, dim3(nm), dim3(1024), 0, s, d);
+      hipLaunchKernelGGL(permute_load_kernel, dim3(ptiles, 1, nm), dim3(256), 0, s, d);
+      TNA_LAUNCHED("svd.qr_order");
+    }
     double qr_bytes = 0.0;
     for (auto &a : mats)
       if (a.precond) qr_bytes += 16.0 * ((double)a.R * a.C / 3.0 + (double)a.R * a.R / 2.0);
     // Blocked Householder QR (no column pivoting: the start it gives converges as fast on
     // these matrices, and the trailing update becomes GEMMs): each 32-column panel is
     // factored column by column, then B[k0:, k0+32:] <- (I - V T^T V^T) B[k0:, k0+32:].
+    // A rows_scaled matrix stops its QR start once every row below the factored panels is at the
+    // rounding level (row_floor2): such rows are never rotated, so the sweeps run on the rows
+    // above (Ra), and a numerically low-rank matrix pays for the panels of its rank only.
+    std::vector<int> watch(nm, 0);
+    int nwatch = 0;
+    for (int z = 0; z < nm; ++z)
+      if (mats[z].precond && mats[z].rows_scaled) {
+        watch[z] = 1;
+        ++nwatch;
+      }
+    if (nwatch > 0 && !g.host_fro)
+      TNA_HIP(hipHostMalloc((void **)&g.host_fro, sizeof(double) * 3 * 4096, hipHostMallocDefault));
     timer_begin("svd.qr", s);
     for (int k0 = 0; k0 < qr_rows; k0 += 32) {
       hipLaunchKernelGGL(qr_panel_kernel, dim3(nm), dim3(QP_NT), 0, s, d, k0);
       TNA_TRY(qr_block_apply(mats, d, nm, k0, true, s));
+      const int k1 = k0 + 32;
+      int tail = 0;
+      for (int z = 0; z < nm; ++z)
+        if (watch[z] && k1 < mats[z].R) tail = std::max(tail, mats[z].R - k1);
+      if (tail == 0) continue;
+      hipLaunchKernelGGL(qr_tail_kernel, dim3(ceil_div(tail, 4), 1, nm), dim3(256), 0, s, d, k1);
+      for (int z = 0; z < nm; ++z)
+        if (watch[z])
+          TNA_HIP(hipMemcpyAsync(g.host_fro + 4096 + 2 * z, mats[z].fro2, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                 s));
+      TNA_HIP(hipStreamSynchronize(s));
+      bool stopped = false;
+      for (int z = 0; z < nm; ++z) {
+        if (!watch[z]) continue;
+        SvdMat &a = mats[z];
+        const double f = std::fmax(0.1 * EPS53 * (double)a.C, a.noise_rel);
+        const double floor2 = f * f * g.host_fro[4096 + 2 * z];
+        if (g.host_fro[4096 + 2 * z + 1] <= floor2) {
+          a.Ra = k1;
+          stopped = true;
+        }
+        if (a.Ra < a.R || k1 + 32 >= a.R) {
+          watch[z] = 0;
+          --nwatch;
+        }
+      }
+      if (stopped) TNA_TRY(upload(mats, g, s));
+      if (nwatch == 0 && std::all_of(mats.begin(), mats.end(), [&](const SvdMat &a) {
+            return !a.precond || a.Ra < a.R || k1 >= a.R;
+          }))
+        break;
     }
     timer_end("svd.qr", 0.0, qr_bytes, s);
     hipLaunchKernelGGL(qr_pinv_kernel, dim3(qr_cblk, 1, nm), dim3(256), 0, s, d);
@@ -1440,6 +1589,34 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
     for (int k0 = 0; k0 < qr_rows; k0 += 32) TNA_TRY(qr_block_apply(mats, d, nm, k0, false, s));
     timer_end("svd.qr_form", 0.0, 0.0, s);
     TNA_LAUNCHED("svd.qr");
+    // the sweeps of a stopped matrix pair blocks of its Ra rows; the Gram partial sums keep
+    // within the slots planned for all R rows
+    bool replan = false;
+    for (auto &a : mats) {
+      if (!a.precond || a.Ra >= a.R) continue;
+      const int slots = (a.nb / 2) * a.ksplit;
+      int nb = ceil_div(a.Ra, BS);
+      if (nb < 2) nb = 2;
+      if (nb & 1) ++nb;
+      a.nb = nb;
+      int ks = ceil_div(1024, (int64_t)(nb / 2) * nm);
+      ks = std::min(ks, ceil_div(a.C, 256));
+      ks = std::min(ks, slots / (nb / 2));
+      a.ksplit = std::max(ks, 1);
+      replan = true;
+    }
+    if (replan) TNA_TRY(upload(mats, g, s));
+  }
+  max_pairs = max_ks = 0;
+  double gram_flops = 0, gram_bytes = 0, apply_flops = 0, apply_bytes = 0;
+  for (auto &a : mats) {
+    max_pairs = std::max(max_pairs, a.nb / 2);
+    max_ks = std::max(max_ks, a.ksplit);
+    const double pairs = a.nb / 2, b2 = 4096.0;
+    gram_flops += 2.0 * b2 * a.C * pairs;
+    gram_bytes += 8.0 * (double)a.Ra * a.C;
+    apply_flops += 2.0 * b2 * (double)(a.C + a.R) * pairs;
+    apply_bytes += 16.0 * ((double)a.Ra * a.C + (double)a.Ra * a.R);
   }
   // one block pair: every sweep inside one workgroup, no host round trip per sweep
   int nfused = 0, n_two = 0, n_tiny = 0;

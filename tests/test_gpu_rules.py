@@ -76,6 +76,31 @@ def test_tfim_matches_oracle_and_free_fermions(h):
     assert abs(Es[-1] - tfim_free_fermion_energy(16, 1.0, h)) <= 1e-9 * abs(Es[-1])
 
 
+def test_tfim_paramagnet_low_rank_centre_chi128():
+    # h = 4, N = 16, chi fixed at 128 from a random MPS of that bond dimension: the centre two-site
+    # matrices are 256 x 256 (QR-started SVD) and, once the environments are good, numerically of low
+    # rank, so the QR start stops early and the Jacobi sweeps work on the rows above the rounding level
+    # only.  Oracle parity visit by visit, the free-fermion energy, and the stopped QR starts on record.
+    import paper_2604_03960_amd as tna
+    N, chi, h = 16, 128, 4.0
+    W = oracle.mpo(2, N, [1.0, h])
+    A, chis, _ = synth.random_mps(N, 2, chi, 0)
+    pp = (0.5, 0.05, 0.1, 0.5, 0.3, chi, chi)
+    ro = oracle.dmrg_run(W, A, chis, oracle.pid_params(*pp), 2, fixed_chi=chi)
+    dm = tna.Dmrg(ctx(), W, A, chis, tna.pid_params(*pp), fixed_chi=chi)
+    logs, Es = [], []
+    for _ in range(2):
+        E, recs, _st = dm.sweep()
+        Es.append(E)
+        logs += recs
+    st = dm.stats()
+    dm.close()
+    _compare(ro, np.array(Es), logs, 1e-10)
+    assert abs(Es[-1] - tfim_free_fermion_energy(N, 1.0, h)) <= 1e-9 * abs(Es[-1])
+    print("svd rows", st["svd_rows"], "swept", st["svd_rows_swept"])
+    assert st["svd_rows_swept"] < st["svd_rows"]
+
+
 def test_tfim_ordered_phase_energy():
     # h = 0.6 < J: the two lowest states are split by ~ (h/J)^N, so the Lanczos vector may carry a
     # different tiny admixture of the partner state than the oracle's (entropies then differ at the
