@@ -57,6 +57,18 @@ __global__ __launch_bounds__(NT) void mix_grouped_kernel(const MixProb *probs, i
 }
 
 // ------------------------------------------------------------------ Lanczos
+// Block b of a chain's G covers elements [beg, end) of the length-n vectors.  For even n (rows
+// 16-byte aligned) the chunks are whole groups of four elements and every thread keeps two
+// 16-byte loads per vector in flight, which the streaming passes need to approach the HBM
+// rate; odd n takes one element per thread and step.
+__device__ inline void lz_range(const LzProb &p, bool vec, int64_t &beg, int64_t &end) {
+  int64_t chunk = (p.n + p.G - 1) / p.G;
+  if (vec) chunk = (chunk + 3) & ~(int64_t)3;
+  beg = chunk * blockIdx.x;
+  if (beg > p.n) beg = p.n;
+  end = beg + chunk < p.n ? beg + chunk : p.n;
+}
+
 // h[i] partials of <V_i, w> for i <= j, w = V_{j+1}; grid (G, chains)
 __global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int which) {
   __shared__ double sh[4];
@@ -64,16 +76,33 @@ __global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int whi
   if (!*p.active || (int)blockIdx.x >= p.G) return;
   const int nv = *p.j + 1;
   const double *V = p.V, *w = p.V + (int64_t)nv * p.n;
-  const int64_t chunk = (p.n + p.G - 1) / p.G;
-  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  const bool vec = (p.n & 1) == 0;
+  int64_t beg, end;
+  lz_range(p, vec, beg, end);
   double *part = which ? p.part2 : p.part1;
   for (int i0 = 0; i0 < nv; i0 += 8) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
-      const double wv = w[e];
+    if (vec) {
+      for (int64_t e = beg + 4 * threadIdx.x; e < end; e += 4 * NT) {
+        const bool two = e + 2 < end;
+        const double2 w0 = *reinterpret_cast<const double2 *>(w + e);
+        const double2 w1 = two ? *reinterpret_cast<const double2 *>(w + e + 2) : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int g = 0; g < 8; ++g)
-        if (i0 + g < nv) acc[g] += V[(int64_t)(i0 + g) * p.n + e] * wv;
+        for (int g = 0; g < 8; ++g)
+          if (i0 + g < nv) {
+            const double *vr = V + (int64_t)(i0 + g) * p.n + e;
+            const double2 a0 = *reinterpret_cast<const double2 *>(vr);
+            const double2 a1 = two ? *reinterpret_cast<const double2 *>(vr + 2) : make_double2(0.0, 0.0);
+            acc[g] += (a0.x * w0.x + a0.y * w0.y) + (a1.x * w1.x + a1.y * w1.y);
+          }
+      }
+    } else {
+      for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+        const double wv = w[e];
+#pragma unroll
+        for (int g = 0; g < 8; ++g)
+          if (i0 + g < nv) acc[g] += V[(int64_t)(i0 + g) * p.n + e] * wv;
+      }
     }
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
@@ -106,15 +135,43 @@ __global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int wh
   const int nv = *p.j + 1;
   const double *h = which ? p.h2 : p.h1;
   double *w = p.V + (int64_t)nv * p.n;
-  const int64_t chunk = (p.n + p.G - 1) / p.G;
-  const int64_t beg = chunk * blockIdx.x, end = beg + chunk < p.n ? beg + chunk : p.n;
+  const bool vec = (p.n & 1) == 0;
+  int64_t beg, end;
+  lz_range(p, vec, beg, end);
   double loc = 0.0;
-  for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
-    double acc = 0.0;
-    for (int i = 0; i < nv; ++i) acc += h[i] * p.V[(int64_t)i * p.n + e];
-    const double v = w[e] - acc;
-    w[e] = v;
-    loc += v * v;
+  if (vec) {
+    for (int64_t e = beg + 4 * threadIdx.x; e < end; e += 4 * NT) {
+      const bool two = e + 2 < end;
+      double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+      for (int i = 0; i < nv; ++i) {
+        const double hi = h[i];
+        const double *vr = p.V + (int64_t)i * p.n + e;
+        const double2 a0 = *reinterpret_cast<const double2 *>(vr);
+        const double2 a1 = two ? *reinterpret_cast<const double2 *>(vr + 2) : make_double2(0.0, 0.0);
+        s0x += hi * a0.x;
+        s0y += hi * a0.y;
+        s1x += hi * a1.x;
+        s1y += hi * a1.y;
+      }
+      const double2 w0 = *reinterpret_cast<const double2 *>(w + e);
+      const double2 v0 = make_double2(w0.x - s0x, w0.y - s0y);
+      *reinterpret_cast<double2 *>(w + e) = v0;
+      loc += v0.x * v0.x + v0.y * v0.y;
+      if (two) {
+        const double2 w1 = *reinterpret_cast<const double2 *>(w + e + 2);
+        const double2 v1 = make_double2(w1.x - s1x, w1.y - s1y);
+        *reinterpret_cast<double2 *>(w + e + 2) = v1;
+        loc += v1.x * v1.x + v1.y * v1.y;
+      }
+    }
+  } else {
+    for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+      double acc = 0.0;
+      for (int i = 0; i < nv; ++i) acc += h[i] * p.V[(int64_t)i * p.n + e];
+      const double v = w[e] - acc;
+      w[e] = v;
+      loc += v * v;
+    }
   }
   if (with_norm) {
     const double r = block_sum(loc, sh);

@@ -1,11 +1,13 @@
 // Dense contractions of the two-site DMRG step on the gfx950 matrix cores.
 //
 // One kernel template serves every GEMM of the path: H_eff stages S1 (L x theta)
-// and S4 (Z x R^T), the environment updates, theta formation.  A 256-thread
-// workgroup (four wave64s in a 2 x 2 arrangement) owns a BM x BN tile of C;
-// K advances in steps of 16 through two LDS buffers (the next slab is
-// fetched into registers while the current one feeds the MFMAs).  Each
-// wave accumulates (BM/2) x (BN/2) as 16 x 16 MFMA tiles:
+// and S4 (Z x R^T), the environment updates, theta formation.  A workgroup owns
+// a BM x BN tile of C: 64 x 64 with 256 threads (four wave64s in a 2 x 2
+// arrangement), or 128 x 128 with 512 threads (eight wave64s, 4 x 2; half the
+// operand traffic per flop of the small tile at the same registers per wave, and
+// two workgroups per compute unit).  K advances in steps of 16 through two LDS
+// buffers (the next slab is fetched into registers while the current one feeds
+// the MFMAs).  Each wave accumulates its share of the tile as 16 x 16 MFMA tiles:
 //   FP64: v_mfma_f64_16x16x4_f64, FP32: v_mfma_f32_16x16x4_f32.
 // Operand layout of the 16x16x4 MFMAs (lane l, result register r = 0..3):
 //   A[i][k]: lane i + 16k      B[k][j]: lane j + 16k
@@ -50,28 +52,37 @@ template <typename T, int BM, int BN> struct TileLds {
   T Bs[2][BK][BN + 1];
 };
 
+// threads of the workgroup that owns a BM x BN tile, and its waves along M
+template <int BM> struct TileShape;
+// (MINW: waves per SIMD the register allocation must leave room for; two 128 x 128
+// workgroups per compute unit need four)
+template <> struct TileShape<64> { static constexpr int NT = 256, WR = 2, MINW = 4; };
+template <> struct TileShape<128> { static constexpr int NT = 512, WR = 4, MINW = 4; };
+
 // One BM x BN tile of C = alpha op(A) op(B) + beta C at (m0, n0).
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
 __device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, int lda, const TB *__restrict__ B, int ldb,
                                           TC *__restrict__ C, int ldc, int M, int N, int K, double alpha, double beta,
                                           int m0, int n0, TileLds<T, BM, BN> &L) {
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int NT = TileShape<BM>::NT, WR = TileShape<BM>::WR, WC = NT / 64 / WR;
+  constexpr int WM = BM / WR, WN = BN / WC;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int LA = BM * BK / 256;  // A elements per thread per slab
-  constexpr int LB = BN * BK / 256;
+  constexpr int LA = BM * BK / NT;  // A elements per thread per slab
+  constexpr int LB = BN * BK / NT;
+  static_assert(BM % WR == 0 && BN % WC == 0 && WM % 16 == 0 && WN % 16 == 0 && LA >= 1 && LB >= 1, "tile shape");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int lr = lane & 15, lk = lane >> 4;
 
   // element coordinates this thread loads (tile-local)
   auto a_coord = [&](int p, int &i, int &k) {
-    if (!TRA) { k = tid % BK; i = tid / BK + (256 / BK) * p; }
-    else { i = tid % BM; k = tid / BM + (256 / BM) * p; }
+    if (!TRA) { k = tid % BK; i = tid / BK + (NT / BK) * p; }
+    else { i = tid % BM; k = tid / BM + (NT / BM) * p; }
   };
   auto b_coord = [&](int p, int &k, int &j) {
-    if (!TRB) { j = tid % BN; k = tid / BN + (256 / BN) * p; }
-    else { k = tid % BK; j = tid / BK + (256 / BK) * p; }
+    if (!TRB) { j = tid % BN; k = tid / BN + (NT / BN) * p; }
+    else { k = tid % BK; j = tid / BK + (NT / BK) * p; }
   };
 
   T ra[LA], rb[LB];
@@ -157,7 +168,7 @@ __device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, int lda, con
 }
 
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
+__global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_kernel(GemmDev g) {
   __shared__ TileLds<T, BM, BN> L;
   const int z = blockIdx.z;
   gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>(static_cast<const TA *>(g.A) + g.sA * z, g.lda,
@@ -172,8 +183,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDev g) {
 // (*jB) * jB_stride / (*jC) * jC_stride, read at run time, so a captured
 // launch serves every Lanczos iteration.
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
-__global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmProb *probs, int nprob, int total, double alpha,
-                                                           double beta) {
+__global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_grouped_kernel(
+    const GemmProb *probs, int nprob, int total, double alpha, double beta) {
   __shared__ TileLds<T, BM, BN> L;
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int lo = 0, hi = nprob - 1;
@@ -196,6 +207,7 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmProb *probs
 
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN>
 tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
+  constexpr int NT = TileShape<BM>::NT;
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
   if (grid.y > 65535 || grid.z > 65535) {
     set_error("gemm: grid too large");
@@ -208,11 +220,11 @@ tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
     timer_begin(name, s);
   }
   if (!a.transA && !a.transB)
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, false>), grid, dim3(256), 0, s, d);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, false>), grid, dim3(NT), 0, s, d);
   else if (!a.transA && a.transB)
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, true>), grid, dim3(256), 0, s, d);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, true>), grid, dim3(NT), 0, s, d);
   else if (a.transA && !a.transB)
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, true, false>), grid, dim3(256), 0, s, d);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, true, false>), grid, dim3(NT), 0, s, d);
   else {
     set_error("gemm: transA && transB not built");
     return TNA_ERR_UNSUPPORTED;
@@ -238,6 +250,7 @@ tna_status launch_types(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
 
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN>
 tna_status launch_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int total, hipStream_t s) {
+  constexpr int NT = TileShape<BM>::NT;
   int grid = total < 2048 ? total : 2048;
   if (grid < 1) return TNA_OK;
   char name[64] = "";
@@ -247,13 +260,13 @@ tna_status launch_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int 
     timer_begin(name, s);
   }
   if (!g.transA && !g.transB)
-    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, false>), dim3(grid), dim3(256), 0, s, d,
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, false>), dim3(grid), dim3(NT), 0, s, d,
                        nprob, total, g.alpha, g.beta);
   else if (!g.transA && g.transB)
-    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, true>), dim3(grid), dim3(256), 0, s, d,
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, true>), dim3(grid), dim3(NT), 0, s, d,
                        nprob, total, g.alpha, g.beta);
   else if (g.transA && !g.transB)
-    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, true, false>), dim3(grid), dim3(256), 0, s, d,
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, true, false>), dim3(grid), dim3(NT), 0, s, d,
                        nprob, total, g.alpha, g.beta);
   else {
     set_error("gemm_grouped: transA && transB not built");

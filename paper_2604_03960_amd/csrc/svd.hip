@@ -402,10 +402,170 @@ __device__ inline void eig_order(EigLds &L, int np, int nq) {
   __syncthreads();
 }
 
+// ---- the eigen step of the blocked method: a tournament on moving slots
+// The elements of the 64 x 64 Gram move between slots so that the pairs of every round are the
+// slot pairs (2t, 2t+1): each round reads its 2 x 2 blocks as contiguous 16-byte pairs, rotates,
+// and writes them to the slots of the next round in a second buffer (one barrier for the
+// rotations, one for the round).  The move is the circle method on 64 slots with slot 0 fixed:
+// every other element advances one place along 1 -> 2 -> 4 -> ... -> 62 -> 63 -> 61 -> ... -> 3
+// -> 1, which brings every pair of elements together once in 63 rounds and restores the starting
+// placement after the 63rd.  The eigenvector columns move with their elements, in registers.
+__device__ inline int tour_next(int s) {
+  if (s == 0) return 0;
+  if (s == 1) return 2;
+  if (s == 62) return 63;
+  return (s & 1) ? s - 2 : s + 2;
+}
+__device__ inline int tour_prev(int m) {
+  if (m == 0) return 0;
+  if (m == 2) return 1;
+  if (m == 63) return 62;
+  return (m & 1) ? m + 2 : m - 2;
+}
+
+struct EigTour {
+  double G[2][64][66];  // the matrix of the current round and of the next (rows 16-byte aligned)
+  double cs[32], sn[32];
+  int rot_any, need;
+  int slot_of[64];
+};
+
+// Outer test on G[0] (rows above the floor only), as eig_needs_rotation
+template <int NTE>
+__device__ inline bool tour_needs_rotation(EigTour &L, double tol, double floor2) {
+  const int tid = threadIdx.x;
+  if (tid == 0) L.need = 0;
+  __syncthreads();
+  int loc = 0;
+  for (int e = tid; e < 4096; e += NTE) {
+    const int i = e >> 6, j = e & 63;
+    if (i < j) {
+      const double gii = L.G[0][i][i], gjj = L.G[0][j][j], gij = L.G[0][i][j];
+      if (gii > floor2 && gjj > floor2 && gii > 0.0 && gjj > 0.0 && fabs(gij) > tol * sqrt(gii * gjj)) loc = 1;
+    }
+  }
+  if (__any(loc) && (tid & 63) == 0) atomicOr(&L.need, 1);
+  __syncthreads();
+  return L.need != 0;
+}
+
+// Sweeps of 63 rounds until one rotates nothing (or inner_max).  Returns the buffer holding the
+// rotated matrix (eigenvalues on its diagonal, every element back on its starting slot); the
+// eigenvector matrix Q (column s for slot s) is left in the other buffer.  Rotation and tests as
+// in eig_inner; the 2 x 2 block (t, u) and its mirror (u, t) are computed by the same operations
+// on the same values, so the matrix stays exactly symmetric.
+template <int NTE>
+__device__ inline int eig_tour(EigTour &L, int inner_max, double floor2) {
+  constexpr int RPW = 64 / (NTE / 64);  // rows of Q per wave
+  constexpr int BPT = 1024 / NTE;       // 2 x 2 blocks per thread
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double q[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) q[r] = (wave * RPW + r == lane) ? 1.0 : 0.0;
+  const double tol_in = 4.0 * EPS53;
+  const int qsrc = tour_prev(lane), qpair = lane >> 1;
+  int cur = 0;
+  for (int sweep = 0; sweep < inner_max; ++sweep) {
+    __syncthreads();  // every thread has read rot_any of the previous sweep
+    if (tid == 0) L.rot_any = 0;
+    __syncthreads();
+    for (int rr = 0; rr < 63; ++rr) {
+      double (*Gi)[66] = L.G[cur];
+      double (*Go)[66] = L.G[cur ^ 1];
+      double x[BPT][4];
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {  // Gi does not change during the round: read before the rotations
+        const int e = tid + b * NTE, t = e >> 5, u = e & 31;
+        const double2 r0 = *reinterpret_cast<const double2 *>(&Gi[2 * t][2 * u]);
+        const double2 r1 = *reinterpret_cast<const double2 *>(&Gi[2 * t + 1][2 * u]);
+        x[b][0] = r0.x;
+        x[b][1] = r0.y;
+        x[b][2] = r1.x;
+        x[b][3] = r1.y;
+      }
+      if (tid < 32) {
+        // J = [[c, s], [-s, c]] on the slots (2t, 2t+1), zeroing their coupling
+        const int t = tid;
+        const double a = Gi[2 * t][2 * t], bb = Gi[2 * t + 1][2 * t + 1], g = Gi[2 * t][2 * t + 1];
+        double c = 1.0, sn = 0.0;
+        if (a > floor2 && bb > floor2 && g * g > tol_in * tol_in * fabs(a * bb)) {
+          jacobi_rot(a, bb, g, c, sn);
+          L.rot_any = 1;
+        }
+        L.cs[t] = c;
+        L.sn[t] = sn;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        const int e = tid + b * NTE, t = e >> 5, u = e & 31;
+        const bool up = t <= u;  // Z = J_lo^T X(lo, hi) J_hi, lo = min(t, u)
+        const int lo = up ? t : u, hi = up ? u : t;
+        const double cl = L.cs[lo], sl = L.sn[lo], ch = L.cs[hi], sh = L.sn[hi];
+        const double x00 = x[b][0], x01 = up ? x[b][1] : x[b][2], x10 = up ? x[b][2] : x[b][1], x11 = x[b][3];
+        const double y00 = cl * x00 - sl * x10, y01 = cl * x01 - sl * x11;
+        const double y10 = sl * x00 + cl * x10, y11 = sl * x01 + cl * x11;
+        double z00 = ch * y00 - sh * y01, z01 = sh * y00 + ch * y01;
+        double z10 = ch * y10 - sh * y11, z11 = sh * y10 + ch * y11;
+        if (t == u && sl != 0.0) {
+          z01 = 0.0;
+          z10 = 0.0;
+        }
+        const int r0 = tour_next(2 * t), r1 = tour_next(2 * t + 1);
+        const int c0 = tour_next(2 * u), c1 = tour_next(2 * u + 1);
+        Go[r0][c0] = z00;
+        Go[r0][c1] = up ? z01 : z10;
+        Go[r1][c0] = up ? z10 : z01;
+        Go[r1][c1] = z11;
+      }
+      {  // Q <- Q J on the lane's column, then the column moves with its element
+        const double c = L.cs[qpair], sn = L.sn[qpair];
+        const bool first = (lane & 1) == 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const double pv = __shfl_xor(q[r], 1, 64);
+          const double nv = first ? c * q[r] - sn * pv : sn * pv + c * q[r];
+          q[r] = __shfl(nv, qsrc, 64);
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    const int any = L.rot_any;
+    if (!any) break;
+  }
+  double (*Qb)[66] = L.G[cur ^ 1];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) Qb[wave * RPW + r][lane] = q[r];
+  __syncthreads();
+  return cur;
+}
+
+// slot_of as eig_order, from the diagonal of G
+__device__ inline void tour_order(const double (*G)[66], int *slot_of, int np, int nq) {
+  const int r = threadIdx.x;
+  if (r < 64) {
+    const bool vr = r < 32 ? (r < np) : (r - 32 < nq);
+    if (vr) {
+      const double lr_ = G[r][r];
+      int rank = 0;
+      for (int o = 0; o < 64; ++o) {
+        const bool vo = o < 32 ? (o < np) : (o - 32 < nq);
+        if (o == r || !vo) continue;
+        const double lo = G[o][o];
+        if (lo > lr_ || (lo == lr_ && o < r)) ++rank;
+      }
+      slot_of[rank < np ? rank : 32 + (rank - np)] = r;
+    }
+  }
+  __syncthreads();
+}
+
 // grid (pairs, matrices)
 constexpr int EIG_NT = 512;
+constexpr int KS_MAX = 16;  // K splits of the Gram: at most ceil(4096 / 256)
 __global__ __launch_bounds__(EIG_NT) void eigen_kernel(const SvdMat *mats, int step) {
-  __shared__ EigLds L;
+  __shared__ EigTour L;
   const SvdMat &a = mats[blockIdx.y];
   const int pair = blockIdx.x;
   if (!a.active || a.fused || step >= a.nb - 1 || pair >= a.nb / 2) return;
@@ -419,27 +579,42 @@ __global__ __launch_bounds__(EIG_NT) void eigen_kernel(const SvdMat *mats, int s
     return;
   }
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
+  // the K-split partial Grams (at most KS_MAX), summed in split order: every partial of two
+  // elements is loaded before the first sum, so one memory latency covers the lot
   const double *Gp = a.gram + (int64_t)pair * a.ksplit * 4096;
-  for (int e = tid; e < 4096; e += EIG_NT) {
-    const int i = e >> 6, j = e & 63;
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    double v = 0.0;
-    for (int ks = 0; ks < a.ksplit; ++ks) v += Gp[(int64_t)ks * 4096 + lo * 64 + hi];
-    L.G[i][j] = (valid(i) && valid(j)) ? v : 0.0;
-    L.Q[i][j] = (i == j) ? 1.0 : 0.0;
+  const int nks = a.ksplit;
+  for (int e0 = tid; e0 < 4096; e0 += 2 * EIG_NT) {
+    double part[2][KS_MAX];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = e0 + h * EIG_NT, i = e >> 6, j = e & 63;
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+#pragma unroll
+      for (int ks = 0; ks < KS_MAX; ++ks) part[h][ks] = ks < nks ? Gp[(int64_t)ks * 4096 + lo * 64 + hi] : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = e0 + h * EIG_NT, i = e >> 6, j = e & 63;
+      double v = 0.0;
+#pragma unroll
+      for (int ks = 0; ks < KS_MAX; ++ks)
+        if (ks < nks) v += part[h][ks];
+      L.G[0][i][j] = (valid(i) && valid(j)) ? v : 0.0;
+    }
   }
   const double floor2 = row_floor2(a, *a.fro2);
-  if (!eig_needs_rotation<EIG_NT>(L, a.tol, floor2)) {
+  if (!tour_needs_rotation<EIG_NT>(L, a.tol, floor2)) {
     if (tid == 0) *skip = 1;
     return;
   }
   if (tid == 0) atomicAdd(a.ctr, 1);
-  eig_inner<EIG_NT>(L, a.inner_max, floor2, np, nq);
-  eig_order(L, np, nq);
+  const int cur = eig_tour<EIG_NT>(L, a.inner_max, floor2);
+  tour_order(L.G[cur], L.slot_of, np, nq);
+  const double(*Q)[66] = L.G[cur ^ 1];
   double *Qt = a.qt + (int64_t)pair * 4096;
   for (int e = tid; e < 4096; e += EIG_NT) {
     const int so = e >> 6, ri = e & 63;
-    Qt[e] = (valid(so) && valid(ri)) ? L.Q[ri][L.slot_of[so]] : 0.0;
+    Qt[e] = (valid(so) && valid(ri)) ? Q[ri][L.slot_of[so]] : 0.0;
   }
   if (tid == 0) *skip = 0;
 }
