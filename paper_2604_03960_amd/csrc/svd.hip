@@ -123,10 +123,12 @@ __device__ inline double bsum256(double v, double *red) {
 // -------------------------------------------------------------- gram
 // 64 x 64 Gram of the rows of blocks p and q over columns [kb, ke) on MFMA:
 // wave (qi, qj) holds the 32 x 32 quadrant (qi, qj) as 2 x 2 16 x 16 tiles.
-constexpr int GBK = 32;
-// The next 32-column slab is loaded into registers while the current one is multiplied.
+constexpr int GBK = 64;
+// The next 64-column slab (32 KB of the pair's rows) is loaded into registers while the current
+// one is multiplied.
 __device__ inline void gram_acc(const SvdMat &a, int p, int q, int np, int nq, int64_t kb, int64_t ke,
                                 double (*Ts)[65], v4d acc[2][2]) {
+  constexpr int RS = 256 / GBK, NU = 64 / RS;  // row stride of a thread's loads, rows per thread
   const double *B = a.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -135,26 +137,26 @@ __device__ inline void gram_acc(const SvdMat &a, int p, int q, int np, int nq, i
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-  // thread tid loads column tid % 32 of rows tid / 32 + 8u, u < 8
+  // thread tid loads column tid % GBK of rows tid / GBK + RS u, u < NU
   const int col = tid % GBK, r0 = tid / GBK;
-  const double *rowp[8];
+  const double *rowp[NU];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int r = r0 + 8 * u;
+  for (int u = 0; u < NU; ++u) {
+    const int r = r0 + RS * u;
     const bool valid = r < 32 ? (r < np) : (r - 32 < nq);
     const int grow = r < 32 ? p * BS + r : q * BS + (r - 32);
     rowp[u] = valid ? B + (int64_t)grow * a.C : nullptr;
   }
-  double nx[8];
+  double nx[NU];
   auto load = [&](int64_t k0) {
     const int64_t gc = k0 + col;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) nx[u] = (rowp[u] && gc < ke) ? rowp[u][gc] : 0.0;
+    for (int u = 0; u < NU; ++u) nx[u] = (rowp[u] && gc < ke) ? rowp[u][gc] : 0.0;
   };
   if (kb < ke) load(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) Ts[col][r0 + 8 * u] = nx[u];
+    for (int u = 0; u < NU; ++u) Ts[col][r0 + RS * u] = nx[u];
     __syncthreads();
     if (k0 + GBK < ke) load(k0 + GBK);  // in flight during the products below
 #pragma unroll
@@ -428,6 +430,7 @@ struct EigTour {
   double cs[32], sn[32];
   int rot_any, need;
   int slot_of[64];
+  int rank[64];
 };
 
 // Outer test on G[0] (rows above the floor only), as eig_needs_rotation
@@ -436,12 +439,15 @@ __device__ inline bool tour_needs_rotation(EigTour &L, double tol, double floor2
   const int tid = threadIdx.x;
   if (tid == 0) L.need = 0;
   __syncthreads();
+  // the test squared (no square root on the path): g_ij^2 > tol^2 g_ii g_jj
+  const double tol2 = tol * tol;
   int loc = 0;
-  for (int e = tid; e < 4096; e += NTE) {
-    const int i = e >> 6, j = e & 63;
+#pragma unroll
+  for (int m = 0; m < 4096 / NTE; ++m) {
+    const int e = tid + m * NTE, i = e >> 6, j = e & 63;
     if (i < j) {
       const double gii = L.G[0][i][i], gjj = L.G[0][j][j], gij = L.G[0][i][j];
-      if (gii > floor2 && gjj > floor2 && gii > 0.0 && gjj > 0.0 && fabs(gij) > tol * sqrt(gii * gjj)) loc = 1;
+      if (gii > floor2 && gjj > floor2 && gii > 0.0 && gjj > 0.0 && gij * gij > tol2 * (gii * gjj)) loc = 1;
     }
   }
   if (__any(loc) && (tid & 63) == 0) atomicOr(&L.need, 1);
@@ -541,22 +547,32 @@ __device__ inline int eig_tour(EigTour &L, int inner_max, double floor2) {
   return cur;
 }
 
-// slot_of as eig_order, from the diagonal of G
-__device__ inline void tour_order(const double (*G)[66], int *slot_of, int np, int nq) {
-  const int r = threadIdx.x;
-  if (r < 64) {
-    const bool vr = r < 32 ? (r < np) : (r - 32 < nq);
-    if (vr) {
-      const double lr_ = G[r][r];
-      int rank = 0;
-      for (int o = 0; o < 64; ++o) {
-        const bool vo = o < 32 ? (o < np) : (o - 32 < nq);
-        if (o == r || !vo) continue;
+// slot_of as eig_order, from the diagonal of G: the rank of slot r (eigenvalues descending, ties
+// by slot) counted by NTE / 64 thread groups over slices of the other slots
+template <int NTE>
+__device__ inline void tour_order(const double (*G)[66], int *slot_of, int *rank, int np, int nq) {
+  constexpr int NG = NTE / 64, PER = 64 / NG;
+  const int r = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  auto valid = [&](int x) { return x < 32 ? (x < np) : (x - 32 < nq); };
+  if (threadIdx.x < 64) rank[r] = 0;
+  __syncthreads();
+  if (valid(r)) {
+    const double lr_ = G[r][r];
+    int cnt = 0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int o = grp * PER + m;
+      if (o != r && valid(o)) {
         const double lo = G[o][o];
-        if (lo > lr_ || (lo == lr_ && o < r)) ++rank;
+        cnt += (lo > lr_ || (lo == lr_ && o < r)) ? 1 : 0;
       }
-      slot_of[rank < np ? rank : 32 + (rank - np)] = r;
     }
+    if (cnt) atomicAdd(&rank[r], cnt);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && valid(r)) {
+    const int k = rank[r];
+    slot_of[k < np ? k : 32 + (k - np)] = r;
   }
   __syncthreads();
 }
@@ -579,27 +595,31 @@ __global__ __launch_bounds__(EIG_NT) void eigen_kernel(const SvdMat *mats, int s
     return;
   }
   auto valid = [&](int r) { return r < 32 ? (r < np) : (r - 32 < nq); };
-  // the K-split partial Grams (at most KS_MAX), summed in split order: every partial of two
-  // elements is loaded before the first sum, so one memory latency covers the lot
+  // the K-split partial Grams (at most KS_MAX), summed in split order; only the upper triangle
+  // is read (rows along the lanes, so every load is one contiguous segment) and mirrored, and
+  // all partials of a thread's elements are loaded before the first sum
   const double *Gp = a.gram + (int64_t)pair * a.ksplit * 4096;
   const int nks = a.ksplit;
-  for (int e0 = tid; e0 < 4096; e0 += 2 * EIG_NT) {
-    double part[2][KS_MAX];
+  constexpr int EPP = 4;  // elements per thread and pass: EPP x KS_MAX loads in flight
+  for (int e0 = tid; e0 < 4096; e0 += EPP * EIG_NT) {
+    double part[EPP][KS_MAX];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < EPP; ++h) {
       const int e = e0 + h * EIG_NT, i = e >> 6, j = e & 63;
-      const int lo = i < j ? i : j, hi = i < j ? j : i;
 #pragma unroll
-      for (int ks = 0; ks < KS_MAX; ++ks) part[h][ks] = ks < nks ? Gp[(int64_t)ks * 4096 + lo * 64 + hi] : 0.0;
+      for (int ks = 0; ks < KS_MAX; ++ks) part[h][ks] = (ks < nks && i <= j) ? Gp[(int64_t)ks * 4096 + e] : 0.0;
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < EPP; ++h) {
       const int e = e0 + h * EIG_NT, i = e >> 6, j = e & 63;
+      if (i > j) continue;
       double v = 0.0;
 #pragma unroll
       for (int ks = 0; ks < KS_MAX; ++ks)
         if (ks < nks) v += part[h][ks];
-      L.G[0][i][j] = (valid(i) && valid(j)) ? v : 0.0;
+      v = (valid(i) && valid(j)) ? v : 0.0;
+      L.G[0][i][j] = v;
+      L.G[0][j][i] = v;
     }
   }
   const double floor2 = row_floor2(a, *a.fro2);
@@ -609,7 +629,7 @@ __global__ __launch_bounds__(EIG_NT) void eigen_kernel(const SvdMat *mats, int s
   }
   if (tid == 0) atomicAdd(a.ctr, 1);
   const int cur = eig_tour<EIG_NT>(L, a.inner_max, floor2);
-  tour_order(L.G[cur], L.slot_of, np, nq);
+  tour_order<EIG_NT>(L.G[cur], L.slot_of, L.rank, np, nq);
   const double(*Q)[66] = L.G[cur ^ 1];
   double *Qt = a.qt + (int64_t)pair * 4096;
   for (int e = tid; e < 4096; e += EIG_NT) {
@@ -956,6 +976,7 @@ __global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
   if (!a.active || !a.precond) return;
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j < a.C) a.cperm[j] = j;
+  if (j == 0) a.ctr[2] = 0;  // arrival counter of qr_col_kernel
 }
 
 // A rows_scaled matrix whose QR start may stop early takes its columns in order of decreasing
@@ -1126,6 +1147,118 @@ __global__ __launch_bounds__(QP_NT) void qr_panel_kernel(const SvdMat *mats, int
       }
     }
     __syncthreads();  // panel column k+1 and vsh are rewritten next
+  }
+}
+
+// The panel factorisation spread over row chunks of QC_ROWS rows, one launch per column:
+// launch k applies reflector k to the panel columns right of it and forms the chunk partials
+// that reflector k+1 needs (|B[k+1:, k+1]|^2 and the dots B[k+2:, k+1] . B[k+2:, c]); the last
+// chunk to arrive (arrival counter, device-scope fences, no waiting) sums the partials in chunk
+// order and writes alpha, beta, v_{k+1,k+1} = x0 - alpha and w_c = beta (v . B[:, c]) for the
+// next launch.  The start launch (k = k0 - 1) forms the partials of column k0 only.  The same
+// reflectors as qr_panel_kernel: x = B[k:R, k], alpha = -sign(x_0) |x|, v = x - alpha e_0,
+// beta = 1 / (|x| (|x| + |x_0|)).  Scratch: chunk partials (33 per chunk) at qws[2048 ..), the
+// scalars at qws[2048 + 64 C + R ..).  grid (chunks, 1, matrices), 256 threads.
+constexpr int QC_ROWS = 64;
+__global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0, int k) {
+  __shared__ double red[8][33];
+  __shared__ int last;
+  const SvdMat &a = mats[blockIdx.z];
+  if (!a.active || !a.precond || k0 >= a.Ra) return;
+  const int R = a.R, C = a.C;
+  const int kend = k0 + 32 < R ? k0 + 32 : R, cend = k0 + 32 < C ? k0 + 32 : C;
+  if (k >= kend) return;
+  const int G = (R - k0 + QC_ROWS - 1) / QC_ROWS, blk = blockIdx.x;
+  if (blk >= G) return;
+  const int tid = threadIdx.x, lane = tid & 63, cl = tid & 31, rsub = tid >> 5;
+  const int c = k0 + cl;
+  const bool colok = c < cend;
+  double *B = a.bw;
+  double *part = a.qws + 2048, *betas = a.qws + 2048 + 64 * (int64_t)C, *sc = betas + R;
+  const bool start = k < k0;
+  if (start) {
+    // reflector rows k0 .. kend-1 start as zero (launch k writes its entries from row k on)
+    const int64_t tot = (int64_t)(kend - k0) * R;
+    for (int64_t e = (int64_t)blk * 256 + tid; e < tot; e += (int64_t)G * 256) a.qv[(int64_t)k0 * R + e] = 0.0;
+    if (blk == 0 && tid == 0) a.fro2[1] = 0.0;  // trailing-row maximum of this panel (qr_tail_kernel)
+  }
+  double alpha = 0.0, beta = 0.0, vk = 0.0, x0 = 0.0, wc = 0.0;
+  const int kc = k - k0;
+  if (!start) {
+    alpha = sc[0];
+    beta = sc[1];
+    vk = sc[2];
+    x0 = sc[3];
+    wc = (cl > kc && colok) ? sc[4 + cl] : 0.0;
+  }
+  double val[QC_ROWS / 8];
+#pragma unroll
+  for (int m = 0; m < QC_ROWS / 8; ++m) {
+    const int i = k0 + blk * QC_ROWS + rsub + 8 * m;
+    double x = (i < R && colok) ? B[(int64_t)i * C + c] : 0.0;
+    if (!start) {
+      const double bk = __shfl(x, (lane & 32) | kc, 64);  // this row's column-k entry
+      if (i < R && i >= k && colok && cl >= kc) {
+        const double vi = (i == k) ? vk : bk;
+        if (cl > kc) {
+          x -= wc * vi;
+        } else {
+          x = (i == k) ? (beta != 0.0 ? alpha : x0) : 0.0;
+          a.qv[(int64_t)k * R + i] = vi;
+        }
+        B[(int64_t)i * C + c] = x;
+      }
+    }
+    val[m] = x;
+  }
+  const int nk = k + 1, nc = nk - k0;
+  if (nk >= kend) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < QC_ROWS / 8; ++m) {
+    const int i = k0 + blk * QC_ROWS + rsub + 8 * m;
+    const double y = val[m];
+    const double ynk = __shfl(y, (lane & 32) | nc, 64);
+    if (i < R && i >= nk) {
+      if (cl == nc) acc += y * y;                    // |B[nk:, nk]|^2
+      else if (cl > nc && i > nk) acc += ynk * y;    // B[nk+1:, nk] . B[nk+1:, c]
+    }
+  }
+  red[rsub][cl] = acc;
+  __syncthreads();
+  if (tid < 32 && cl >= nc) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) t += red[g][cl];
+    part[(int64_t)blk * 33 + 1 + cl] = t;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(&a.ctr[2], 1) == G - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (tid < 32 && cl >= nc) {
+    double t = 0.0;
+    for (int b = 0; b < G; ++b) t += part[(int64_t)b * 33 + 1 + cl];
+    red[0][cl] = t;
+  }
+  __syncthreads();
+  if (tid < 32) {
+    const double nx = sqrt(red[0][nc]);
+    const double xn = B[(int64_t)nk * C + nk];
+    const double al = xn >= 0.0 ? -nx : nx;
+    const double be = nx > 0.0 ? 1.0 / (nx * (nx + fabs(xn))) : 0.0;
+    const double v0 = xn - al;
+    if (cl > nc && colok) sc[4 + cl] = be * (red[0][cl] + v0 * B[(int64_t)nk * C + c]);
+    if (cl == 0) {
+      sc[0] = al;
+      sc[1] = be;
+      sc[2] = v0;
+      sc[3] = xn;
+      betas[nk] = be;
+      a.ctr[2] = 0;
+    }
   }
 }
 
@@ -1723,7 +1856,9 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       TNA_HIP(hipHostMalloc((void **)&g.host_fro, sizeof(double) * 3 * 4096, hipHostMallocDefault));
     timer_begin("svd.qr", s);
     for (int k0 = 0; k0 < qr_rows; k0 += 32) {
-      hipLaunchKernelGGL(qr_panel_kernel, dim3(nm), dim3(QP_NT), 0, s, d, k0);
+      const int chunks = ceil_div(qr_rows - k0, QC_ROWS);
+      for (int k = k0 - 1; k < k0 + 32 && k < qr_rows; ++k)
+        hipLaunchKernelGGL(qr_col_kernel, dim3(chunks, 1, nm), dim3(256), 0, s, d, k0, k);
       TNA_TRY(qr_block_apply(mats, d, nm, k0, true, s));
       const int k1 = k0 + 32;
       int tail = 0;
