@@ -212,7 +212,7 @@ def run_fixed_chi(a):
                   fixed_iters=a.matvecs, fixed_chi=a.chi)
     for _ in range(a.warmup):
         dm.sweep()
-    gname = "gemmg." + ("f64" if a.prec == "f64" else "f32")
+    gname = "heff." + ("f64" if a.prec == "f64" else "f32")  # the H_eff products (both GEMM forms)
     ctx.set_timing(True, gname)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -224,7 +224,7 @@ def run_fixed_chi(a):
     ctx.set_timing(False)
     fl = sum(r["flops"] for r in stats)
     ms = sum(r["ms"] for r in stats)
-    dom = max(stats, key=lambda r: r["ms"])["name"] if stats else ""
+    dom = gname if stats else ""
     chis = np.array([r["k"] for r in recs])
     out = {"metric": f"DMRG sweeps/s at fixed chi={a.chi}", "value": a.steps / (t1 - t0), "unit": "sweeps/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * (t1 - t0) / a.steps,
@@ -252,10 +252,11 @@ def run_scheduler(a):
     chi_min, chi_max, eps_t = 16, a.chi_max, 1e-8
     pid = tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, chi_min, chi_max)
 
-    def run(model, params, N, sweeps, net=None):
+    def run(model, params, N, sweeps, net=None, cmin=chi_min):
         W = tna.mpo_build(model, N, params)
         A, chi, _ = synth.random_mps(N, 2, chi_min, seed=N + 7 * model)
-        dm = tna.Dmrg(ctx, W, A, chi, pid, eps_target=eps_t)
+        pp = pid if cmin == chi_min else tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, cmin, chi_max)
+        dm = tna.Dmrg(ctx, W, A, chi, pp, eps_target=eps_t)
         if net is not None:
             dm.set_scheduler(net)
         recs, E = [], None
@@ -283,6 +284,12 @@ def run_scheduler(a):
     E_ml, r_ml, t_ml = run(tna.MODEL_J1J2, [1.0, 0.241], N, a.steps, net=net)
     last = 2 * (N - 1)
     s_pid, s_ml = scheduler.summarize(r_pid[-last:], eps_t), scheduler.summarize(r_ml[-last:], eps_t)
+    # the PID alone at matched cost: chi_min raised to the cube root of the learned run's mean k^3 over
+    # its last sweep, so that both spend about the same sum of k^3
+    k3 = np.mean([float(r["k"]) ** 3 for r in r_ml[-last:]])
+    c_match = int(min(max(round(k3 ** (1.0 / 3.0)), chi_min), chi_max))
+    E_pm, r_pm, t_pm = run(tna.MODEL_J1J2, [1.0, 0.241], N, a.steps, cmin=c_match)
+    s_pm = scheduler.summarize(r_pm[-last:], eps_t)
     out = {"metric": f"sweeps/s, J1-J2 N={N} with the learned scheduler (PID fallback)", "value": a.steps / t_ml,
            "unit": "sweeps/s", "n_gpus": 1, "steps": a.steps, "warmup": 0, "ms_per_step": 1e3 * t_ml / a.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32-mlp",
@@ -290,6 +297,7 @@ def run_scheduler(a):
                                            "train_samples": int(X.shape[0]), "epochs": 150},
            "pid_only": {"sweeps_per_s": a.steps / t_pid, "E_per_site": E_pid / N, **s_pid},
            "learned": {"sweeps_per_s": a.steps / t_ml, "E_per_site": E_ml / N, **s_ml},
+           "pid_matched_cost": {"chi_min": c_match, "sweeps_per_s": a.steps / t_pm, "E_per_site": E_pm / N, **s_pm},
            "dE_per_site_learned_minus_pid": (E_ml - E_pid) / N, "train_s": t_train,
            "loss_first_last": [float(losses[0]), float(losses[-1])]}
     print(json.dumps(out))

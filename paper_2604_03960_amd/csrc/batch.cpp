@@ -133,16 +133,19 @@ double group_flops(const std::vector<GemmProb> &probs) {
   for (auto &p : probs) f += 2.0 * p.M * (double)p.N * p.K;
   return f;
 }
+// algorithmic bytes of a group (each operand read once, C written once), es bytes per element
+double group_bytes(const std::vector<GemmProb> &probs, int es) {
+  double by = 0.0;
+  for (auto &p : probs) by += (double)es * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N);
+  return by;
+}
 
 // grouped GEMM with its tile picked by the autotuner (kind names the operation)
 tna_status tuned_gemm(int kind, GemmGroup g, std::vector<GemmProb> probs, Arena &ar, hipStream_t s, bool measure,
                       int *tile_out = nullptr) {
   if (probs.empty()) return TNA_OK;
-  const int es = g.compute == G_F64 ? 8 : 4;
-  double by = 0.0;
-  for (auto &p : probs) by += (double)es * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N);
   g.flops = group_flops(probs);
-  g.bytes = by;
+  g.bytes = group_bytes(probs, g.compute == G_F64 ? 8 : 4);
   const auto key = std::make_pair(kind, flop_bucket(g.flops));
   auto it = g_tune.table.find(key);
   int tile = 64;
@@ -493,6 +496,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     g4.tile = tile4;
     g1.flops = group_flops(b1);
     g4.flops = group_flops(b4);
+    g1.bytes = group_bytes(b1, f32 ? 4 : 8);
+    g4.bytes = group_bytes(b4, f32 ? 4 : 8);
     tot1 = gemm_group_tiles(p1, tile1);
     tot4 = gemm_group_tiles(p4, tile4);
     TNA_TRY(arena_push(en->ar, p1.data(), nc, s, &dp1));

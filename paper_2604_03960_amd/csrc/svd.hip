@@ -969,6 +969,10 @@ __global__ void zero_ctr_kernel(const SvdMat *mats, int nmat) {
 // same way.  No column pivoting: on the prescribed-spectrum matrices it did not
 // lower the sweep count; cperm / pinv keep the (identity) column order explicit.
 constexpr int QR_MIN_ROWS_DEV = 256;
+// The products of a block reflector with 32 rows (S = V V^T and W = V X) are long in K and short
+// in M: K is cut into QR_SPLIT pieces that run as one batched launch, and the pieces are summed in
+// order afterwards.
+constexpr int QR_SPLIT = 8;
 
 // grid (column blocks, 1, matrices): the identity column order
 __global__ __launch_bounds__(256) void qr_init_kernel(const SvdMat *mats) {
@@ -1268,24 +1272,30 @@ __global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0,
 __global__ __launch_bounds__(64) void qr_tfactor_kernel(const SvdMat *mats, int k0) {
   const SvdMat &a = mats[blockIdx.x];
   if (!a.active || !a.precond || k0 >= a.Ra) return;
+  __shared__ double Ss[32][33], Ts[32][33], bs[32];
   const int nb = a.R - k0 < 32 ? a.R - k0 : 32;
   const double *S = a.qws;
   double *T = a.qws + 1024;
   const double *beta = a.qws + 2048 + 64 * (int64_t)a.C + k0;
   const int r = threadIdx.x;
-  if (r < 32)
-    for (int c = 0; c < 32; ++c) T[r * 32 + c] = 0.0;
+  // S, beta into LDS once; the recurrence runs in LDS and T goes out at the end
+  for (int e = r; e < 1024; e += 64) {
+    Ss[e >> 5][e & 31] = S[e];
+    Ts[e >> 5][e & 31] = 0.0;
+  }
+  if (r < 32) bs[r] = r < nb ? beta[r] : 0.0;
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
     if (r < i) {
       double acc = 0.0;
-      for (int c = r; c < i; ++c) acc += T[r * 32 + c] * S[c * 32 + i];
-      T[r * 32 + i] = -beta[i] * acc;
+      for (int c = r; c < i; ++c) acc += Ts[r][c] * Ss[c][i];
+      Ts[r][i] = -bs[i] * acc;
     } else if (r == i) {
-      T[i * 32 + i] = beta[i];
+      Ts[i][i] = bs[i];
     }
     __syncthreads();
   }
+  for (int e = r; e < 1024; e += 64) T[e] = Ts[e >> 5][e & 31];
 }
 
 // grid (ceil((R - k1) / 4), 1, matrices): fro2[1] <- the largest squared norm of the rows k1.. of B
@@ -1303,6 +1313,17 @@ __global__ __launch_bounds__(256) void qr_tail_kernel(const SvdMat *mats, int k1
   ss = wave_sum_d(ss);
   if (lane == 0)
     atomicMax(reinterpret_cast<unsigned long long *>(a.fro2 + 1), (unsigned long long)__double_as_longlong(ss));
+}
+
+// out[r * ldo + c] = sum over p < np of part[p * M N + r N + c] (split order), r < M, c < N; grid-stride
+__global__ __launch_bounds__(256) void splitk_sum_kernel(const double *part, int np, int M, int N, double *out,
+                                                         int ldo) {
+  const int64_t n = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int p = 0; p < np; ++p) v += part[(int64_t)p * n + e];
+    out[(e / N) * ldo + e % N] = v;
+  }
 }
 
 // grid (column blocks, 1, matrices)
@@ -1686,7 +1707,7 @@ tna_status svd_plan_mat(int m, int n, int dtype, int batch_hint, SvdMat *a, int 
 size_t svd_work_doubles(const SvdMat &a) {
   const size_t npairs = a.nb / 2;
   return (size_t)a.R * a.C + (size_t)a.R * a.R + npairs * a.ksplit * 4096 + npairs * 4096 + a.R + 8 +
-         (a.precond ? (size_t)a.R * a.R + 2048 + 64 * (size_t)a.C + 2 * (size_t)a.R : 0);
+         (a.precond ? (size_t)a.R * a.R + 2048 + 64 * (size_t)a.C + 2 * (size_t)a.R + QR_SPLIT * 32 * (size_t)a.C : 0);
 }
 size_t svd_work_ints(const SvdMat &a) { return (size_t)a.nb / 2 + a.R + 4 + (a.precond ? 2 * (size_t)a.C : 0); }
 
@@ -1713,7 +1734,8 @@ void svd_bind_work(SvdMat *a, double *dw, int *iw) {
   if (a->precond) {
     a->qv = dw;
     dw += (size_t)a->R * a->R;
-    a->qws = dw;  // S (32 x 32), T (32 x 32), W and W2 (32 x C each), betas (R), spare (R)
+    a->qws = dw;  // S (32 x 32), T (32 x 32), W and W2 (32 x C each), betas (R), spare (R), then the
+                  // split-K partial products (QR_SPLIT x 32 x C)
     a->cperm = iw;
     iw += a->C;
     a->pinv = iw;
@@ -1740,6 +1762,28 @@ static tna_status upload(const std::vector<SvdMat> &mats, SvdGroup &g, hipStream
   return TNA_OK;
 }
 
+// C (M x N, row stride ldc) = A B over K cut into up to QR_SPLIT pieces: A is M x K (rows, lda; transA 0),
+// B is K x N (transB 0: rows of ldb) or N x K (transB 1); pieces go to `part` (one M x N block
+// each), then are summed into C in piece order.
+static tna_status splitk_gemm(int M, int N, int K, const double *A, int lda, const double *B, int ldb, int transB,
+                              double *C, int ldc, double *part, hipStream_t s) {
+  const int kc = std::max(32, ceil_div(ceil_div(K, QR_SPLIT), 16) * 16);
+  const int full = K / kc, rem = K - full * kc;
+  const int64_t mn = (int64_t)M * N;
+  if (full > 0)
+    TNA_TRY(gemm(GemmArgs{M, N, kc, A, lda, 0, G_F64, B, ldb, transB, G_F64, part, N, G_F64, 1.0, 0.0, full, kc,
+                          transB ? (int64_t)kc : (int64_t)kc * ldb, mn, G_F64, 0}, s));
+  if (rem > 0)
+    TNA_TRY(gemm(GemmArgs{M, N, rem, A + (int64_t)full * kc, lda, 0, G_F64,
+                          B + (transB ? (int64_t)full * kc : (int64_t)full * kc * ldb), ldb, transB, G_F64,
+                          part + (int64_t)full * mn, N, G_F64, 1.0, 0.0, 1, 0, 0, 0, G_F64, 0}, s));
+  const int np = full + (rem > 0 ? 1 : 0);
+  hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(mn, 256), 1024)), dim3(256), 0, s,
+                     part, np, M, N, C, ldc);
+  TNA_LAUNCHED("svd.splitk");
+  return TNA_OK;
+}
+
 // X[k0:, :] <- (I - V T^T V^T) X[k0:, :] for the 32 reflectors k0.. of every QR-started
 // matrix, X the trailing columns of B (on_b) or all of Jt; V as rows in qv, T from
 // S = V^T V by qr_tfactor_kernel; scratch in qws.
@@ -1752,8 +1796,8 @@ static tna_status qr_block_apply(const std::vector<SvdMat> &mats, const SvdMat *
     any = true;
     const int R = a.R, nbk = std::min(32, R - k0), K = R - k0;
     const double *Vb = a.qv + (int64_t)k0 * R + k0;
-    TNA_TRY(gemm(GemmArgs{nbk, nbk, K, Vb, R, 0, G_F64, Vb, R, 1, G_F64, a.qws, 32, G_F64, 1.0, 0.0, 1, 0, 0, 0,
-                          G_F64, 0}, s));
+    double *part = a.qws + 2048 + 64 * (int64_t)a.C + 2 * (int64_t)R;
+    TNA_TRY(splitk_gemm(nbk, nbk, K, Vb, R, Vb, R, 1, a.qws, 32, part, s));  // S = V V^T, row stride 32
   }
   if (!any) return TNA_OK;
   hipLaunchKernelGGL(qr_tfactor_kernel, dim3(nm), dim3(64), 0, s, d, k0);
@@ -1766,8 +1810,7 @@ static tna_status qr_block_apply(const std::vector<SvdMat> &mats, const SvdMat *
     double *T = a.qws + 1024, *W = a.qws + 2048, *W2 = a.qws + 2048 + 32 * (int64_t)a.C;
     double *X = on_b ? a.bw + (int64_t)k0 * a.C + k0 + 32 : a.jt + (int64_t)k0 * R;
     const int ldx = on_b ? a.C : R, N = on_b ? a.C - k0 - 32 : R;
-    TNA_TRY(gemm(GemmArgs{nbk, N, K, Vb, R, 0, G_F64, X, ldx, 0, G_F64, W, N, G_F64, 1.0, 0.0, 1, 0, 0, 0, G_F64, 0},
-                 s));
+    TNA_TRY(splitk_gemm(nbk, N, K, Vb, R, X, ldx, 0, W, N, a.qws + 2048 + 64 * (int64_t)a.C + 2 * (int64_t)R, s));
     TNA_TRY(gemm(GemmArgs{nbk, N, nbk, T, 32, 1, G_F64, W, N, 0, G_F64, W2, N, G_F64, 1.0, 0.0, 1, 0, 0, 0, G_F64, 0},
                  s));
     TNA_TRY(gemm(GemmArgs{K, N, nbk, Vb, R, 1, G_F64, W2, N, 0, G_F64, X, ldx, G_F64, -1.0, 1.0, 1, 0, 0, 0, G_F64,
