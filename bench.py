@@ -87,20 +87,30 @@ def copy_probe():
 # what the counter reads for a 1 GiB device copy); valid only while the kernel's source file
 # is unchanged since the counters were taken (sha256 recorded next to the figure)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
-KERNEL_SOURCE = {"lz.small": "paper_2604_03960_amd/csrc/batch.hip", "svd.fused": "paper_2604_03960_amd/csrc/svd.hip",
-                 "heff.f64": "paper_2604_03960_amd/csrc/gemm.hip", "heff.f32": "paper_2604_03960_amd/csrc/gemm.hip",
-                 "svd.apply": "paper_2604_03960_amd/csrc/svd.hip", "svd.eigen": "paper_2604_03960_amd/csrc/svd.hip"}
+# the H_eff products' kernel is in gemm.hip, their launch shapes (problem lists) in batch.cpp
+_HEFF_SRC = ["paper_2604_03960_amd/csrc/gemm.hip", "paper_2604_03960_amd/csrc/batch.cpp"]
+KERNEL_SOURCE = {"lz.small": ["paper_2604_03960_amd/csrc/batch.hip"], "svd.fused": ["paper_2604_03960_amd/csrc/svd.hip"],
+                 "heff.f64": _HEFF_SRC, "heff.f32": _HEFF_SRC,
+                 "svd.apply": ["paper_2604_03960_amd/csrc/svd.hip"], "svd.eigen": ["paper_2604_03960_amd/csrc/svd.hip"]}
+
+
+def source_sha256(kernel):
+    """sha256 over the concatenated sources a kernel family's traffic figure depends on"""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCE[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_for(kernel):
-    import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
             table = json.load(f)
         ent = table[kernel]
-        with open(os.path.join(ROOT, KERNEL_SOURCE[kernel]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != ent["source_sha256"]:
-                return None
+        if source_sha256(kernel) != ent["source_sha256"]:
+            return None
         return ent["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
@@ -210,14 +220,26 @@ def run_fixed_chi(a):
     prec = tna.HEFF_F64 if a.prec == "f64" else tna.HEFF_F32
     dm = tna.Dmrg(ctx, W, A, chi, tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, 16, a.chi), heff_prec=prec,
                   fixed_iters=a.matvecs, fixed_chi=a.chi)
-    for _ in range(a.warmup):
-        dm.sweep()
+    def sweep(tag):
+        """one sweep as its bond visits in sweep order (the engine step of a sweep), with progress lines"""
+        recs, E = [], None
+        for h in (0, 1):
+            for i in range(N - 1):
+                b = i if h == 0 else N - 2 - i
+                E, rec, _ = dm.visit(b, h)
+                recs.append(rec)
+                if i % 10 == 9:
+                    progress(f"{tag}: half {h}, {i + 1} of {N - 1} visits")
+        return E, recs
+
+    for w in range(a.warmup):
+        sweep(f"warm-up sweep {w + 1}")
     gname = "heff." + ("f64" if a.prec == "f64" else "f32")  # the H_eff products (both GEMM forms)
     ctx.set_timing(True, gname)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        E, recs, st = dm.sweep()
+    for i in range(a.steps):
+        E, recs = sweep(f"timed sweep {i + 1}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = ctx.kernel_stats(reset=True)

@@ -295,6 +295,10 @@ struct tna_batch_stats_s {
   long svd_rows, svd_rows_swept; /* rows (min(m, n)) of the visits' SVDs, and the rows their Jacobi sweeps
                             worked on: fewer where a QR start stopped because every later row was at the
                             rounding level (those rows are never rotated) */
+  long heff_ident_steps; /* steps whose H_eff products left out the MPO's identity channels (the left
+                            environment's last channel and the right environment's first channel equal
+                            the identity to 1e-10, as they do for canonical tensors) */
+  double heff_ident_dev;  /* largest deviation of those channels from the identity at the last step */
   int autotune_entries, steps;
 };
 tna_status tna_dmrg_batch_create(tna_ctx ctx, int nchains, const int *N, int d, int D, const double *const *W_host,

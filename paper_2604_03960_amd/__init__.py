@@ -74,6 +74,7 @@ class BatchStats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_lanczos", C.c_double), ("ms_svd", C.c_double), ("ms_env", C.c_double),
                 ("lanczos_iters", C.c_long), ("graph_launches", C.c_long), ("small_launches", C.c_long),
                 ("heff_f32_iters", C.c_long), ("svd_rows", C.c_long), ("svd_rows_swept", C.c_long),
+                ("heff_ident_steps", C.c_long), ("heff_ident_dev", C.c_double),
                 ("autotune_entries", C.c_int),
                 ("steps", C.c_int)]
 

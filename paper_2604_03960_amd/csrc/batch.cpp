@@ -192,6 +192,7 @@ int parts_for(int64_t n) {
 }
 
 constexpr int SPEC = 32;                    // doubles per spectrum record (the SVD writes 0..24)
+constexpr double IDENT_TOL = 1e-10;         // largest deviation of an identity channel that is used as one
 constexpr int LZ_SMALL_N = 4096;            // longest theta of the single-workgroup Lanczos path
 constexpr int NT_SMALL = 512;               // its workgroup size
 constexpr size_t LZ_SLOT = 128;             // per-chain h1/h2/y/nrm2 slots
@@ -222,6 +223,8 @@ struct tna_engine_s {
   long graph_launches = 0, lanczos_iters = 0;
   long heff_f32_iters = 0;  // Lanczos iterations whose H_eff ran on FP32 operands
   long svd_rows = 0, svd_rows_swept = 0;
+  long ident_steps = 0;  // steps whose H_eff products skipped the MPO's identity channels
+  double ident_dev = 0.0;  // largest identity-channel deviation at the last step
   double ms_lanczos = 0, ms_svd = 0, ms_env = 0;
 };
 
@@ -239,7 +242,7 @@ tna_status engine_create(int nslot, tna_engine *out) {
   e->T1.resize(nslot);
   e->T2.resize(nslot);
   TNA_TRY(e->ints.ensure(sizeof(int) * 2 * nslot));
-  TNA_TRY(e->dbl.ensure(sizeof(double) * 2 * nslot));
+  TNA_TRY(e->dbl.ensure(sizeof(double) * 4 * nslot));  // Lanczos records, then identity-channel deviations
   TNA_TRY(e->lzst.ensure(sizeof(double) * (LZ_PER + 2 * LZ_PART) * nslot));
   TNA_TRY(e->spec.ensure(sizeof(double) * SPEC * nslot));
   TNA_TRY(e->feat_d.ensure(sizeof(float) * 32 * nslot));
@@ -284,6 +287,8 @@ void engine_stats(tna_engine e, tna_batch_stats *st) {
   st->heff_f32_iters = e->heff_f32_iters;
   st->svd_rows = e->svd_rows;
   st->svd_rows_swept = e->svd_rows_swept;
+  st->heff_ident_steps = e->ident_steps;
+  st->heff_ident_dev = e->ident_dev;
   st->autotune_entries = (int)g_tune.table.size();
 }
 
@@ -398,30 +403,89 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     maxG = std::max(maxG, p.G);
     maxk = std::max(maxk, v.kmax);
   }
+  // ---- the MPO's identity channels.  Every MPO here keeps the not-yet-started state in the last
+  // bond channel and the finished state in the first (W[D-1][D-1] = W[0][0] = 1 are the only ways
+  // into them), so for left-canonical tensors the left environment's channel D-1 is the identity
+  // matrix and for right-canonical ones the right environment's channel 0 is.  When both hold to
+  // 1e-10 for every chain of the step (checked on the device), S1 skips the channel-(D-1) rows of L
+  // (that part of X is theta itself, which the mixing reads directly) and S4 skips the channel-0
+  // columns (the mixing writes that part of Z straight into the result, which S4 then adds to):
+  // a fifth less of both products for D = 5.  Otherwise (a stopped SVD, a hand-made state) the
+  // full products run.
+  bool ident = true;
+  {
+    double *dev = rec_dev + 2 * en->nslot;
+    TNA_HIP(hipMemsetAsync(dev, 0, sizeof(double) * 2 * en->nslot, s));
+    for (int q = 0; q < nc; ++q) {
+      const Visit &v = vs[q];
+      const int sl = slot[q];
+      TNA_TRY(ident_deviation(ch[q]->Le[v.b].as<double>(), v.chl, D, D - 1, dev + 2 * sl, s));
+      TNA_TRY(ident_deviation(ch[q]->Re[v.b + 1].as<double>(), v.chr, D, 0, dev + 2 * sl + 1, s));
+    }
+    double *hd = en->h_dbl + SPEC * en->nslot;
+    TNA_HIP(hipMemcpyAsync(hd, dev, sizeof(double) * 2 * en->nslot, hipMemcpyDeviceToHost, s));
+    TNA_HIP(hipStreamSynchronize(s));
+    en->ident_dev = 0.0;
+    for (int q = 0; q < nc; ++q) {
+      const int sl = slot[q];
+      if (!(hd[2 * sl] <= IDENT_TOL && hd[2 * sl + 1] <= IDENT_TOL)) ident = false;
+      en->ident_dev = std::max(en->ident_dev, std::max(hd[2 * sl], hd[2 * sl + 1]));
+    }
+  }
+  en->ident_steps += ident ? 1 : 0;
   std::vector<GemmProb> s1, s4;
+  std::vector<int> s1_chain, s4_chain;  // chain of each problem
   std::vector<MixProb> mx;
   int64_t max_mix = 1;
+  const size_t el = f32 ? sizeof(float) : sizeof(double);
   for (int q = 0; q < nc; ++q) {
     tna_dmrg dm = ch[q];
     const Visit &v = vs[q];
     const int sl = slot[q];
-    const void *L = f32 ? (const void *)en->Lf[sl].ptr : dm->Le[v.b].ptr;
-    const void *R = f32 ? (const void *)en->Rf[sl].ptr : dm->Re[v.b + 1].ptr;
-    // S1: X[(a,w)][(s',t',c')] = L[(a,w)][a'] V_j[a'][(s',t',c')]
-    s1.push_back(GemmProb{v.chl * D, d * d * v.chr, v.chl, v.chl, d * d * v.chr, d * d * v.chr, L, lp[q].V,
-                          en->X[sl].ptr, j_dev + sl, nullptr, act_dev + sl, v.nv, 0, 0, 0});
+    const char *L = static_cast<const char *>(f32 ? (const void *)en->Lf[sl].ptr : dm->Le[v.b].ptr);
+    const char *R = static_cast<const char *>(f32 ? (const void *)en->Rf[sl].ptr : dm->Re[v.b + 1].ptr);
+    char *X = static_cast<char *>(en->X[sl].ptr), *Z = static_cast<char *>(en->Z[sl].ptr);
+    MixProb mp{v.chl, v.chr, X, Z, (int64_t)D * d * d * v.chr, 1, (int64_t)d * d * D * v.chr, 1, d * d * v.chr,
+               v.chr, D * v.chr, v.chr, dm->M12.as<double>() + (size_t)I2 * I2 * v.b, act_dev + sl};
+    if (!ident) {
+      // S1: X[(a,w)][(s',t',c')] = L[(a,w)][a'] V_j[a'][(s',t',c')]
+      s1.push_back(GemmProb{v.chl * D, d * d * v.chr, v.chl, v.chl, d * d * v.chr, d * d * v.chr, L, lp[q].V, X,
+                            j_dev + sl, nullptr, act_dev + sl, v.nv, 0, 0, 0});
+      s1_chain.push_back(q);
+      // S4: V_{j+1}[(a,s,t)][c] = Z[(a,s,t)][(w'',c')] R[c][(w'',c')]
+      s4.push_back(GemmProb{v.chl * d * d, v.chr, D * v.chr, D * v.chr, D * v.chr, v.chr, Z, R, lp[q].V + v.nv,
+                            nullptr, j_dev + sl, act_dev + sl, 0, v.nv, 0, 0});
+      s4_chain.push_back(q);
+    } else {
+      // S1 per channel w < D-1: X[(a,w)][.] = L[a][w][a'] V_j[a'][.]
+      for (int w = 0; w < D - 1; ++w) {
+        s1.push_back(GemmProb{v.chl, d * d * v.chr, v.chl, D * v.chl, d * d * v.chr, D * d * d * v.chr,
+                              L + el * w * v.chl, lp[q].V, X + el * (size_t)w * d * d * v.chr, j_dev + sl, nullptr,
+                              act_dev + sl, v.nv, 0, 0, 0});
+        s1_chain.push_back(q);
+      }
+      mp.in_last = lp[q].V;  // channel D-1 of X is V_j
+      mp.is0_last = (int64_t)d * d * v.chr;
+      mp.jin = j_dev + sl;
+      mp.jin_stride = v.nv;
+      mp.out_first = lp[q].V + v.nv;  // channel 0 of Z goes to V_{j+1}
+      mp.os0_first = (int64_t)d * d * v.chr;
+      mp.och1_first = v.chr;
+      mp.jout = j_dev + sl;
+      mp.jout_stride = v.nv;
+      // S4 over the channels w'' >= 1, added to V_{j+1}
+      s4.push_back(GemmProb{v.chl * d * d, v.chr, (D - 1) * v.chr, D * v.chr, D * v.chr, v.chr, Z + el * v.chr,
+                            R + el * v.chr, lp[q].V + v.nv, nullptr, j_dev + sl, act_dev + sl, 0, v.nv, 0, 0});
+      s4_chain.push_back(q);
+    }
     // S2: Z[a][(s,t)][w''][c'] = sum W12 X[a][w][(s',t')][c'];  channel strides per (a, c')
-    mx.push_back(MixProb{v.chl, v.chr, en->X[sl].ptr, en->Z[sl].ptr, (int64_t)D * d * d * v.chr, 1,
-                         (int64_t)d * d * D * v.chr, 1, d * d * v.chr, v.chr, D * v.chr, v.chr,
-                         dm->M12.as<double>() + (size_t)I2 * I2 * v.b, act_dev + sl});
-    // S4: V_{j+1}[(a,s,t)][c] = Z[(a,s,t)][(w'',c')] R[c][(w'',c')]
-    s4.push_back(GemmProb{v.chl * d * d, v.chr, D * v.chr, D * v.chr, D * v.chr, v.chr, en->Z[sl].ptr, R,
-                          lp[q].V + v.nv, nullptr, j_dev + sl, act_dev + sl, 0, v.nv, 0, 0});
+    mx.push_back(mp);
     max_mix = std::max<int64_t>(max_mix, (int64_t)v.chl * v.chr);
   }
   const int tc = f32 ? G_F32 : G_F64;
   GemmGroup g1{0, 0, tc, G_F64, tc, tc, 64, 1.0, 0.0, 0.0, 0.0, "heff"};  // the H_eff products S1 and S4
-  GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, 0.0, 0.0, 0.0, "heff"};
+  GemmGroup g4{0, 1, tc, tc, G_F64, tc, 64, 1.0, ident ? 1.0 : 0.0, 0.0, 0.0, "heff"};
+  const int n1 = (int)s1.size(), n4 = (int)s4.size();
   for (int q = 0; q < nc; ++q) {
     en->hflags[slot[q]] = 0;
     en->hflags[en->nslot + slot[q]] = 1;
@@ -470,9 +534,9 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     return b;
   };
   auto iterate_direct = [&]() -> tna_status {
-    TNA_TRY(gemm_grouped(g1, dp1, nc, tot1, s));
+    TNA_TRY(gemm_grouped(g1, dp1, n1, tot1, s));
     TNA_TRY(mix_grouped(dmx, nc, max_mix, D, d * d, d * d, D, f32, s));
-    TNA_TRY(gemm_grouped(g4, dp4, nc, tot4, s));
+    TNA_TRY(gemm_grouped(g4, dp4, n4, tot4, s));
     return lz_iteration(dlp, nc, maxG, maxk, lz_bytes, s);
   };
   if (nbig > 0) {
@@ -483,11 +547,10 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     }
     // tile choice for the two H_eff GEMMs, measured before capture (j = 0)
     std::vector<GemmProb> b1, b4;
-    for (int q = 0; q < nc; ++q)
-      if (!small[q]) {
-        b1.push_back(s1[q]);
-        b4.push_back(s4[q]);
-      }
+    for (int i = 0; i < n1; ++i)
+      if (!small[s1_chain[i]]) b1.push_back(s1[i]);
+    for (int i = 0; i < n4; ++i)
+      if (!small[s4_chain[i]]) b4.push_back(s4[i]);
     TNA_TRY(tuned_gemm(1, g1, b1, en->ar, s, true, &tile1));
     TNA_TRY(tuned_gemm(2, g4, b4, en->ar, s, true, &tile4));
     TNA_TRY(arena_push(en->ar, mx.data(), nc, s, &dmx));
@@ -500,16 +563,16 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     g4.bytes = group_bytes(b4, f32 ? 4 : 8);
     tot1 = gemm_group_tiles(p1, tile1);
     tot4 = gemm_group_tiles(p4, tile4);
-    TNA_TRY(arena_push(en->ar, p1.data(), nc, s, &dp1));
-    TNA_TRY(arena_push(en->ar, p4.data(), nc, s, &dp4));
+    TNA_TRY(arena_push(en->ar, p1.data(), n1, s, &dp1));
+    TNA_TRY(arena_push(en->ar, p4.data(), n4, s, &dp4));
     // capture one Lanczos iteration (H_eff + CGS2 + record + normalise + advance); with
     // kernel timing on, the iteration is launched directly so that events can bracket
     // single kernels
     if (use_graph) {
       TNA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      tna_status cs = gemm_grouped(g1, dp1, nc, tot1, s);
+      tna_status cs = gemm_grouped(g1, dp1, n1, tot1, s);
       if (cs == TNA_OK) cs = mix_grouped(dmx, nc, max_mix, D, d * d, d * d, D, f32, s);
-      if (cs == TNA_OK) cs = gemm_grouped(g4, dp4, nc, tot4, s);
+      if (cs == TNA_OK) cs = gemm_grouped(g4, dp4, n4, tot4, s);
       if (cs == TNA_OK) cs = lz_iteration(dlp, nc, maxG, maxk, 0.0, s);
       hipError_t ce = hipStreamEndCapture(s, &graph);
       if (cs != TNA_OK) return cs;

@@ -40,9 +40,19 @@ __global__ __launch_bounds__(NT) void mix_grouped_kernel(const MixProb *probs, i
   const T *in = static_cast<const T *>(p.in) + o0 * p.is0 + o1 * p.is1;
   T *out = static_cast<T *>(p.out) + o0 * p.os0 + o1 * p.os1;
   const int I = I1 * I2, J = J1 * J2;
+  const double *inl = p.in_last ? p.in_last + (p.jin ? (int64_t)(*p.jin) * p.jin_stride : 0) + o0 * p.is0_last +
+                                      o1 * p.is1
+                                : nullptr;
+  double *outf = p.out_first ? p.out_first + (p.jout ? (int64_t)(*p.jout) * p.jout_stride : 0) + o0 * p.os0_first +
+                                   o1 * p.os1
+                             : nullptr;
   T x[32];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) x[i] = (i < I) ? in[(i / I2) * p.ich1 + (i % I2) * p.ich2] : T(0);
+  for (int i = 0; i < 32; ++i) {
+    T v = T(0);
+    if (i < I) v = (inl && i / I2 == I1 - 1) ? (T)inl[(i % I2) * p.ich2] : in[(i / I2) * p.ich1 + (i % I2) * p.ich2];
+    x[i] = v;
+  }
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     if (j < J) {
@@ -51,9 +61,23 @@ __global__ __launch_bounds__(NT) void mix_grouped_kernel(const MixProb *probs, i
 #pragma unroll
       for (int i = 0; i < 32; ++i)
         if (i < I) acc += (T)Mj[i] * x[i];
-      out[(j / J2) * p.och1 + (j % J2) * p.och2] = acc;
+      if (outf && j % J2 == 0) outf[(j / J2) * p.och1_first] = (double)acc;
+      else out[(j / J2) * p.och1 + (j % J2) * p.och2] = acc;
     }
   }
+}
+
+__global__ __launch_bounds__(NT) void ident_dev_kernel(const double *E, int chi, int D, int w, double *out) {
+  double m = 0.0;
+  const int64_t n = (int64_t)chi * chi;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
+    const int64_t a = e / chi, b = e - a * chi;
+    m = fmax(m, fabs(E[(a * D + w) * chi + b] - (a == b ? 1.0 : 0.0)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(m));
 }
 
 // ------------------------------------------------------------------ Lanczos
@@ -628,6 +652,14 @@ __global__ __launch_bounds__(NT) void convert_grouped_kernel(const CvtProb *prob
 }
 
 }  // namespace
+
+tna_status ident_deviation(const double *E, int chi, int D, int w, double *out, hipStream_t s) {
+  const int64_t n = (int64_t)chi * chi;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+  hipLaunchKernelGGL(ident_dev_kernel, dim3(grid), dim3(NT), 0, s, E, chi, D, w, out);
+  TNA_LAUNCHED("ident.check");
+  return TNA_OK;
+}
 
 tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, int I2, int J1, int J2, int f32,
                        hipStream_t s) {

@@ -219,7 +219,22 @@ struct MixProb {
   int ich1, ich2, och1, och2;  // channel i = (i1, i2) sits at i1*ich1 + i2*ich2
   const double *M;             // J x I
   const int *active;           // device flag, may be null
+  // optional (null = off): the input channels i1 = I1-1 read from in_last (FP64) at
+  // o0*is0_last + o1*is1 + i2*ich2 plus (*jin)*jin_stride, and the output channels j2 = 0 go to
+  // out_first (FP64) at o0*os0_first + o1*os1 + j1*och1_first plus (*jout)*jout_stride
+  const double *in_last;
+  int64_t is0_last;
+  const int *jin;
+  int64_t jin_stride;
+  double *out_first;
+  int64_t os0_first;
+  int och1_first;
+  const int *jout;
+  int64_t jout_stride;
 };
+// max |E[a][w][a'] - delta(a, a')| over a, a' < chi into *out as the bit pattern of a non-negative
+// double (*out zeroed beforehand); E is chi x D x chi.  grid-stride.
+tna_status ident_deviation(const double *E, int chi, int D, int w, double *out, hipStream_t s);
 tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, int I2, int J1, int J2, int f32,
                        hipStream_t s);
 // One chain's Lanczos state for the current sweep step (device pointers).

@@ -97,8 +97,10 @@ def test_tfim_paramagnet_low_rank_centre_chi128():
     dm.close()
     _compare(ro, np.array(Es), logs, 1e-10)
     assert abs(Es[-1] - tfim_free_fermion_energy(N, 1.0, h)) <= 1e-9 * abs(Es[-1])
-    print("svd rows", st["svd_rows"], "swept", st["svd_rows_swept"])
+    print("svd rows", st["svd_rows"], "swept", st["svd_rows_swept"], "identity-channel steps", st["heff_ident_steps"])
     assert st["svd_rows_swept"] < st["svd_rows"]
+    # canonical tensors: the grouped H_eff products left out the MPO's identity channels
+    assert st["heff_ident_steps"] > 0
 
 
 def test_tfim_ordered_phase_energy():
