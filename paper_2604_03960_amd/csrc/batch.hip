@@ -29,38 +29,52 @@ __device__ inline double block_sum(double v, double *sh) {
 }
 
 // ------------------------------------------------------------------ mixing
-template <typename T>
-__global__ __launch_bounds__(NT) void mix_grouped_kernel(const MixProb *probs, int I1, int I2, int J1, int J2) {
+// Pointers read from a descriptor in memory are generic to the compiler, which then uses flat
+// accesses (counted against both memory and LDS waits); the mixing's operands live in device
+// memory, so they are cast to the global address space.
+template <typename T> using gptr = T __attribute__((address_space(1))) *;
+
+// One thread per (o0, o1): the J outputs from the I inputs with the J x I matrix M, which every thread
+// of the launch reads at the same addresses: through the constant address space those reads become
+// scalar loads shared by the wave.  The channel counts are template constants for the MPOs and
+// physical dimensions in use (CI1 = 0: runtime counts, at most 32 channels).
+template <typename T, int CI1, int CI2, int CJ1, int CJ2>
+__global__ __launch_bounds__(NT) void mix_grouped_kernel(const MixProb *probs, int rI1, int rI2, int rJ1, int rJ2) {
+  constexpr bool fixed = CI1 > 0;
+  const int I1 = fixed ? CI1 : rI1, I2 = fixed ? CI2 : rI2, J1 = fixed ? CJ1 : rJ1, J2 = fixed ? CJ2 : rJ2;
+  constexpr int IM = fixed ? CI1 * CI2 : 32, JM = fixed ? CJ1 * CJ2 : 32;
   const MixProb &p = probs[blockIdx.y];
   if (p.active && !*p.active) return;
+  const int I = I1 * I2, J = J1 * J2;
+  const double __attribute__((address_space(4))) *Ms = (const double __attribute__((address_space(4))) *)p.M;
   const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int64_t total = (int64_t)p.n0 * p.n1;
   if (idx >= total) return;
   const int64_t o0 = idx / p.n1, o1 = idx - o0 * p.n1;
-  const T *in = static_cast<const T *>(p.in) + o0 * p.is0 + o1 * p.is1;
-  T *out = static_cast<T *>(p.out) + o0 * p.os0 + o1 * p.os1;
-  const int I = I1 * I2, J = J1 * J2;
-  const double *inl = p.in_last ? p.in_last + (p.jin ? (int64_t)(*p.jin) * p.jin_stride : 0) + o0 * p.is0_last +
-                                      o1 * p.is1
-                                : nullptr;
-  double *outf = p.out_first ? p.out_first + (p.jout ? (int64_t)(*p.jout) * p.jout_stride : 0) + o0 * p.os0_first +
-                                   o1 * p.os1
-                             : nullptr;
-  T x[32];
+  const gptr<const T> in = (gptr<const T>)(static_cast<const T *>(p.in) + o0 * p.is0 + o1 * p.is1);
+  const gptr<T> out = (gptr<T>)(static_cast<T *>(p.out) + o0 * p.os0 + o1 * p.os1);
+  const gptr<const double> inl =
+      p.in_last ? (gptr<const double>)(p.in_last + (p.jin ? (int64_t)(*p.jin) * p.jin_stride : 0) + o0 * p.is0_last +
+                                       o1 * p.is1)
+                : nullptr;
+  const gptr<double> outf =
+      p.out_first ? (gptr<double>)(p.out_first + (p.jout ? (int64_t)(*p.jout) * p.jout_stride : 0) + o0 * p.os0_first +
+                                   o1 * p.os1)
+                  : nullptr;
+  T x[IM];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) {
+  for (int i = 0; i < IM; ++i) {
     T v = T(0);
     if (i < I) v = (inl && i / I2 == I1 - 1) ? (T)inl[(i % I2) * p.ich2] : in[(i / I2) * p.ich1 + (i % I2) * p.ich2];
     x[i] = v;
   }
 #pragma unroll
-  for (int j = 0; j < 32; ++j) {
+  for (int j = 0; j < JM; ++j) {
     if (j < J) {
       T acc = T(0);
-      const double *Mj = p.M + j * I;
 #pragma unroll
-      for (int i = 0; i < 32; ++i)
-        if (i < I) acc += (T)Mj[i] * x[i];
+      for (int i = 0; i < IM; ++i)
+        if (i < I) acc += (T)Ms[j * I + i] * x[i];
       if (outf && j % J2 == 0) outf[(j / J2) * p.och1_first] = (double)acc;
       else out[(j / J2) * p.och1 + (j % J2) * p.och2] = acc;
     }
@@ -671,8 +685,24 @@ tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, i
   dim3 grid((unsigned)((max_elems + NT - 1) / NT), nprob);
   const char *name = f32 ? "mixg.f32" : "mixg.f64";
   timer_begin(name, s);
-  if (f32) hipLaunchKernelGGL(mix_grouped_kernel<float>, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
-  else hipLaunchKernelGGL(mix_grouped_kernel<double>, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
+  // compile-time channel counts for the H_eff mixing (D, d^2, d^2, D) and the environment mixing
+  // (D, d, d, D) of the MPOs here (d = 2; D = 3, 5, 8)
+  auto launch = [&](auto kf, auto kd) {
+    if (f32) hipLaunchKernelGGL(kf, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
+    else hipLaunchKernelGGL(kd, grid, dim3(NT), 0, s, d, I1, I2, J1, J2);
+  };
+#define TNA_MIX_CASE(a, b, c, e)                                                                       \
+  if (I1 == a && I2 == b && J1 == c && J2 == e) {                                                   \
+    launch(mix_grouped_kernel<float, a, b, c, e>, mix_grouped_kernel<double, a, b, c, e>);          \
+  } else
+  TNA_MIX_CASE(5, 4, 4, 5)
+  TNA_MIX_CASE(5, 2, 2, 5)
+  TNA_MIX_CASE(8, 4, 4, 8)
+  TNA_MIX_CASE(8, 2, 2, 8)
+  TNA_MIX_CASE(3, 4, 4, 3)
+  TNA_MIX_CASE(3, 2, 2, 3)
+  launch(mix_grouped_kernel<float, 0, 0, 0, 0>, mix_grouped_kernel<double, 0, 0, 0, 0>);
+#undef TNA_MIX_CASE
   timer_end(name, 2.0 * I1 * I2 * J1 * J2 * (double)max_elems * nprob,
             (double)(f32 ? 4 : 8) * (I1 * I2 + J1 * J2) * (double)max_elems * nprob, s);
   TNA_LAUNCHED("mix.grouped");

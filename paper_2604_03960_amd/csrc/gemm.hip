@@ -59,11 +59,16 @@ template <int BM> struct TileShape;
 template <> struct TileShape<64> { static constexpr int NT = 256, WR = 2, MINW = 4; };
 template <> struct TileShape<128> { static constexpr int NT = 512, WR = 4, MINW = 4; };
 
+// Device-memory pointers in the global address space: operand pointers read from a descriptor in
+// memory are generic to the compiler, whose flat accesses count against the LDS waits as well and so
+// tie the operand prefetch to the LDS reads of the products.
+template <typename X> using gp = X __attribute__((address_space(1))) *;
+
 // One BM x BN tile of C = alpha op(A) op(B) + beta C at (m0, n0).
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
-__device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, int lda, const TB *__restrict__ B, int ldb,
-                                          TC *__restrict__ C, int ldc, int M, int N, int K, double alpha, double beta,
-                                          int m0, int n0, TileLds<T, BM, BN> &L) {
+__device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, gp<const TB> __restrict__ B, int ldb,
+                                          gp<TC> __restrict__ C, int ldc, int M, int N, int K, double alpha,
+                                          double beta, int m0, int n0, TileLds<T, BM, BN> &L) {
   constexpr int NT = TileShape<BM>::NT, WR = TileShape<BM>::WR, WC = NT / 64 / WR;
   constexpr int WM = BM / WR, WN = BN / WC;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -171,10 +176,10 @@ template <typename T, typename TA, typename TB, typename TC, int BM, int BN, boo
 __global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_kernel(GemmDev g) {
   __shared__ TileLds<T, BM, BN> L;
   const int z = blockIdx.z;
-  gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>(static_cast<const TA *>(g.A) + g.sA * z, g.lda,
-                                             static_cast<const TB *>(g.B) + g.sB * z, g.ldb,
-                                             static_cast<TC *>(g.C) + g.sC * z, g.ldc, g.M, g.N, g.K, g.alpha,
-                                             g.beta, blockIdx.y * BM, blockIdx.x * BN, L);
+  gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>((gp<const TA>)(static_cast<const TA *>(g.A) + g.sA * z), g.lda,
+                                             (gp<const TB>)(static_cast<const TB *>(g.B) + g.sB * z), g.ldb,
+                                             (gp<TC>)(static_cast<TC *>(g.C) + g.sC * z), g.ldc, g.M, g.N, g.K,
+                                             g.alpha, g.beta, blockIdx.y * BM, blockIdx.x * BN, L);
 }
 
 // Persistent grouped GEMM: the grid walks a static work list of tiles that
@@ -199,7 +204,8 @@ __global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_g
     const int tm = local / p.tiles_n, tn = local - tm * p.tiles_n;
     const TB *B = static_cast<const TB *>(p.B) + (p.jB ? (int64_t)(*p.jB) * p.jB_stride : 0);
     TC *C = static_cast<TC *>(p.C) + (p.jC ? (int64_t)(*p.jC) * p.jC_stride : 0);
-    gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>(static_cast<const TA *>(p.A), p.lda, B, p.ldb, C, p.ldc, p.M, p.N,
+    gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>((gp<const TA>)static_cast<const TA *>(p.A), p.lda, (gp<const TB>)B,
+                                               p.ldb, (gp<TC>)C, p.ldc, p.M, p.N,
                                                p.K, alpha, beta, tm * BM, tn * BN, L);
     __syncthreads();
   }

@@ -116,3 +116,32 @@ def test_scheduler_inputs_labels_and_fallback_match_oracle():
         nfb += g["fallback"]
     print(f"scheduler plumbing: {nused} proposals, {nfb} fallbacks over {len(logs)} visits")
     assert nused > 0 and 0 < nfb < nused  # both branches of the rule ran
+
+
+def test_resume_keeps_scheduler_trajectory(tmp_path):
+    """Checkpoint a run with a scheduler attached, continue it, then resume the checkpoint with the same
+    network re-attached: the resumed sweep repeats the continued one visit by visit (proposals, fallbacks,
+    kept ranks, energies), so the saved proposals survive the resume."""
+    import paper_2604_03960_amd as tna
+    ctx = tna.Context(0)
+    N, kp = 14, 20
+    W = oracle.mpo(0, N, [1.0, 1.0, 0.0])
+    A, chi, _ = synth.random_mps(N, 2, CHI[0], seed=11)
+    net = _constant_net(ctx, kp)
+    dm = tna.Dmrg(ctx, W, A, chi, tna.pid_params(2.0, 0.1, 0.5, 1.0, 0.3, *CHI), eps_target=EPS_T)
+    dm.set_scheduler(net)
+    dm.sweep()
+    path = str(tmp_path / "sched.tnack")
+    dm.save(path)
+    _, ref, _ = dm.sweep()
+    dm.close()
+    rs = tna.Dmrg.load(ctx, path)
+    rs.set_scheduler(net)
+    _, got, _ = rs.sweep()
+    rs.close()
+    assert len(got) == len(ref)
+    assert any(r["chi_sched"] > 0 for r in ref)
+    for g, r in zip(got, ref):
+        assert (g["bond"], g["dir"], g["chi_sched"], g["fallback"], g["k"]) == \
+            (r["bond"], r["dir"], r["chi_sched"], r["fallback"], r["k"])
+        assert abs(g["E"] - r["E"]) <= 1e-10 * abs(r["E"])
