@@ -107,30 +107,36 @@ __device__ inline void lz_range(const LzProb &p, bool vec, int64_t &beg, int64_t
   end = beg + chunk < p.n ? beg + chunk : p.n;
 }
 
-// h[i] partials of <V_i, w> for i <= j, w = V_{j+1}; grid (G, chains)
-__global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int which) {
-  __shared__ double sh[4];
-  const LzProb &p = probs[blockIdx.y];
-  if (!*p.active || (int)blockIdx.x >= p.G) return;
+// 16-byte load and store of two elements in device memory
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld2(gptr<const double> a) {
+  const v2d t = *(gptr<const v2d>)a;
+  return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ void st2(gptr<double> a, double2 v) { *(gptr<v2d>)a = v2d{v.x, v.y}; }
+
+// h[i] partials of <V_i, w> for i <= j, w = V_{j+1}, over block b's range
+__device__ __forceinline__ void lz_dot_body(const LzProb &p, double *part, double *sh) {
   const int nv = *p.j + 1;
-  const double *V = p.V, *w = p.V + (int64_t)nv * p.n;
-  const bool vec = (p.n & 1) == 0;
+  const int64_t n = p.n;
+  const int G = p.G;
+  const gptr<const double> V = (gptr<const double>)p.V, w = V + (int64_t)nv * n;
+  const bool vec = (n & 1) == 0;
   int64_t beg, end;
   lz_range(p, vec, beg, end);
-  double *part = which ? p.part2 : p.part1;
   for (int i0 = 0; i0 < nv; i0 += 8) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (vec) {
       for (int64_t e = beg + 4 * threadIdx.x; e < end; e += 4 * NT) {
         const bool two = e + 2 < end;
-        const double2 w0 = *reinterpret_cast<const double2 *>(w + e);
-        const double2 w1 = two ? *reinterpret_cast<const double2 *>(w + e + 2) : make_double2(0.0, 0.0);
+        const double2 w0 = ld2(w + e);
+        const double2 w1 = two ? ld2(w + e + 2) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int g = 0; g < 8; ++g)
           if (i0 + g < nv) {
-            const double *vr = V + (int64_t)(i0 + g) * p.n + e;
-            const double2 a0 = *reinterpret_cast<const double2 *>(vr);
-            const double2 a1 = two ? *reinterpret_cast<const double2 *>(vr + 2) : make_double2(0.0, 0.0);
+            const gptr<const double> vr = V + (int64_t)(i0 + g) * n + e;
+            const double2 a0 = ld2(vr);
+            const double2 a1 = two ? ld2(vr + 2) : make_double2(0.0, 0.0);
             acc[g] += (a0.x * w0.x + a0.y * w0.y) + (a1.x * w1.x + a1.y * w1.y);
           }
       }
@@ -139,17 +145,25 @@ __global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int whi
         const double wv = w[e];
 #pragma unroll
         for (int g = 0; g < 8; ++g)
-          if (i0 + g < nv) acc[g] += V[(int64_t)(i0 + g) * p.n + e] * wv;
+          if (i0 + g < nv) acc[g] += V[(int64_t)(i0 + g) * n + e] * wv;
       }
     }
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
       if (i0 + g < nv) {
         const double r = block_sum(acc[g], sh);
-        if (threadIdx.x == 0) part[(int64_t)(i0 + g) * p.G + blockIdx.x] = r;
+        if (threadIdx.x == 0) part[(int64_t)(i0 + g) * G + blockIdx.x] = r;
       }
     }
   }
+}
+
+// grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int which) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  lz_dot_body(p, which ? p.part2 : p.part1, sh);
 }
 
 // h[i] = sum_b part[i][b]; grid (kmax+1, chains)
@@ -165,15 +179,18 @@ __global__ __launch_bounds__(NT) void lz_reduce_kernel(const LzProb *probs, int 
   if (threadIdx.x == 0) (which ? p.h2 : p.h1)[i] = v;
 }
 
-// w -= sum_{i<=j} h[i] V_i; with norm: partial |w|^2 into part1[b]; grid (G, chains)
-__global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int which, int with_norm) {
-  __shared__ double sh[4];
-  const LzProb &p = probs[blockIdx.y];
-  if (!*p.active || (int)blockIdx.x >= p.G) return;
+// Coefficients that every thread of the launch reads at the same address (written by an earlier
+// launch): through the constant address space these are scalar loads.
+template <typename T> using cptr = const T __attribute__((address_space(4))) *;
+
+// w -= sum_{i<=j} h[i] V_i over block b's range; with norm: partial |w|^2 into part1[b]
+__device__ __forceinline__ void lz_axpy_body(const LzProb &p, const double *hg, int with_norm, double *sh) {
+  const cptr<double> h = (cptr<double>)hg;
   const int nv = *p.j + 1;
-  const double *h = which ? p.h2 : p.h1;
-  double *w = p.V + (int64_t)nv * p.n;
-  const bool vec = (p.n & 1) == 0;
+  const int64_t n = p.n;
+  const gptr<const double> V = (gptr<const double>)p.V;
+  const gptr<double> w = (gptr<double>)p.V + (int64_t)nv * n;
+  const bool vec = (n & 1) == 0;
   int64_t beg, end;
   lz_range(p, vec, beg, end);
   double loc = 0.0;
@@ -183,29 +200,29 @@ __global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int wh
       double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
       for (int i = 0; i < nv; ++i) {
         const double hi = h[i];
-        const double *vr = p.V + (int64_t)i * p.n + e;
-        const double2 a0 = *reinterpret_cast<const double2 *>(vr);
-        const double2 a1 = two ? *reinterpret_cast<const double2 *>(vr + 2) : make_double2(0.0, 0.0);
+        const gptr<const double> vr = V + (int64_t)i * n + e;
+        const double2 a0 = ld2(vr);
+        const double2 a1 = two ? ld2(vr + 2) : make_double2(0.0, 0.0);
         s0x += hi * a0.x;
         s0y += hi * a0.y;
         s1x += hi * a1.x;
         s1y += hi * a1.y;
       }
-      const double2 w0 = *reinterpret_cast<const double2 *>(w + e);
+      const double2 w0 = ld2(w + e);
       const double2 v0 = make_double2(w0.x - s0x, w0.y - s0y);
-      *reinterpret_cast<double2 *>(w + e) = v0;
+      st2(w + e, v0);
       loc += v0.x * v0.x + v0.y * v0.y;
       if (two) {
-        const double2 w1 = *reinterpret_cast<const double2 *>(w + e + 2);
+        const double2 w1 = ld2(w + e + 2);
         const double2 v1 = make_double2(w1.x - s1x, w1.y - s1y);
-        *reinterpret_cast<double2 *>(w + e + 2) = v1;
+        st2(w + e + 2, v1);
         loc += v1.x * v1.x + v1.y * v1.y;
       }
     }
   } else {
     for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
       double acc = 0.0;
-      for (int i = 0; i < nv; ++i) acc += h[i] * p.V[(int64_t)i * p.n + e];
+      for (int i = 0; i < nv; ++i) acc += h[i] * V[(int64_t)i * n + e];
       const double v = w[e] - acc;
       w[e] = v;
       loc += v * v;
@@ -214,6 +231,104 @@ __global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int wh
   if (with_norm) {
     const double r = block_sum(loc, sh);
     if (threadIdx.x == 0) p.part1[blockIdx.x] = r;
+  }
+}
+
+// grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int which, int with_norm) {
+  __shared__ double sh[4];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  lz_axpy_body(p, which ? p.h2 : p.h1, with_norm, sh);
+}
+
+// The first pass's update fused with the second pass's projections: w -= sum_{i<=j} h1[i] V_i, then
+// partials of <V_i, w> into part2, both from one read of each V_i (kept in registers between the
+// two), which saves one of the four streams over the basis per iteration.  The basis length is a
+// compile-time constant of each case (no guarded loads, all NV loads of an element in flight at
+// once); bases longer than LZ_FUSE_MAX vectors take the update and then the projections over the
+// block's range, as the separate kernels do.
+constexpr int LZ_FUSE_MAX = 24;
+template <int NV>
+__device__ __forceinline__ void lz_fused(gptr<const double> V, gptr<double> w, cptr<double> h, int64_t n,
+                                         int64_t beg, int64_t end, bool vec, double (*sw)[NT / 64]) {
+  double hv[NV], acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    hv[i] = h[i];
+    acc[i] = 0.0;
+  }
+  if (vec) {  // beg and end even: whole 16-byte pairs
+    for (int64_t e = beg + 2 * threadIdx.x; e < end; e += 2 * NT) {
+      double2 v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = ld2(V + (int64_t)i * n + e);
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        sx += hv[i] * v[i].x;
+        sy += hv[i] * v[i].y;
+      }
+      double2 wv = ld2(w + e);
+      wv.x -= sx;
+      wv.y -= sy;
+      st2(w + e, wv);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[i].x * wv.x + v[i].y * wv.y;
+    }
+  } else {
+    for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
+      double v[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = V[(int64_t)i * n + e];
+      double sx = 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sx += hv[i] * v[i];
+      const double wv = w[e] - sx;
+      w[e] = wv;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[i] * wv;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double r = wave_sum(acc[i]);
+    if ((threadIdx.x & 63) == 0) sw[i][threadIdx.x >> 6] = r;
+  }
+}
+
+// grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_axpy_dot_kernel(const LzProb *probs) {
+  __shared__ double sh[4];
+  __shared__ double sw[LZ_FUSE_MAX][NT / 64];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const int nv = *p.j + 1;
+  if (nv > LZ_FUSE_MAX) {
+    lz_axpy_body(p, p.h1, 0, sh);
+    __syncthreads();
+    lz_dot_body(p, p.part2, sh);
+    return;
+  }
+  const int64_t n = p.n;
+  const int G = p.G;
+  double *part = p.part2;
+  const gptr<const double> V = (gptr<const double>)p.V;
+  const gptr<double> w = (gptr<double>)p.V + (int64_t)nv * n;
+  const cptr<double> h = (cptr<double>)p.h1;
+  const bool vec = (n & 1) == 0;
+  int64_t beg, end;
+  lz_range(p, vec, beg, end);
+  switch (nv) {
+#define LZ_FUSED(k) \
+  case k: lz_fused<k>(V, w, h, n, beg, end, vec, sw); break;
+    LZ_FUSED(1) LZ_FUSED(2) LZ_FUSED(3) LZ_FUSED(4) LZ_FUSED(5) LZ_FUSED(6) LZ_FUSED(7) LZ_FUSED(8) LZ_FUSED(9) LZ_FUSED(10) LZ_FUSED(11) LZ_FUSED(12) LZ_FUSED(13) LZ_FUSED(14) LZ_FUSED(15) LZ_FUSED(16) LZ_FUSED(17) LZ_FUSED(18) LZ_FUSED(19) LZ_FUSED(20) LZ_FUSED(21) LZ_FUSED(22) LZ_FUSED(23) LZ_FUSED(24)
+#undef LZ_FUSED
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    const double *q = sw[threadIdx.x];
+    part[(int64_t)threadIdx.x * G + blockIdx.x] = (q[0] + q[1]) + (q[2] + q[3]);
   }
 }
 
@@ -711,15 +826,18 @@ tna_status mix_grouped(const MixProb *d, int nprob, int64_t max_elems, int I1, i
 
 tna_status lz_iteration(const LzProb *d, int nch, int maxG, int kmax, double bytes_hint, hipStream_t s) {
   const dim3 g(maxG, nch), r(kmax + 1, nch), one(1, nch);
-  for (int pass = 0; pass < 2; ++pass) {
-    timer_begin("lz.dot", s);
-    hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, pass);
-    timer_end("lz.dot", bytes_hint / 4.0, bytes_hint, s);
-    hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, pass);
-    timer_begin("lz.axpy", s);
-    hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, pass, pass);
-    timer_end("lz.axpy", bytes_hint / 4.0, bytes_hint, s);
-  }
+  // CGS2: projections h1, update with h1 fused with the projections h2, update with h2 and |w|^2
+  timer_begin("lz.dot", s);
+  hipLaunchKernelGGL(lz_dot_kernel, g, dim3(NT), 0, s, d, 0);
+  timer_end("lz.dot", bytes_hint / 4.0, bytes_hint, s);
+  hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, 0);
+  timer_begin("lz.axpy_dot", s);
+  hipLaunchKernelGGL(lz_axpy_dot_kernel, g, dim3(NT), 0, s, d);
+  timer_end("lz.axpy_dot", bytes_hint / 2.0, bytes_hint, s);
+  hipLaunchKernelGGL(lz_reduce_kernel, r, dim3(NT), 0, s, d, 1);
+  timer_begin("lz.axpy", s);
+  hipLaunchKernelGGL(lz_axpy_kernel, g, dim3(NT), 0, s, d, 1, 1);
+  timer_end("lz.axpy", bytes_hint / 4.0, bytes_hint, s);
   hipLaunchKernelGGL(lz_record_kernel, one, dim3(NT), 0, s, d);
   hipLaunchKernelGGL(lz_normalize_kernel, g, dim3(NT), 0, s, d);
   hipLaunchKernelGGL(lz_advance_kernel, dim3((nch + 63) / 64), dim3(64), 0, s, d, nch);

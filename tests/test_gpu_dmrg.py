@@ -152,12 +152,15 @@ def test_c2_headline_first_sweep():
     assert abs(E - ro["E"][0]) / N <= 1e-10 + amb
 
 
-def test_fixed_iterations_grouped_path():
+@pytest.mark.parametrize("its", [12, 26])
+def test_fixed_iterations_grouped_path(its):
     """The fixed-profile throughput mode (a fixed number of matvecs per Lanczos, every bond at
     min(chi, rank)) at a chi that sends the middle bonds through the grouped, graph-replayed Lanczos:
-    N = 14, chi 40, 12 matvecs per visit, two sweeps, against the oracle's fixed-iteration Lanczos."""
+    N = 14, chi 40, 12 or 26 matvecs per visit (26: bases longer than the 24 vectors whose
+    reorthogonalisation update and projections share one read), two sweeps, against the oracle's
+    fixed-iteration Lanczos."""
     import paper_2604_03960_amd as tna
-    N, chi_f, its = 14, 40, 12
+    N, chi_f = 14, 40
     W = oracle.mpo(oracle.MODEL_XXZ, N, [1.0, 1.0, 0.0])
     A, chi, _ = synth.random_mps(N, 2, 8, seed=4)
     pp = (2.0, 0.1, 0.5, 1.0, 0.3, 8, chi_f)
