@@ -666,7 +666,7 @@ def run_chi2048(a):
         "roofline": roof, "svd_chi2048": svd, "g1_f32_heff": g1, "pid_N100": pid100,
         "heff_chi2048_vs_oracle": cpu.get("heff_chi2048_sampled"),
         "cpu_baseline": cpu.get("cpu_baseline"),
-        "kernel_ranking_one_step": sorted(ranking, key=lambda r: -r["ms"])[:10],
+        "kernel_ranking_one_step": sorted(ranking, key=lambda r: -r["ms"])[:16],
     }
     print(json.dumps(out))
 

@@ -158,13 +158,6 @@ __device__ __forceinline__ void lz_dot_body(const LzProb &p, double *part, doubl
   }
 }
 
-// grid (G, chains)
-__global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int which) {
-  __shared__ double sh[4];
-  const LzProb &p = probs[blockIdx.y];
-  if (!*p.active || (int)blockIdx.x >= p.G) return;
-  lz_dot_body(p, which ? p.part2 : p.part1, sh);
-}
 
 // h[i] = sum_b part[i][b]; grid (kmax+1, chains)
 __global__ __launch_bounds__(NT) void lz_reduce_kernel(const LzProb *probs, int which) {
@@ -234,102 +227,143 @@ __device__ __forceinline__ void lz_axpy_body(const LzProb &p, const double *hg, 
   }
 }
 
-// grid (G, chains)
-__global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int which, int with_norm) {
-  __shared__ double sh[4];
-  const LzProb &p = probs[blockIdx.y];
-  if (!*p.active || (int)blockIdx.x >= p.G) return;
-  lz_axpy_body(p, which ? p.h2 : p.h1, with_norm, sh);
-}
 
-// The first pass's update fused with the second pass's projections: w -= sum_{i<=j} h1[i] V_i, then
-// partials of <V_i, w> into part2, both from one read of each V_i (kept in registers between the
-// two), which saves one of the four streams over the basis per iteration.  The basis length is a
-// compile-time constant of each case (no guarded loads, all NV loads of an element in flight at
-// once); bases longer than LZ_FUSE_MAX vectors take the update and then the projections over the
-// block's range, as the separate kernels do.
-constexpr int LZ_FUSE_MAX = 24;
-template <int NV>
-__device__ __forceinline__ void lz_fused(gptr<const double> V, gptr<double> w, cptr<double> h, int64_t n,
+// Passes over one chain's range with a basis of NV vectors, w = V_NV.  NV is a compile-time constant
+// of each case (no guarded loads; all NV loads of an element pair are in flight at once):
+//   LZ_DOT:    partials of <V_i, w>;
+//   LZ_UPDOT:  w -= sum_i h[i] V_i, then partials of <V_i, w> from the same loads: the first CGS
+//              pass's update fused with the second pass's projections, one read of the basis for both;
+//   LZ_UPNORM: w -= sum_i h[i] V_i and the partial of |w|^2.
+// Per-wave partials go to sw[i][wave] (the norm's to sw[0][wave]).  Bases longer than LZ_FIXED_MAX
+// vectors take lz_dot_body / lz_axpy_body.
+enum { LZ_DOT = 0, LZ_UPDOT = 1, LZ_UPNORM = 2 };
+constexpr int LZ_FIXED_MAX = 24;
+template <int NV, int MODE>
+__device__ __forceinline__ void lz_fixed(gptr<const double> V, gptr<double> w, cptr<double> h, int64_t n,
                                          int64_t beg, int64_t end, bool vec, double (*sw)[NT / 64]) {
-  double hv[NV], acc[NV];
+  constexpr bool upd = MODE != LZ_DOT, dots = MODE != LZ_UPNORM;
+  constexpr int NA = dots ? NV : 1;
+  double hv[NV], acc[NA];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    hv[i] = h[i];
-    acc[i] = 0.0;
-  }
+  for (int i = 0; i < NV; ++i) hv[i] = upd ? h[i] : 0.0;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) acc[i] = 0.0;
   if (vec) {  // beg and end even: whole 16-byte pairs
     for (int64_t e = beg + 2 * threadIdx.x; e < end; e += 2 * NT) {
       double2 v[NV];
 #pragma unroll
       for (int i = 0; i < NV; ++i) v[i] = ld2(V + (int64_t)i * n + e);
-      double sx = 0.0, sy = 0.0;
-#pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        sx += hv[i] * v[i].x;
-        sy += hv[i] * v[i].y;
-      }
       double2 wv = ld2(w + e);
-      wv.x -= sx;
-      wv.y -= sy;
-      st2(w + e, wv);
+      if (upd) {
+        double sx = 0.0, sy = 0.0;
 #pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += v[i].x * wv.x + v[i].y * wv.y;
+        for (int i = 0; i < NV; ++i) {
+          sx += hv[i] * v[i].x;
+          sy += hv[i] * v[i].y;
+        }
+        wv.x -= sx;
+        wv.y -= sy;
+        st2(w + e, wv);
+      }
+      if (dots) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += v[i].x * wv.x + v[i].y * wv.y;
+      } else {
+        acc[0] += wv.x * wv.x + wv.y * wv.y;
+      }
     }
   } else {
     for (int64_t e = beg + threadIdx.x; e < end; e += NT) {
       double v[NV];
 #pragma unroll
       for (int i = 0; i < NV; ++i) v[i] = V[(int64_t)i * n + e];
-      double sx = 0.0;
+      double wv = w[e];
+      if (upd) {
+        double sx = 0.0;
 #pragma unroll
-      for (int i = 0; i < NV; ++i) sx += hv[i] * v[i];
-      const double wv = w[e] - sx;
-      w[e] = wv;
+        for (int i = 0; i < NV; ++i) sx += hv[i] * v[i];
+        wv -= sx;
+        w[e] = wv;
+      }
+      if (dots) {
 #pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += v[i] * wv;
+        for (int i = 0; i < NV; ++i) acc[i] += v[i] * wv;
+      } else {
+        acc[0] += wv * wv;
+      }
     }
   }
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
+  for (int i = 0; i < NA; ++i) {
     const double r = wave_sum(acc[i]);
     if ((threadIdx.x & 63) == 0) sw[i][threadIdx.x >> 6] = r;
   }
 }
 
-// grid (G, chains)
-__global__ __launch_bounds__(NT) void lz_axpy_dot_kernel(const LzProb *probs) {
+// One pass of block b over chain p's range for nv <= LZ_FIXED_MAX; partials into part[i * G + b].
+template <int MODE>
+__device__ __forceinline__ void lz_pass(const LzProb &p, int nv, const double *hg, double *part,
+                                        double (*sw)[NT / 64]) {
+  const int64_t n = p.n;
+  const int G = p.G;
+  const gptr<const double> V = (gptr<const double>)p.V;
+  const gptr<double> w = (gptr<double>)p.V + (int64_t)nv * n;
+  const cptr<double> h = (cptr<double>)hg;
+  const bool vec = (n & 1) == 0;
+  int64_t beg, end;
+  lz_range(p, vec, beg, end);
+  switch (nv) {
+#define LZ_F(k) \
+  case k: lz_fixed<k, MODE>(V, w, h, n, beg, end, vec, sw); break;
+    LZ_F(1) LZ_F(2) LZ_F(3) LZ_F(4) LZ_F(5) LZ_F(6) LZ_F(7) LZ_F(8) LZ_F(9) LZ_F(10) LZ_F(11) LZ_F(12) LZ_F(13) LZ_F(14) LZ_F(15) LZ_F(16) LZ_F(17) LZ_F(18) LZ_F(19) LZ_F(20) LZ_F(21) LZ_F(22) LZ_F(23) LZ_F(24)
+#undef LZ_F
+  }
+  __syncthreads();
+  const int nout = MODE == LZ_UPNORM ? 1 : nv;
+  if ((int)threadIdx.x < nout) {
+    const double *q = sw[threadIdx.x];
+    part[(int64_t)threadIdx.x * G + blockIdx.x] = (q[0] + q[1]) + (q[2] + q[3]);
+  }
+}
+
+// CGS projections: h[i] partials of <V_i, w> into part1 (which = 0) or part2; grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_dot_kernel(const LzProb *probs, int which) {
   __shared__ double sh[4];
-  __shared__ double sw[LZ_FUSE_MAX][NT / 64];
+  __shared__ double sw[LZ_FIXED_MAX][NT / 64];
   const LzProb &p = probs[blockIdx.y];
   if (!*p.active || (int)blockIdx.x >= p.G) return;
   const int nv = *p.j + 1;
-  if (nv > LZ_FUSE_MAX) {
+  double *part = which ? p.part2 : p.part1;
+  if (nv > LZ_FIXED_MAX) lz_dot_body(p, part, sh);
+  else lz_pass<LZ_DOT>(p, nv, nullptr, part, sw);
+}
+
+// CGS update with h1 (which = 0) or h2; with norm: partial |w|^2 into part1[b]; grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_axpy_kernel(const LzProb *probs, int which, int with_norm) {
+  __shared__ double sh[4];
+  __shared__ double sw[LZ_FIXED_MAX][NT / 64];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const int nv = *p.j + 1;
+  const double *h = which ? p.h2 : p.h1;
+  if (nv > LZ_FIXED_MAX || !with_norm) lz_axpy_body(p, h, with_norm, sh);
+  else lz_pass<LZ_UPNORM>(p, nv, h, p.part1, sw);
+}
+
+// First-pass update with h1 fused with the second-pass projections into part2; grid (G, chains)
+__global__ __launch_bounds__(NT) void lz_axpy_dot_kernel(const LzProb *probs) {
+  __shared__ double sh[4];
+  __shared__ double sw[LZ_FIXED_MAX][NT / 64];
+  const LzProb &p = probs[blockIdx.y];
+  if (!*p.active || (int)blockIdx.x >= p.G) return;
+  const int nv = *p.j + 1;
+  if (nv > LZ_FIXED_MAX) {
     lz_axpy_body(p, p.h1, 0, sh);
     __syncthreads();
     lz_dot_body(p, p.part2, sh);
     return;
   }
-  const int64_t n = p.n;
-  const int G = p.G;
-  double *part = p.part2;
-  const gptr<const double> V = (gptr<const double>)p.V;
-  const gptr<double> w = (gptr<double>)p.V + (int64_t)nv * n;
-  const cptr<double> h = (cptr<double>)p.h1;
-  const bool vec = (n & 1) == 0;
-  int64_t beg, end;
-  lz_range(p, vec, beg, end);
-  switch (nv) {
-#define LZ_FUSED(k) \
-  case k: lz_fused<k>(V, w, h, n, beg, end, vec, sw); break;
-    LZ_FUSED(1) LZ_FUSED(2) LZ_FUSED(3) LZ_FUSED(4) LZ_FUSED(5) LZ_FUSED(6) LZ_FUSED(7) LZ_FUSED(8) LZ_FUSED(9) LZ_FUSED(10) LZ_FUSED(11) LZ_FUSED(12) LZ_FUSED(13) LZ_FUSED(14) LZ_FUSED(15) LZ_FUSED(16) LZ_FUSED(17) LZ_FUSED(18) LZ_FUSED(19) LZ_FUSED(20) LZ_FUSED(21) LZ_FUSED(22) LZ_FUSED(23) LZ_FUSED(24)
-#undef LZ_FUSED
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < nv) {
-    const double *q = sw[threadIdx.x];
-    part[(int64_t)threadIdx.x * G + blockIdx.x] = (q[0] + q[1]) + (q[2] + q[3]);
-  }
+  lz_pass<LZ_UPDOT>(p, nv, p.h1, p.part2, sw);
 }
 
 // beta^2 = sum of the norm partials; records alpha_j, beta_j^2; grid (1, chains)
