@@ -18,8 +18,11 @@
 // sweep).  Afterwards sigma_r = |row r|, a bitonic sort orders them, and the
 // factors are written with the sign gauge (largest-magnitude entry of each
 // left vector positive) and Gram-Schmidt completion of null vectors.
+#include <hip/hip_cooperative_groups.h>
+
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #include "dev_reduce.h"
 #include "internal.h"
@@ -1266,6 +1269,137 @@ __global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0,
   }
 }
 
+// The same panel factorisation as qr_col_kernel in one cooperative launch per panel: each
+// workgroup keeps its 64-row chunk of the panel in registers for all 32 columns, and one grid
+// barrier per column replaces a launch.  Per column every workgroup writes its chunk partials
+// (|B[k+1:, k+1]|^2, the dots B[k+2:, k+1] . B[k+2:, c], and, for the chunk holding row k+1,
+// that row's entries) into one of two alternating buffers, passes the barrier, and sums all
+// chunks' partials in chunk order itself, so every workgroup forms the same reflector scalars
+// with the additions of the per-launch path (row k+1's entries come from one chunk, the other
+// chunks add exact zeros).  The chunk is written back to B after the last column.  Must be
+// launched with hipLaunchCooperativeKernel (all workgroups resident); every workgroup of the
+// grid passes the same 33 barriers whatever its matrix.  Scratch: 2 x 65 partials per chunk at
+// qws[2048 ..).  grid (chunks, 1, matrices), 256 threads.
+__global__ __launch_bounds__(256) void qr_panel_coop_kernel(const SvdMat *mats, int k0) {
+  __shared__ double red[8][33];
+  __shared__ double rowv[32];
+  __shared__ double scs[4 + 32];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const SvdMat &a = mats[blockIdx.z];
+  const int R = a.R, C = a.C;
+  const bool on = a.active && a.precond && k0 < a.Ra && k0 < R;
+  const int kend = k0 + 32 < R ? k0 + 32 : R, cend = k0 + 32 < C ? k0 + 32 : C;
+  const int G = on ? (R - k0 + QC_ROWS - 1) / QC_ROWS : 0, blk = blockIdx.x;
+  const bool mine = blk < G;
+  const int tid = threadIdx.x, lane = tid & 63, cl = tid & 31, rsub = tid >> 5;
+  const int c = k0 + cl;
+  const bool colok = c < cend;
+  double *B = a.bw;
+  double *part = a.qws + 2048, *betas = a.qws + 2048 + 64 * (int64_t)C;
+  double val[QC_ROWS / 8];
+  if (mine) {
+    // reflector rows k0 .. kend-1 start as zero (column k writes its entries from row k on)
+    const int64_t tot = (int64_t)(kend - k0) * R;
+    for (int64_t e = (int64_t)blk * 256 + tid; e < tot; e += (int64_t)G * 256) a.qv[(int64_t)k0 * R + e] = 0.0;
+    if (blk == 0 && tid == 0) a.fro2[1] = 0.0;  // trailing-row maximum of this panel (qr_tail_kernel)
+  }
+#pragma unroll
+  for (int m = 0; m < QC_ROWS / 8; ++m) {
+    const int i = k0 + blk * QC_ROWS + rsub + 8 * m;
+    val[m] = (mine && i < R && colok) ? B[(int64_t)i * C + c] : 0.0;
+  }
+  for (int it = 0; it <= 32; ++it) {
+    const int k = k0 - 1 + it;
+    if (mine && it > 0 && k < kend) {  // apply reflector k to the chunk
+      const int kc = k - k0;
+      const double alpha = scs[0], beta = scs[1], vk = scs[2], x0 = scs[3];
+      const double wc = (cl > kc && colok) ? scs[4 + cl] : 0.0;
+#pragma unroll
+      for (int m = 0; m < QC_ROWS / 8; ++m) {
+        const int i = k0 + blk * QC_ROWS + rsub + 8 * m;
+        double x = val[m];
+        const double bk = __shfl(x, (lane & 32) | kc, 64);  // this row's column-k entry
+        if (i < R && i >= k && colok && cl >= kc) {
+          const double vi = (i == k) ? vk : bk;
+          if (cl > kc) {
+            x -= wc * vi;
+          } else {
+            x = (i == k) ? (beta != 0.0 ? alpha : x0) : 0.0;
+            a.qv[(int64_t)k * R + i] = vi;
+          }
+        }
+        val[m] = x;
+      }
+    }
+    const int nk = k + 1, nc = nk - k0;
+    const bool more = mine && nk < kend;
+    double *pp = part + (int64_t)(it & 1) * G * 65;
+    if (more) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < QC_ROWS / 8; ++m) {
+        const int i = k0 + blk * QC_ROWS + rsub + 8 * m;
+        const double y = val[m];
+        const double ynk = __shfl(y, (lane & 32) | nc, 64);
+        if (i < R && i >= nk) {
+          if (cl == nc) acc += y * y;                    // |B[nk:, nk]|^2
+          else if (cl > nc && i > nk) acc += ynk * y;    // B[nk+1:, nk] . B[nk+1:, c]
+        }
+      }
+      red[rsub][cl] = acc;
+      __syncthreads();
+      if (tid < 32) {
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) t += red[g][cl];
+        pp[(int64_t)blk * 65 + 1 + cl] = cl >= nc ? t : 0.0;
+      }
+      // row nk's entries from the chunk that holds the row, exact zeros from the others
+      const int own = (nk - k0) / QC_ROWS, ro = (nk - k0) % QC_ROWS;
+      if (blk != own) {
+        if (tid < 32) pp[(int64_t)blk * 65 + 33 + cl] = 0.0;
+      } else if (rsub == ro % 8) {
+#pragma unroll
+        for (int m = 0; m < QC_ROWS / 8; ++m)
+          if (m == ro / 8) pp[(int64_t)blk * 65 + 33 + cl] = colok ? val[m] : 0.0;
+      }
+    }
+    grid.sync();  // device-scope release and acquire: the partials written above are visible after it
+    if (more) {
+      if (tid < 64) {
+        double t = 0.0;
+        for (int b = 0; b < G; ++b) t += pp[(int64_t)b * 65 + 1 + tid];
+        if (tid < 32) red[0][tid] = t;
+        else rowv[tid - 32] = t;
+      }
+      __syncthreads();
+      if (tid < 32) {
+        const double nx = sqrt(red[0][nc]);
+        const double xn = rowv[nc];
+        const double al = xn >= 0.0 ? -nx : nx;
+        const double be = nx > 0.0 ? 1.0 / (nx * (nx + fabs(xn))) : 0.0;
+        const double v0 = xn - al;
+        if (cl > nc && colok) scs[4 + cl] = be * (red[0][cl] + v0 * rowv[cl]);
+        if (cl == 0) {
+          scs[0] = al;
+          scs[1] = be;
+          scs[2] = v0;
+          scs[3] = xn;
+          if (blk == 0) betas[nk] = be;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (mine) {
+#pragma unroll
+    for (int m = 0; m < QC_ROWS / 8; ++m) {
+      const int i = k0 + blk * QC_ROWS + rsub + 8 * m;
+      if (i < R && colok) B[(int64_t)i * C + c] = val[m];
+    }
+  }
+}
+
 // T of the compact form H_k0 ... H_k0+nb-1 = I - V T V^T (T upper triangular) from
 // S = V^T V and the betas: T_ii = beta_i, T[0:i, i] = -beta_i T[0:i, 0:i] S[0:i, i].
 // One workgroup per matrix; S at qws[0..1024), T at qws[1024..2048), 32 x 32 row-major.
@@ -1897,11 +2031,35 @@ tna_status svd_group_run(std::vector<SvdMat> &mats, SvdGroup &g, int max_sweeps,
       }
     if (nwatch > 0 && !g.host_fro)
       TNA_HIP(hipHostMalloc((void **)&g.host_fro, sizeof(double) * 3 * 4096, hipHostMallocDefault));
+    // the panel factorisation: one cooperative launch per panel where the runtime admits the
+    // grid (all workgroups resident), else one launch per column.  TNA_QR_PANEL=col forces the
+    // per-column launches; TNA_QR_PANEL=coop makes a refused cooperative launch an error.
+    const char *qp = std::getenv("TNA_QR_PANEL");
+    const bool force_coop = qp && std::strcmp(qp, "coop") == 0;
+    bool coop = !(qp && std::strcmp(qp, "col") == 0);
     timer_begin("svd.qr", s);
     for (int k0 = 0; k0 < qr_rows; k0 += 32) {
       const int chunks = ceil_div(qr_rows - k0, QC_ROWS);
-      for (int k = k0 - 1; k < k0 + 32 && k < qr_rows; ++k)
-        hipLaunchKernelGGL(qr_col_kernel, dim3(chunks, 1, nm), dim3(256), 0, s, d, k0, k);
+      bool panel_done = false;
+      if (coop) {
+        int kk0 = k0;
+        void *args[] = {(void *)&d, (void *)&kk0};
+        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(qr_panel_coop_kernel),
+                                                        dim3(chunks, 1, nm), dim3(256), args, 0, s);
+        if (e == hipSuccess) {
+          panel_done = true;
+        } else {
+          (void)hipGetLastError();  // not admitted: the per-column launches from here on
+          if (force_coop) {
+            set_error("svd: cooperative QR panel launch not admitted");
+            return TNA_ERR_UNSUPPORTED;
+          }
+          coop = false;
+        }
+      }
+      if (!panel_done)
+        for (int k = k0 - 1; k < k0 + 32 && k < qr_rows; ++k)
+          hipLaunchKernelGGL(qr_col_kernel, dim3(chunks, 1, nm), dim3(256), 0, s, d, k0, k);
       TNA_TRY(qr_block_apply(mats, d, nm, k0, true, s));
       const int k1 = k0 + 32;
       int tail = 0;

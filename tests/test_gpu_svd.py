@@ -148,3 +148,30 @@ def test_svd_batched_c3_against_closed_form_and_oracle():
     big = So >= 1e-4 * So[0]
     S1 = S[1].cpu().numpy()
     assert np.all(np.abs(S1[big] - So[big]) <= 1e-10 * So[big])
+
+
+@pytest.mark.parametrize("case", ["single_600x280", "batched_4x300x520", "decaying_1024"])
+def test_qr_panel_cooperative_equals_per_column(case, monkeypatch):
+    """The QR start's panel factorisation in one cooperative launch per panel (every workgroup
+    resident, one grid barrier per column) against one launch per column: the same reflectors from
+    the same additions in the same order, so sigma, U, Vt, the spectrum sums and the sweep counts
+    agree bit for bit.  TNA_QR_PANEL=coop makes a refused cooperative launch an error, so the first
+    call really ran the cooperative form."""
+    import torch
+    c = ctx()
+    if case == "single_600x280":
+        As, k = synth.random_matrix(600, 280, 17)[None], 180
+    elif case == "batched_4x300x520":
+        As, k = np.stack([synth.random_matrix(300, 520, 40 + i) for i in range(4)]), 200
+    else:
+        As, k = synth.svd_test_matrix(1024, 8.0, seed=3)[None], 512
+    Ad = torch.from_numpy(np.ascontiguousarray(As)).cuda()
+    outs = {}
+    for mode in ("coop", "col"):
+        monkeypatch.setenv("TNA_QR_PANEL", mode)
+        S, U, Vt, spec, sw, st = c.svd_truncate_batched(Ad, k)
+        assert st == 0, (mode, st)
+        outs[mode] = [t.cpu().numpy().copy() for t in (S, U, Vt, spec)] + [np.array(sw).copy()]
+    print(case, "sweeps", outs["coop"][4], "max sigma", outs["coop"][0].max())
+    for a, b in zip(outs["coop"], outs["col"]):
+        assert np.array_equal(a, b)
