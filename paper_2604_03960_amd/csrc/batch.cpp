@@ -154,7 +154,7 @@ tna_status tuned_gemm(int kind, GemmGroup g, std::vector<GemmProb> probs, Arena 
     float best = 1e30f;
     for (int cand : {64, 128}) {
       std::vector<GemmProb> pr = probs;
-      const int total = gemm_group_tiles(pr, cand);
+      const int total = gemm_group_tiles(pr, cand, &g.pairs);
       const GemmProb *d = nullptr;
       TNA_TRY(arena_push(ar, pr.data(), pr.size(), s, &d));
       g.tile = cand;
@@ -180,7 +180,7 @@ tna_status tuned_gemm(int kind, GemmGroup g, std::vector<GemmProb> probs, Arena 
   }
   if (tile_out) *tile_out = tile;
   g.tile = tile;
-  const int total = gemm_group_tiles(probs, tile);
+  const int total = gemm_group_tiles(probs, tile, &g.pairs);
   const GemmProb *d = nullptr;
   TNA_TRY(arena_push(ar, probs.data(), probs.size(), s, &d));
   return gemm_grouped(g, d, (int)probs.size(), total, s);
@@ -561,8 +561,8 @@ tna_status engine_step(tna_engine en, const std::vector<tna_dmrg> &ch, const std
     g4.flops = group_flops(b4);
     g1.bytes = group_bytes(b1, f32 ? 4 : 8);
     g4.bytes = group_bytes(b4, f32 ? 4 : 8);
-    tot1 = gemm_group_tiles(p1, tile1);
-    tot4 = gemm_group_tiles(p4, tile4);
+    tot1 = gemm_group_tiles(p1, tile1, &g1.pairs);
+    tot4 = gemm_group_tiles(p4, tile4, &g4.pairs);
     TNA_TRY(arena_push(en->ar, p1.data(), n1, s, &dp1));
     TNA_TRY(arena_push(en->ar, p4.data(), n4, s, &dp4));
     // capture one Lanczos iteration (H_eff + CGS2 + record + normalise + advance); with

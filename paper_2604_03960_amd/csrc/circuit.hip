@@ -158,7 +158,7 @@ tna_status run_group(tna_circuit c, const std::vector<int> &bs, const double *G,
                             nullptr, nullptr, 0, 0, 0, 0});
     }
     GemmGroup g{0, 0, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
-    const int total = gemm_group_tiles(pr, 64);
+    const int total = gemm_group_tiles(pr, 64, &g.pairs);
     const GemmProb *dp = nullptr;
     TNA_TRY(upload(c, c->desc, so, pr, &dp, s));
     TNA_TRY(gemm_grouped(g, dp, ng, total, s));
@@ -251,7 +251,7 @@ tna_status run_group(tna_circuit c, const std::vector<int> &bs, const double *G,
                             nullptr, nullptr, nullptr, 0, 0, 0, 0});
     }
     GemmGroup g{0, 1, G_F64, G_F64, G_F64, G_F64, 64, 1.0, 0.0, 0.0, 0.0};
-    const int total = gemm_group_tiles(pr, 64);
+    const int total = gemm_group_tiles(pr, 64, &g.pairs);
     const GemmProb *dp = nullptr;
     TNA_TRY(upload(c, c->desc, so, pr, &dp, s));
     TNA_TRY(gemm_grouped(g, dp, ng, total, s));

@@ -12,13 +12,16 @@
 // Operand layout of the 16x16x4 MFMAs (lane l, result register r = 0..3):
 //   A[i][k]: lane i + 16k      B[k][j]: lane j + 16k
 //   D[i][j]: lane j + 16(i%4), reg i/4 for f64;  lane j + 16(i/4), reg i%4 for f32.
+#include <cstdint>
 #include <cstdio>
+#include <type_traits>
 
 #include "internal.h"
 
 namespace tna {
 namespace {
 
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -65,7 +68,7 @@ template <> struct TileShape<128> { static constexpr int NT = 512, WR = 4, MINW 
 template <typename X> using gp = X __attribute__((address_space(1))) *;
 
 // One BM x BN tile of C = alpha op(A) op(B) + beta C at (m0, n0).
-template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB, bool PAIRS>
 __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, gp<const TB> __restrict__ B, int ldb,
                                           gp<TC> __restrict__ C, int ldc, int M, int N, int K, double alpha,
                                           double beta, int m0, int n0, TileLds<T, BM, BN> &L) {
@@ -74,7 +77,8 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int LA = BM * BK / NT;  // A elements per thread per slab
   constexpr int LB = BN * BK / NT;
-  static_assert(BM % WR == 0 && BN % WC == 0 && WM % 16 == 0 && WN % 16 == 0 && LA >= 1 && LB >= 1, "tile shape");
+  static_assert(BM % WR == 0 && BN % WC == 0 && WM % 16 == 0 && WN % 16 == 0 && LA >= 2 && LB >= 2 &&
+                    LA % 2 == 0 && LB % 2 == 0, "tile shape");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
@@ -91,7 +95,66 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
   };
 
   T ra[LA], rb[LB];
+  // PAIRS (FP64 operands with even sizes and leading dimensions and 16-byte aligned bases, checked on
+  // the host for the whole launch): two consecutive elements per 16-byte load, half the load
+  // instructions of the element-wise form that serves every other case.
+  constexpr bool pairs = PAIRS && std::is_same<T, double>::value && std::is_same<TA, double>::value &&
+                         std::is_same<TB, double>::value;
+  // pair p of a thread: A rows/columns (i, k) and B (k, j) of its first element; the second element
+  // follows along the contiguous index (k for A, i for A^T; j for B, k for B^T)
+  auto a_pair = [&](int p, int &i, int &k) {
+    if (!TRA) { k = (tid % (BK / 2)) * 2; i = tid / (BK / 2) + (NT / (BK / 2)) * p; }
+    else { i = (tid % (BM / 2)) * 2; k = tid / (BM / 2) + (NT / (BM / 2)) * p; }
+  };
+  auto b_pair = [&](int p, int &k, int &j) {
+    if (!TRB) { j = (tid % (BN / 2)) * 2; k = tid / (BN / 2) + (NT / (BN / 2)) * p; }
+    else { k = (tid % (BK / 2)) * 2; j = tid / (BK / 2) + (NT / (BK / 2)) * p; }
+  };
+  auto load_pairs = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < LA / 2; ++p) {
+      int i, k;
+      a_pair(p, i, k);
+      const int gi = m0 + i, gk = k0 + k;
+      v2d v = {0.0, 0.0};
+      if (gi < M && gk < K)
+        v = *(gp<const v2d>)((gp<const double>)A + (TRA ? (int64_t)gk * lda + gi : (int64_t)gi * lda + gk));
+      ra[2 * p] = v.x;
+      ra[2 * p + 1] = v.y;
+    }
+#pragma unroll
+    for (int p = 0; p < LB / 2; ++p) {
+      int k, j;
+      b_pair(p, k, j);
+      const int gk = k0 + k, gj = n0 + j;
+      v2d v = {0.0, 0.0};
+      if (gj < N && gk < K)
+        v = *(gp<const v2d>)((gp<const double>)B + (TRB ? (int64_t)gj * ldb + gk : (int64_t)gk * ldb + gj));
+      rb[2 * p] = v.x;
+      rb[2 * p + 1] = v.y;
+    }
+  };
+  auto store_pairs = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < LA / 2; ++p) {
+      int i, k;
+      a_pair(p, i, k);
+      L.As[buf][k][i] = ra[2 * p];
+      L.As[buf][k + (TRA ? 0 : 1)][i + (TRA ? 1 : 0)] = ra[2 * p + 1];
+    }
+#pragma unroll
+    for (int p = 0; p < LB / 2; ++p) {
+      int k, j;
+      b_pair(p, k, j);
+      L.Bs[buf][k][j] = rb[2 * p];
+      L.Bs[buf][k + (TRB ? 1 : 0)][j + (TRB ? 0 : 1)] = rb[2 * p + 1];
+    }
+  };
   auto load = [&](int k0) {
+    if constexpr (pairs) {
+      load_pairs(k0);
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
       int i, k;
@@ -112,6 +175,10 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
     }
   };
   auto store = [&](int buf) {
+    if constexpr (pairs) {
+      store_pairs(buf);
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
       int i, k;
@@ -139,6 +206,8 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * BK);
+    // the compiler's MFMA / LDS-read interleaving strategy 0 for this block
+    __builtin_amdgcn_iglp_opt(0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[TM], bv[TN];
@@ -172,11 +241,11 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
       }
 }
 
-template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB, bool PAIRS>
 __global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_kernel(GemmDev g) {
   __shared__ TileLds<T, BM, BN> L;
   const int z = blockIdx.z;
-  gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>((gp<const TA>)(static_cast<const TA *>(g.A) + g.sA * z), g.lda,
+  gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB, PAIRS>((gp<const TA>)(static_cast<const TA *>(g.A) + g.sA * z), g.lda,
                                              (gp<const TB>)(static_cast<const TB *>(g.B) + g.sB * z), g.ldb,
                                              (gp<TC>)(static_cast<TC *>(g.C) + g.sC * z), g.ldc, g.M, g.N, g.K,
                                              g.alpha, g.beta, blockIdx.y * BM, blockIdx.x * BN, L);
@@ -187,7 +256,7 @@ __global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_k
 // tiles_m * tiles_n)); operand pointers may carry a device-side element offset
 // (*jB) * jB_stride / (*jC) * jC_stride, read at run time, so a captured
 // launch serves every Lanczos iteration.
-template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB>
+template <typename T, typename TA, typename TB, typename TC, int BM, int BN, bool TRA, bool TRB, bool PAIRS>
 __global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_grouped_kernel(
     const GemmProb *probs, int nprob, int total, double alpha, double beta) {
   __shared__ TileLds<T, BM, BN> L;
@@ -204,12 +273,18 @@ __global__ __launch_bounds__(TileShape<BM>::NT, TileShape<BM>::MINW) void gemm_g
     const int tm = local / p.tiles_n, tn = local - tm * p.tiles_n;
     const TB *B = static_cast<const TB *>(p.B) + (p.jB ? (int64_t)(*p.jB) * p.jB_stride : 0);
     TC *C = static_cast<TC *>(p.C) + (p.jC ? (int64_t)(*p.jC) * p.jC_stride : 0);
-    gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB>((gp<const TA>)static_cast<const TA *>(p.A), p.lda, (gp<const TB>)B,
+    gemm_tile<T, TA, TB, TC, BM, BN, TRA, TRB, PAIRS>((gp<const TA>)static_cast<const TA *>(p.A), p.lda, (gp<const TB>)B,
                                                p.ldb, (gp<TC>)C, p.ldc, p.M, p.N,
                                                p.K, alpha, beta, tm * BM, tn * BN, L);
     __syncthreads();
   }
 }
+
+template <typename T, typename TA, typename TB>
+constexpr bool all_f64() {
+  return std::is_same<T, double>::value && std::is_same<TA, double>::value && std::is_same<TB, double>::value;
+}
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 template <typename T, typename TA, typename TB, typename TC, int BM, int BN>
 tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
@@ -225,15 +300,26 @@ tna_status launch_tile(const GemmArgs &a, const GemmDev &d, hipStream_t s) {
                   a.transA ? 'T' : 'N', a.transB ? 'T' : 'N');
     timer_begin(name, s);
   }
-  if (!a.transA && !a.transB)
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, false>), grid, dim3(NT), 0, s, d);
-  else if (!a.transA && a.transB)
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, true>), grid, dim3(NT), 0, s, d);
-  else if (a.transA && !a.transB)
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, true, false>), grid, dim3(NT), 0, s, d);
-  else {
+  if (a.transA && a.transB) {
     set_error("gemm: transA && transB not built");
     return TNA_ERR_UNSUPPORTED;
+  }
+  auto go = [&](auto pairs_c) {
+    constexpr bool P = decltype(pairs_c)::value;
+    if (!a.transA && !a.transB)
+      hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, false, P>), grid, dim3(NT), 0, s, d);
+    else if (!a.transA)
+      hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, false, true, P>), grid, dim3(NT), 0, s, d);
+    else
+      hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TC, BM, BN, true, false, P>), grid, dim3(NT), 0, s, d);
+  };
+  if constexpr (all_f64<T, TA, TB>()) {
+    const bool pairs = ((a.lda | a.ldb | a.M | a.N | a.K) & 1) == 0 && aligned16(a.A) && aligned16(a.B) &&
+                       (a.batch == 1 || ((a.sA | a.sB) & 1) == 0);
+    if (pairs) go(std::true_type{});
+    else go(std::false_type{});
+  } else {
+    go(std::false_type{});
   }
   if (name[0]) {
     const double mnk = (double)a.M * a.N * a.K * a.batch;
@@ -265,18 +351,27 @@ tna_status launch_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int 
                   BN, g.transA ? 'T' : 'N', g.transB ? 'T' : 'N');
     timer_begin(name, s);
   }
-  if (!g.transA && !g.transB)
-    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, false>), dim3(grid), dim3(NT), 0, s, d,
-                       nprob, total, g.alpha, g.beta);
-  else if (!g.transA && g.transB)
-    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, true>), dim3(grid), dim3(NT), 0, s, d,
-                       nprob, total, g.alpha, g.beta);
-  else if (g.transA && !g.transB)
-    hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, true, false>), dim3(grid), dim3(NT), 0, s, d,
-                       nprob, total, g.alpha, g.beta);
-  else {
+  if (g.transA && g.transB) {
     set_error("gemm_grouped: transA && transB not built");
     return TNA_ERR_UNSUPPORTED;
+  }
+  auto go = [&](auto pairs_c) {
+    constexpr bool P = decltype(pairs_c)::value;
+    if (!g.transA && !g.transB)
+      hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, false, P>), dim3(grid), dim3(NT), 0, s,
+                         d, nprob, total, g.alpha, g.beta);
+    else if (!g.transA)
+      hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, false, true, P>), dim3(grid), dim3(NT), 0, s,
+                         d, nprob, total, g.alpha, g.beta);
+    else
+      hipLaunchKernelGGL((gemm_grouped_kernel<T, TA, TB, TC, BM, BN, true, false, P>), dim3(grid), dim3(NT), 0, s,
+                         d, nprob, total, g.alpha, g.beta);
+  };
+  if constexpr (all_f64<T, TA, TB>()) {
+    if (g.pairs) go(std::true_type{});
+    else go(std::false_type{});
+  } else {
+    go(std::false_type{});
   }
   if (name[0]) timer_end(name, g.flops, g.bytes, s);
   TNA_LAUNCHED("gemm.grouped");
@@ -291,14 +386,18 @@ tna_status grouped_types(const GemmGroup &g, const GemmProb *d, int nprob, int t
 
 }  // namespace
 
-int gemm_group_tiles(std::vector<GemmProb> &probs, int tile) {
+int gemm_group_tiles(std::vector<GemmProb> &probs, int tile, int *pairs) {
   int total = 0;
+  bool all_pairs = true;
   for (auto &p : probs) {
     p.tile0 = total;
     p.tiles_n = (p.N + tile - 1) / tile;
     const int tm = (p.M + tile - 1) / tile;
     total += (p.M > 0 && p.N > 0) ? tm * p.tiles_n : 0;
+    all_pairs = all_pairs && ((p.lda | p.ldb | p.M | p.N | p.K) & 1) == 0 && aligned16(p.A) && aligned16(p.B) &&
+                (!p.jB || (p.jB_stride & 1) == 0);
   }
+  if (pairs) *pairs = all_pairs ? 1 : 0;
   return total;
 }
 

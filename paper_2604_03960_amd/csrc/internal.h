@@ -102,9 +102,12 @@ struct GemmGroup {
   double alpha, beta;
   double flops, bytes;  // algorithmic work of the whole launch (timing only)
   const char *tag = nullptr;  // timer name prefix (default "gemmg")
+  int pairs = 0;              // every problem takes 16-byte operand loads (set by gemm_group_tiles)
 };
-// Assigns tile ranges for a square tile of the given size; returns the total.
-int gemm_group_tiles(std::vector<GemmProb> &probs, int tile);
+// Assigns tile ranges for a square tile of the given size; returns the total.  With pairs given,
+// *pairs = 1 when every problem's operands can move two elements per 16-byte load (even sizes and
+// leading dimensions, 16-byte aligned bases, even device-offset strides), else 0.
+int gemm_group_tiles(std::vector<GemmProb> &probs, int tile, int *pairs = nullptr);
 tna_status gemm_grouped(const GemmGroup &g, const GemmProb *d, int nprob, int total, hipStream_t s);
 
 // ------------------------------------------------------------------ MPO mixing
