@@ -206,7 +206,9 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * BK);
-    // the compiler's MFMA / LDS-read interleaving strategy 0 for this block
+    // this wave's MFMA block at raised issue priority (the next slab's loads are out; the LDS store
+    // and the barrier follow it), with the compiler's MFMA / LDS-read interleaving strategy 0
+    __builtin_amdgcn_s_setprio(1);
     __builtin_amdgcn_iglp_opt(0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
@@ -220,6 +222,7 @@ __device__ __forceinline__ void gemm_tile(gp<const TA> __restrict__ A, int lda, 
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
     }
+    __builtin_amdgcn_s_setprio(0);
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
   }
