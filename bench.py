@@ -121,9 +121,11 @@ def progress(msg):
         print(msg, file=sys.stderr, flush=True)
 
 
-def roofline_from(stats, dominant):
+def roofline_from(stats, dominant, with_traffic=True):
     """Roofline of the kernel (or kernel family: every timer name that starts with `dominant`) from HIP
-    events: algorithmic flops or bytes per launch over the mean launch time."""
+    events: algorithmic flops or bytes per launch over the mean launch time.  The measured HBM traffic
+    per launch (profiles/hbm_traffic.json) belongs to the headline's launch shape: runs whose launches
+    of the same kernel have other shapes pass with_traffic=False and report it as null."""
     fam = [r for r in stats if r["name"].startswith(dominant) and r["count"] > 0]
     if len(fam) > 1:
         agg = {"name": dominant, "count": sum(r["count"] for r in fam), "ms": sum(r["ms"] for r in fam),
@@ -142,7 +144,8 @@ def roofline_from(stats, dominant):
                 roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                         "frac": ach / PEAK["hbm_gbs"]}
             roof.update({"kernel": dominant, "launches": r["count"], "avg_us": 1e3 * avg_ms,
-                         "flops_per_launch": fl, "bytes_per_launch": by, "traffic": traffic_for(dominant)})
+                         "flops_per_launch": fl, "bytes_per_launch": by,
+                         "traffic": traffic_for(dominant) if with_traffic else None})
             return roof
     return None
 
@@ -255,7 +258,7 @@ def run_fixed_chi(a):
                       "matvecs_per_visit": a.matvecs, "heff_prec": a.prec},
            "E_per_site": E / N, "k_max": int(chis.max()), "k_mean": float(chis.mean()),
            "heff_gemm_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
-           "roofline": roofline_from(stats, dom) if dom else None,
+           "roofline": roofline_from(stats, dom, with_traffic=False) if dom else None,
            "phase_ms": {"lanczos": sum(r["ms_lanczos"] for r in recs), "svd": sum(r["ms_svd"] for r in recs)}}
     print(json.dumps(out))
 
@@ -756,7 +759,7 @@ def run_pid100(a):
     ms_step = 1e3 * (t1 - t0) / a.steps
     chi_fin, _ = dm.state()
 
-    roof = roofline_from(stats, dominant) if dominant else None
+    roof = roofline_from(stats, dominant, with_traffic=False) if dominant else None
 
     # isolated SVD at chi = 2048 (4096 x 4096, FP64)
     svd = None

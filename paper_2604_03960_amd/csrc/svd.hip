@@ -1069,103 +1069,19 @@ __global__ __launch_bounds__(256) void permute_load_kernel(const SvdMat *mats) {
   }
 }
 
-// grid (matrices), 1024 threads: Householder QR of the panel of columns k0 .. k0+31 of B
-// (rows k0..), one column after the other: x = B[k:R, k], alpha = -sign(x_0) |x|,
-// v = x - alpha e_0 (kept in LDS, stored as row k of qv), beta = 2 / v^T v =
-// 1 / (|x| (|x| + |x_0|)) (stored in qws); B[k:, k] <- (alpha, 0, ...); then every later
-// column c of the panel: B[k:, c] -= beta (v^T B[k:, c]) v, rows walked eight at a time
-// with the loads issued before their use.  The trailing columns are updated afterwards
-// with the block reflector (qr_block_apply).
-constexpr int QP_NT = 1024, QP_RG = QP_NT / 32, QP_UN = 8;
-__global__ __launch_bounds__(QP_NT) void qr_panel_kernel(const SvdMat *mats, int k0) {
-  __shared__ double vsh[4096];
-  __shared__ double red[QP_NT / 64];
-  __shared__ double part[QP_RG][33];
-  __shared__ double s_x0, s_nrm;
-  const SvdMat &a = mats[blockIdx.x];
-  if (!a.active || !a.precond || k0 >= a.Ra) return;
-  const int R = a.R, C = a.C, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) a.fro2[1] = 0.0;  // the trailing-row maximum of this panel (qr_tail_kernel)
-  const int kend = k0 + 32 < R ? k0 + 32 : R;
-  const int cend = k0 + 32 < C ? k0 + 32 : C;
-  double *B = a.bw;
-  for (int k = k0; k < kend; ++k) {
-    double ss = 0.0;
-    for (int i = k + tid; i < R; i += QP_NT) {
-      const double x = B[(int64_t)i * C + k];
-      vsh[i] = x;
-      ss += x * x;
-    }
-    ss = wave_sum_d(ss);
-    if (lane == 0) red[wave] = ss;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < QP_NT / 64; ++w) t += red[w];
-      s_nrm = sqrt(t);
-      s_x0 = vsh[k];
-    }
-    __syncthreads();
-    const double x0 = s_x0, nx = s_nrm;
-    const double alpha = x0 >= 0.0 ? -nx : nx;
-    const double beta = nx > 0.0 ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
-    if (tid == 0) {
-      vsh[k] = x0 - alpha;
-      a.qws[2048 + 64 * (int64_t)C + k] = beta;
-    }
-    __syncthreads();
-    double *vrow = a.qv + (int64_t)k * R;
-    for (int i = tid; i < R; i += QP_NT) {
-      vrow[i] = i < k ? 0.0 : vsh[i];
-      if (i >= k) B[(int64_t)i * C + k] = (i == k) ? (nx > 0.0 ? alpha : x0) : 0.0;
-    }
-    const int cl = tid & 31, rg = tid >> 5, c = k + 1 + cl;
-    const bool colok = c < cend && beta != 0.0;
-    double w = 0.0;
-    if (colok) {
-      int i = k + rg;
-      for (; i + (QP_UN - 1) * QP_RG < R; i += QP_UN * QP_RG) {
-        double x[QP_UN];
-#pragma unroll
-        for (int u = 0; u < QP_UN; ++u) x[u] = B[(int64_t)(i + u * QP_RG) * C + c];
-#pragma unroll
-        for (int u = 0; u < QP_UN; ++u) w += vsh[i + u * QP_RG] * x[u];
-      }
-      for (; i < R; i += QP_RG) w += vsh[i] * B[(int64_t)i * C + c];
-    }
-    part[rg][cl] = w;
-    __syncthreads();
-    if (colok) {
-      double wt = 0.0;
-#pragma unroll
-      for (int g = 0; g < QP_RG; ++g) wt += part[g][cl];
-      const double f = beta * wt;
-      int i = k + rg;
-      for (; i + (QP_UN - 1) * QP_RG < R; i += QP_UN * QP_RG) {
-        double x[QP_UN];
-#pragma unroll
-        for (int u = 0; u < QP_UN; ++u) x[u] = B[(int64_t)(i + u * QP_RG) * C + c];
-#pragma unroll
-        for (int u = 0; u < QP_UN; ++u) B[(int64_t)(i + u * QP_RG) * C + c] = x[u] - f * vsh[i + u * QP_RG];
-      }
-      for (; i < R; i += QP_RG) {
-        const int64_t r = (int64_t)i * C + c;
-        B[r] = B[r] - f * vsh[i];
-      }
-    }
-    __syncthreads();  // panel column k+1 and vsh are rewritten next
-  }
-}
-
-// The panel factorisation spread over row chunks of QC_ROWS rows, one launch per column:
-// launch k applies reflector k to the panel columns right of it and forms the chunk partials
-// that reflector k+1 needs (|B[k+1:, k+1]|^2 and the dots B[k+2:, k+1] . B[k+2:, c]); the last
-// chunk to arrive (arrival counter, device-scope fences, no waiting) sums the partials in chunk
-// order and writes alpha, beta, v_{k+1,k+1} = x0 - alpha and w_c = beta (v . B[:, c]) for the
-// next launch.  The start launch (k = k0 - 1) forms the partials of column k0 only.  The same
-// reflectors as qr_panel_kernel: x = B[k:R, k], alpha = -sign(x_0) |x|, v = x - alpha e_0,
-// beta = 1 / (|x| (|x| + |x_0|)).  Scratch: chunk partials (33 per chunk) at qws[2048 ..), the
-// scalars at qws[2048 + 64 C + R ..).  grid (chunks, 1, matrices), 256 threads.
+// Householder QR of the panel of columns k0 .. k0+31 of B (rows k0..), one column after the
+// other: x = B[k:R, k], alpha = -sign(x_0) |x|, v = x - alpha e_0 (stored as row k of qv),
+// beta = 2 / v^T v = 1 / (|x| (|x| + |x_0|)) (stored in qws); B[k:, k] <- (alpha, 0, ...); then
+// every later column c of the panel: B[k:, c] -= beta (v^T B[k:, c]) v.  The trailing columns are
+// updated afterwards with the block reflector (qr_block_apply).
+//
+// Spread over row chunks of QC_ROWS rows, one launch per column: launch k applies reflector k to
+// the panel columns right of it and forms the chunk partials that reflector k+1 needs
+// (|B[k+1:, k+1]|^2 and the dots B[k+2:, k+1] . B[k+2:, c]); the last chunk to arrive (arrival
+// counter, device-scope fences, no waiting) sums the partials in chunk order and writes alpha, beta,
+// v_{k+1,k+1} = x0 - alpha and w_c = beta (v . B[:, c]) for the next launch.  The start launch
+// (k = k0 - 1) forms the partials of column k0 only.  Scratch: chunk partials (33 per chunk) at
+// qws[2048 ..), the scalars at qws[2048 + 64 C + R ..).  grid (chunks, 1, matrices), 256 threads.
 constexpr int QC_ROWS = 64;
 __global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0, int k) {
   __shared__ double red[8][33];
