@@ -1196,7 +1196,9 @@ __global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0,
 // launched with hipLaunchCooperativeKernel (all workgroups resident); every workgroup of the
 // grid passes the same 33 barriers whatever its matrix.  Scratch: 2 x 65 partials per chunk at
 // qws[2048 ..).  grid (chunks, 1, matrices), 256 threads.
+constexpr int QC_GROUP = 64;
 __global__ __launch_bounds__(256) void qr_panel_coop_kernel(const SvdMat *mats, int k0) {
+  __shared__ double pl[QC_GROUP * 64];
   __shared__ double red[8][33];
   __shared__ double rowv[32];
   __shared__ double scs[4 + 32];
@@ -1282,9 +1284,18 @@ __global__ __launch_bounds__(256) void qr_panel_coop_kernel(const SvdMat *mats, 
     }
     grid.sync();  // device-scope release and acquire: the partials written above are visible after it
     if (more) {
+      // the chunks' partials come in through LDS, QC_GROUP chunks at a time with every thread
+      // loading (the far-memory latency paid once per group), and are summed in chunk order
+      double t = 0.0;
+      for (int b0 = 0; b0 < G; b0 += QC_GROUP) {
+        const int nb = G - b0 < QC_GROUP ? G - b0 : QC_GROUP;
+        for (int e = tid; e < nb * 64; e += 256) pl[e] = pp[(int64_t)(b0 + (e >> 6)) * 65 + 1 + (e & 63)];
+        __syncthreads();
+        if (tid < 64)
+          for (int b = 0; b < nb; ++b) t += pl[b * 64 + tid];
+        __syncthreads();
+      }
       if (tid < 64) {
-        double t = 0.0;
-        for (int b = 0; b < G; ++b) t += pp[(int64_t)b * 65 + 1 + tid];
         if (tid < 32) red[0][tid] = t;
         else rowv[tid - 32] = t;
       }
