@@ -1082,7 +1082,7 @@ __global__ __launch_bounds__(256) void permute_load_kernel(const SvdMat *mats) {
 // v_{k+1,k+1} = x0 - alpha and w_c = beta (v . B[:, c]) for the next launch.  The start launch
 // (k = k0 - 1) forms the partials of column k0 only.  Scratch: chunk partials (33 per chunk) at
 // qws[2048 ..), the scalars at qws[2048 + 64 C + R ..).  grid (chunks, 1, matrices), 256 threads.
-constexpr int QC_ROWS = 64;
+constexpr int QC_ROWS = 128;
 __global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0, int k) {
   __shared__ double red[8][33];
   __shared__ int last;
