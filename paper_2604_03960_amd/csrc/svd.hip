@@ -1186,7 +1186,7 @@ __global__ __launch_bounds__(256) void qr_col_kernel(const SvdMat *mats, int k0,
 }
 
 // The same panel factorisation as qr_col_kernel in one cooperative launch per panel: each
-// workgroup keeps its 64-row chunk of the panel in registers for all 32 columns, and one grid
+// workgroup keeps its QC_ROWS-row chunk of the panel in registers for all 32 columns, and one grid
 // barrier per column replaces a launch.  Per column every workgroup writes its chunk partials
 // (|B[k+1:, k+1]|^2, the dots B[k+2:, k+1] . B[k+2:, c], and, for the chunk holding row k+1,
 // that row's entries) into one of two alternating buffers, passes the barrier, and sums all
