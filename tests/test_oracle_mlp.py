@@ -120,3 +120,17 @@ def test_adam_second_step_with_opposing_gradient_stands_still():
     oracle.adam_step(p, -b1 * g1, m, v, 2, lr=0.05, b1=b1)
     assert np.allclose(p, after1, rtol=0, atol=1e-15)
     assert np.allclose(after1, [1.0, 2.0, 3.0] - 0.05 * g1 / (np.abs(g1) + 1e-8), rtol=1e-13)
+
+
+def test_adam_two_steps_hand_computed():
+    # one parameter from 0 with gradients 1 then 3 (lr 0.1, b1 0.9, b2 0.999, eps 1e-8), by hand:
+    # t = 1: m = 0.1, v = 0.001, corrected 1 and 1, p = -0.1 / (1 + 1e-8);
+    # t = 2: m = 0.09 + 0.3 = 0.39, v = 0.000999 + 0.009 = 0.009999, corrected by 1 - 0.9^2 = 0.19 and
+    #        1 - 0.999^2 = 0.001999: 39/19 and 9999/1999, p -= 0.1 (39/19) / (sqrt(9999/1999) + 1e-8)
+    p = np.zeros(1)
+    m, v = np.zeros(1), np.zeros(1)
+    oracle.adam_step(p, np.array([1.0]), m, v, 1, lr=0.1)
+    assert abs(p[0] - (-0.1 / (1 + 1e-8))) <= 1e-16
+    oracle.adam_step(p, np.array([3.0]), m, v, 2, lr=0.1)
+    assert abs(m[0] - 0.39) <= 1e-15 and abs(v[0] - 0.009999) <= 1e-16  # (1 - b2) is not exact in binary
+    assert abs(p[0] - (-0.1917781104876684)) <= 1e-14
