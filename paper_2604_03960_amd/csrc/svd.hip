@@ -532,7 +532,7 @@ __device__ inline int eig_tour(EigTour &L, int inner_max, double floor2) {
         const bool first = (lane & 1) == 0;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-          const double pv = __shfl_xor(q[r], 1, 64);
+          const double pv = dpp_d<0xB1, 0xf>(q[r]);  // the pair partner's value (quad_perm [1,0,3,2])
           const double nv = first ? c * q[r] - sn * pv : sn * pv + c * q[r];
           q[r] = __shfl(nv, qsrc, 64);
         }
